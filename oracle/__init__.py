@@ -1,0 +1,270 @@
+"""CPU oracle for the (safe) multi-shift triangular solve — TEST INFRASTRUCTURE.
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may use
+this package. The GPU library never imports it, and this package never imports
+the GPU library: the two share no code. The only shared module is
+``workloads`` (seeded input generators, no solver arithmetic).
+
+What each function follows (T. Moon, J. Poulson, arXiv 1607.01477):
+
+* :func:`solve` — back substitution, Alg 1 (Sec. 2) on ``U - lambda_j I``
+  for each shift, the per-column content of Alg 3.
+* :func:`solve_safe` — Alg 4 (Sec. 3) per column (``nb=0``), or Alg 5 (Sec. 3)
+  with decision block size ``nb``; scale factors ``s_j = 2^-k_j``.
+* :func:`solve_adjoint` — forward substitution with ``(U - lambda_j I)^H``, the
+  lower-triangular variant noted in the footnote to Sec. 2.
+* :func:`gradient` — gradients of a real loss through the solve (not in the
+  paper): ``gB = Y``, ``gU = -triu(Y X^H)``, ``glambda_j = x_j^H y_j``.
+* :func:`triang_eig` — TriangEig, Alg 6 (Sec. 4).
+* :func:`lanczos_sigma_min` — second stage of the Van Loan/Lui method, Alg 7
+  (Sec. 5): Lanczos on ``(U - zI)^{-H}(U - zI)^{-1}``.
+
+The C part is built with gcc (``-O2 -fno-fast-math -ffp-contract=off
+-fopenmp``) by :func:`build`.
+
+Parity: pinned by ``tests/test_oracle_*.py`` (closed forms, library solvers,
+brute force, hand-traced scaling examples, invariants). The Lanczos estimate
+is pinned only through the diagonal closed form, the Ritz inequality and
+dense SVDs; its agreement with any other Lanczos run is "parity unpinned"
+beyond those.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import sys
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mstrsm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_mstrsm.so")
+_lock = threading.Lock()
+_lib = None
+
+OMEGA_LOG2 = 960
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle into oracle/liboracle_mstrsm.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-std=c11", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_LIB)
+            P = ctypes.c_void_p
+            I = ctypes.c_int
+            lib.oracle_mstrsm.argtypes = [I, I, P, I, P, P, I]
+            lib.oracle_mstrsm_adjoint.argtypes = [I, I, P, I, P, P, I]
+            lib.oracle_mstrsm_safe.argtypes = [I, I, P, I, P, P, I, P, P, P, I, I, I, P]
+            for f in (lib.oracle_mstrsm, lib.oracle_mstrsm_adjoint, lib.oracle_mstrsm_safe):
+                f.restype = I
+            lib.oracle_num_threads.restype = I
+            lib.oracle_set_num_threads.argtypes = [I]
+            _lib = lib
+    return _lib
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
+
+
+def set_num_threads(t: int) -> None:
+    _load().oracle_set_num_threads(int(t))
+
+
+def _cm(a) -> np.ndarray:
+    return np.asfortranarray(np.asarray(a, dtype=np.complex128))
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None and a.size else None
+
+
+def solve(U, lam, B) -> np.ndarray:
+    """X with (U - lam[j] I) X[:, j] = B[:, j] (plain; singular systems give inf/NaN)."""
+    U = _cm(U)
+    lam = np.ascontiguousarray(lam, dtype=np.complex128)
+    X = _cm(B).copy(order="F")
+    m, n = X.shape
+    if U.shape != (m, m) or lam.shape != (n,):
+        raise ValueError("shape mismatch")
+    rc = _load().oracle_mstrsm(m, n, _ptr(U), max(1, m), _ptr(lam), _ptr(X), max(1, m))
+    if rc != 0:
+        raise RuntimeError("oracle_mstrsm failed: %d" % rc)
+    return X
+
+
+def solve_adjoint(U, lam, G) -> np.ndarray:
+    """Y with (U - lam[j] I)^H Y[:, j] = G[:, j]."""
+    U = _cm(U)
+    lam = np.ascontiguousarray(lam, dtype=np.complex128)
+    Y = _cm(G).copy(order="F")
+    m, n = Y.shape
+    if U.shape != (m, m) or lam.shape != (n,):
+        raise ValueError("shape mismatch")
+    rc = _load().oracle_mstrsm_adjoint(m, n, _ptr(U), max(1, m), _ptr(lam), _ptr(Y), max(1, m))
+    if rc != 0:
+        raise RuntimeError("oracle_mstrsm_adjoint failed: %d" % rc)
+    return Y
+
+
+def solve_safe(U, lam, B, col_len=None, nb: int = 64, omega_log2: int = OMEGA_LOG2,
+               force_phase2: bool = False, trace: bool = False):
+    """Safe solve: returns (X, scale, k) with (U - lam_j I) X_j = 2^-k_j B_j.
+
+    nb = 0 applies Alg 4 to each column unblocked; nb > 0 is Alg 5 with that
+    decision block size. col_len[j] limits column j to rows [0, col_len[j]).
+    With trace=True also returns an array (nblocks, n, 2) of (G(j) after the
+    block's bound update, max cabs1 of the rows above after its substitution).
+    """
+    U = _cm(U)
+    lam = np.ascontiguousarray(lam, dtype=np.complex128)
+    X = _cm(B).copy(order="F")
+    m, n = X.shape
+    if U.shape != (m, m) or lam.shape != (n,):
+        raise ValueError("shape mismatch")
+    cl = None
+    if col_len is not None:
+        cl = np.ascontiguousarray(col_len, dtype=np.int32)
+        if cl.shape != (n,):
+            raise ValueError("col_len shape")
+    scale = np.zeros(n, dtype=np.float64)
+    k = np.zeros(n, dtype=np.int32)
+    nbe = m if (nb <= 0 or nb >= m) else nb
+    nblk = (m + nbe - 1) // nbe if m > 0 else 0
+    tr = np.zeros((max(nblk, 1), n, 2), dtype=np.float64) if trace else None
+    rc = _load().oracle_mstrsm_safe(m, n, _ptr(U), max(1, m), _ptr(lam), _ptr(X), max(1, m),
+                                    _ptr(cl) if cl is not None else None,
+                                    _ptr(scale), _ptr(k), int(nb), int(omega_log2),
+                                    int(bool(force_phase2)), _ptr(tr) if tr is not None else None)
+    if rc != 0:
+        raise RuntimeError("oracle_mstrsm_safe failed: %d" % rc)
+    if trace:
+        return X, scale, k, tr[:nblk]
+    return X, scale, k
+
+
+def gradient(U, lam, X, Y):
+    """Gradients of a real loss L through X = solve(U, lam, B), given
+    Y = solve_adjoint(U, lam, dL/dX) (PyTorch convention: the gradient of a
+    complex input z is dL/dRe z + i dL/dIm z).
+
+    gB = Y; gU = -triu(Y X^H); glam_j = sum_i conj(X_ij) Y_ij.
+    """
+    Y = np.asarray(Y)
+    X = np.asarray(X)
+    gU = -np.triu(Y @ X.conj().T)
+    glam = np.sum(X.conj() * Y, axis=0)
+    return gU, glam, Y.copy()
+
+
+def triang_eig(T, nb: int = 64, omega_log2: int = OMEGA_LOG2, force_phase2: bool = False):
+    """TriangEig (Alg 6): lam = diag(T); Z = -T with zero diagonal; safe
+    multi-shift solve with column j limited to rows [0, j); diag(Z) = s.
+    Returns (lam, Z, k) with T Z[:, j] = lam_j Z[:, j] and Z(j, j) = 2^-k_j."""
+    T = _cm(T)
+    m = T.shape[0]
+    lam = np.array(np.diag(T), dtype=np.complex128)
+    Z = np.asfortranarray(np.triu(-T, 1))
+    col_len = np.arange(m, dtype=np.int32)
+    Z, s, k = solve_safe(T, lam, Z, col_len=col_len, nb=nb, omega_log2=omega_log2,
+                         force_phase2=force_phase2)
+    Z[np.arange(m), np.arange(m)] = s
+    return lam, Z, k
+
+
+def relative_residual(U, lam, X, B, k=None, cols=None) -> np.ndarray:
+    """Per column ||(U - lam_j I) x_j - 2^-k_j b_j||_inf / (||U - lam_j I||_inf ||x_j||_inf)
+    with the true modulus; absolute residual where x_j = 0."""
+    U = np.asarray(U)
+    X = np.asarray(X)
+    B = np.asarray(B)
+    lam = np.asarray(lam)
+    if cols is None:
+        cols = np.arange(X.shape[1])
+    cols = np.asarray(cols)
+    Xc = X[:, cols]
+    Bc = B[:, cols]
+    if k is not None:
+        Bc = Bc * np.ldexp(1.0, -np.asarray(k)[cols].astype(np.int64))[None, :]
+    Ut = np.triu(U)
+    R = Ut @ Xc - Xc * lam[cols][None, :] - Bc
+    offrow = np.sum(np.abs(np.triu(U, 1)), axis=1)
+    d = np.diag(U)
+    unorm = np.max(offrow[:, None] + np.abs(d[:, None] - lam[cols][None, :]), axis=0)
+    rn = np.max(np.abs(R), axis=0)
+    xn = np.max(np.abs(Xc), axis=0)
+    den = unorm * xn
+    out = np.where(den > 0, rn / np.where(den > 0, den, 1.0), rn)
+    return out
+
+
+def _theta_max(alpha: np.ndarray, beta: np.ndarray) -> float:
+    from scipy.linalg import eigvalsh_tridiagonal
+    if alpha.size == 1:
+        return float(alpha[0])
+    return float(eigvalsh_tridiagonal(alpha, beta)[-1])
+
+
+def lanczos_sigma_min(U, z, V0, iters: int = 15):
+    """Inverse Lanczos estimate of sigma_min(U - z_j I) for every shift z_j.
+
+    Plain Lanczos (no reorthogonalisation) on A_j = (U - z_j I)^{-H}(U - z_j I)^{-1}
+    with start vector V0[:, j] (normalised here), each product computed as one
+    upper and one adjoint multi-shift solve over all shifts at once:
+      w = A v_k; alpha_k = Re(v_k^H w); w -= alpha_k v_k + beta_{k-1} v_{k-1};
+      beta_k = ||w||_2; v_{k+1} = w / beta_k (stop early only if beta_k = 0).
+    theta_max = largest eigenvalue of the k x k tridiagonal; sigma = theta^-1/2.
+    Returns (sigma, alpha, beta, steps)."""
+    U = _cm(U)
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    V = _cm(V0).copy(order="F")
+    m, N = V.shape
+    V = V / np.linalg.norm(V, axis=0, keepdims=True)
+    Vprev = np.zeros_like(V)
+    alpha = np.zeros((iters, N))
+    beta = np.zeros((iters, N))
+    steps = np.full(N, iters, dtype=np.int64)
+    bprev = np.zeros(N)
+    active = np.ones(N, dtype=bool)
+    for it in range(iters):
+        Y = solve(U, z, V)
+        W = solve_adjoint(U, z, Y)
+        a = np.real(np.sum(V.conj() * W, axis=0))
+        W = W - a[None, :] * V - bprev[None, :] * Vprev
+        b = np.linalg.norm(W, axis=0)
+        alpha[it] = np.where(active, a, 0.0)
+        beta[it] = np.where(active, b, 0.0)
+        stop = active & (b == 0.0)
+        steps[stop] = it + 1
+        active = active & ~stop
+        Vprev = V
+        V = W / np.where(b > 0, b, 1.0)[None, :]
+        bprev = b
+    sigma = np.empty(N)
+    for j in range(N):
+        s = int(steps[j])
+        th = _theta_max(alpha[:s, j], beta[:s - 1, j])
+        sigma[j] = 1.0 / np.sqrt(th)
+    return sigma, alpha, beta, steps
+
+
+__all__ = ["build", "solve", "solve_safe", "solve_adjoint", "gradient", "triang_eig",
+           "relative_residual", "lanczos_sigma_min", "num_threads", "set_num_threads",
+           "OMEGA_LOG2"]
+
+if __name__ == "__main__":  # pragma: no cover
+    print(build(force="--force" in sys.argv))
