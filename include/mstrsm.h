@@ -1,0 +1,193 @@
+/*
+ * mstrsm.h — blocked multi-shift triangular solves on AMD Instinct MI355X (gfx950).
+ *
+ * Implements the method of T. Moon and J. Poulson, "Accelerating eigenvector
+ * and pseudospectra computation using blocked multi-shift triangular solves"
+ * (arXiv 1607.01477): one upper-triangular U, many shifts lambda_j, solved
+ * together so that the bulk of the work is a matrix-matrix product.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All matrix and vector pointers are DEVICE pointers (hipMalloc'd or
+ *    equivalent) unless a parameter says otherwise.
+ *  - Complex numbers are complex128, stored interleaved {double re, im}
+ *    (hipDoubleComplex / std::complex<double> / torch.complex128 layout).
+ *  - Matrices are column-major with a leading dimension >= max(1, rows).
+ *  - The strict lower triangle of U is never read.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Every call only
+ *    enqueues work on it and returns; the caller synchronises the stream
+ *    before reading outputs. No pointer is retained after a call returns.
+ *  - Workspace is allocated stream-ordered on `stream` (hipMallocAsync) and
+ *    released the same way before the call returns.
+ *  - Arguments are validated on the host before anything is enqueued. On
+ *    MST_EARG, mst_last_bad_arg() gives the 1-based position of the first
+ *    offending argument. m == 0 or n == 0 returns MST_OK with nothing enqueued.
+ *  - Calls from several host threads are allowed; the error state
+ *    (mst_last_bad_arg, mst_last_error) is per thread.
+ */
+#ifndef MSTRSM_H
+#define MSTRSM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MST_OK = 0,
+    MST_EARG = -1,          /* invalid argument, see mst_last_bad_arg() */
+    MST_EHIP = -2,          /* a HIP runtime call failed, see mst_last_error() */
+    MST_ENOMEM = -3,        /* workspace allocation failed */
+    MST_EUNSUPPORTED = -4   /* valid but unsupported combination of options */
+} mst_status;
+
+/* Options. A NULL mst_opts* means all defaults; a zero field means its default. */
+typedef struct {
+    int nb;            /* diagonal-block (and scaling-decision) size: 16, 32 or 64; default 64 */
+    int outer_nb;      /* rows per deferred substitution step, a multiple of nb; default 256.
+                          Equal to nb gives the paper's right-looking order (Alg 3 / Alg 5). */
+    int precision;     /* 0: all FP64.
+                          1: substitution GEMMs in FP32 on MFMA (FP32 accumulation),
+                             diagonal blocks in FP64, then FP64 iterative refinement
+                             on the residual B - (U X - X diag(lambda)). mstrsm only. */
+    int max_sweeps;    /* refinement sweeps for precision 1: 1..3; default 2 */
+    int omega_log2;    /* overflow threshold Omega = 2^omega_log2 for the safe solve;
+                          default 960 (leaves 2^64 of headroom below DBL_MAX). Smaller
+                          values force rescaling at small sizes (testing). Range 8..1000. */
+    int force_phase2;  /* accepted for interface compatibility: the GPU safe solve always
+                          runs the checked back substitution, which gives the same result */
+    int reserved[4];
+} mst_opts;
+
+/*
+ * mstrsm — plain multi-shift solve, problem (2) of Sec. 2 with Alg 3:
+ *     (U - shifts[j] I) X(:,j) = B(:,j),   j = 0..n-1.
+ *   m, n      rows of U / number of shifts (= columns of B)
+ *   U, ldu    m x m upper triangular, read only
+ *   shifts    n complex, read only
+ *   B, ldb    m x n; on entry the right-hand sides, on exit X
+ *   opt       nullable
+ * Like xTRSM it does not detect singular or overflowing systems: a zero or
+ * subnormal pivot gives Inf/NaN in X. With opt->precision = 1 the result has
+ * FP64 accuracy after the refinement sweeps (max_sweeps) but the substitution
+ * GEMMs run in FP32.
+ */
+mst_status mstrsm(int m, int n, const void* U, int ldu, const void* shifts,
+                  void* B, int ldb, const mst_opts* opt, void* stream);
+
+/*
+ * mstrsm_safe — safe multi-shift solve, problem (6) of Sec. 3 with Alg 5:
+ *     (U - shifts[j] I) X(:,j) = s_j B(:,j),  s_j = 2^-k_j in [0, 1],
+ * with power-of-two scale factors chosen so that no intermediate quantity
+ * reaches Omega, and exactly zero pivots replaced by delta = 2^-52 max|U|_1
+ * (|z|_1 = |Re z| + |Im z|; delta = 2^-1022 when U = 0). Finite input gives
+ * finite X. Scaling decisions are taken per diagonal block of nb rows, so
+ * they depend on nb (any nb gives a valid answer).
+ *   col_len   nullable, device, n int32: column j uses rows [0, col_len[j]) only;
+ *             the rows below are neither read nor written and act as zero
+ *             right-hand-side entries (the triangular-eigenvector short-cut,
+ *             Sec. 4). Values are clamped to [0, m].
+ *   scale     device, n doubles: s_j (0 when k_j > 1074)
+ *   scale_log2 nullable, device, n int32: k_j (exact)
+ */
+mst_status mstrsm_safe(int m, int n, const void* U, int ldu, const void* shifts,
+                       void* B, int ldb, const int* col_len, double* scale, int* scale_log2,
+                       const mst_opts* opt, void* stream);
+
+/*
+ * mstrsm_adjoint — conjugate-transposed multi-shift solve (the lower-triangular
+ * forward-substitution variant noted in the footnote to Sec. 2):
+ *     (U - shifts[j] I)^H Y(:,j) = G(:,j).
+ *   G, ldg    m x n; on entry G, on exit Y.
+ * Plain FP64 (no scaling); singular systems give Inf/NaN like mstrsm.
+ */
+mst_status mstrsm_adjoint(int m, int n, const void* U, int ldu, const void* shifts,
+                          void* G, int ldg, const mst_opts* opt, void* stream);
+
+/*
+ * Gradient pieces of a real loss L through X = solve(U, shifts, B), given
+ * Y = adjoint solve of dL/dX (gradient convention dL/dRe z + i dL/dIm z).
+ * The gradient of B is Y itself.
+ *
+ * mst_grad_u:     gU = -triu(Y X^H), m x m; the strict lower triangle is set to 0.
+ *                 Y and X are m x n.
+ * mst_grad_shift: gshift[j] = sum_i conj(X(i,j)) Y(i,j), n complex.
+ */
+mst_status mst_grad_u(int m, int n, const void* Y, int ldy, const void* X, int ldx,
+                      void* gU, int ldgu, void* stream);
+mst_status mst_grad_shift(int m, int n, const void* X, int ldx, const void* Y, int ldy,
+                          void* gshift, void* stream);
+
+/*
+ * mst_residual — R = B0 - (U X - X diag(shifts)), the FP64 residual of the
+ * multi-shift system (used by the mixed-precision refinement).
+ * R may not alias X; it may alias B0 (then ldr must equal ldb0).
+ */
+mst_status mst_residual(int m, int n, const void* U, int ldu, const void* shifts,
+                        const void* X, int ldx, const void* B0, int ldb0,
+                        void* R, int ldr, void* stream);
+
+/*
+ * mst_triang_eig — TriangEig, Alg 6 (Sec. 4): eigenvectors of an upper
+ * triangular T through one safe multi-shift solve with shifts diag(T):
+ *   Z(:,j) = [z; s_j; 0] with (T(0:j,0:j) - T(j,j) I) z = -s_j T(0:j, j),
+ * so that T Z(:,j) = T(j,j) Z(:,j) and Z(j,j) = s_j = 2^-k_j.
+ *   T, ldt        m x m upper triangular, read only
+ *   Z, ldz        m x m output (the strict lower triangle is set to 0)
+ *   eigvals       m complex output (diag(T))
+ *   scale_log2    nullable, m int32 output (k_j)
+ */
+mst_status mst_triang_eig(int m, const void* T, int ldt, void* Z, int ldz, void* eigvals,
+                          int* scale_log2, const mst_opts* opt, void* stream);
+
+/*
+ * mst_lanczos_sigma_min — second stage of the Van Loan/Lui method (Alg 7,
+ * Sec. 5): for every shift z_j, `iters` steps of plain Lanczos (no
+ * reorthogonalisation) on (U - z_j I)^{-H} (U - z_j I)^{-1}, each product
+ * being one mstrsm and one mstrsm_adjoint over all shifts at once;
+ * sigma[j] = theta_max^{-1/2} with theta_max the largest eigenvalue of the
+ * Lanczos tridiagonal (computed on the device by bisection).
+ *   V, ldv     m x N start vectors (normalised here); overwritten (workspace)
+ *   iters      1..64
+ *   sigma      device, N doubles: estimate of sigma_min(U - z_j I)
+ *   alpha,beta nullable, device, iters x N doubles each (column j at offset j*iters)
+ *   steps      nullable, device, N int32: steps taken (< iters only if beta hit 0)
+ */
+mst_status mst_lanczos_sigma_min(int m, int N, const void* U, int ldu, const void* z,
+                                 void* V, int ldv, int iters, double* sigma,
+                                 double* alpha, double* beta, int* steps,
+                                 const mst_opts* opt, void* stream);
+
+/*
+ * Kernel timing (diagnostics). Between mst_profile_start() and
+ * mst_profile_stop(), every kernel launch made by this thread is bracketed by
+ * a pair of HIP events on its stream and attributed to one family. stop()
+ * waits for the recorded events and returns, per family, the summed kernel
+ * time in milliseconds, the nominal real flops those launches performed
+ * (8 per complex multiply-add) and the launch count. Arrays have
+ * MST_PROF_KINDS entries (any may be NULL).
+ */
+enum {
+    MST_PROF_GEMM_F64 = 0,   /* substitution GEMM, FP64 matrix cores */
+    MST_PROF_GEMM_F32 = 1,   /* substitution GEMM, FP32 matrix cores */
+    MST_PROF_DIAG = 2,       /* diagonal-block solves */
+    MST_PROF_RESID = 3,      /* residual and gradient products */
+    MST_PROF_AUX = 4,        /* norms, rescaling, conversions, Lanczos vectors */
+    MST_PROF_KINDS = 5
+};
+mst_status mst_profile_start(void);
+mst_status mst_profile_stop(double* ms, double* flops, long long* launches);
+
+/* Human-readable name of a status code (static storage). */
+const char* mst_status_string(mst_status s);
+/* 1-based position of the first bad argument of this thread's last MST_EARG. */
+int mst_last_bad_arg(void);
+/* Text of this thread's last MST_EHIP / MST_ENOMEM failure (static storage per thread). */
+const char* mst_last_error(void);
+/* Library version, e.g. "0.1.0". */
+const char* mst_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSTRSM_H */

@@ -1,0 +1,283 @@
+"""Blocked multi-shift triangular solves on AMD MI355X (gfx950).
+
+Python binding of ``libmstrsm.so`` (C-ABI declared in ``include/mstrsm.h``).
+Every function here only marshals arguments: tensors must be complex128 (int32
+for ``col_len``) on a ROCm device; matrices are passed column-major (a
+Fortran-ordered view, ``t.stride(0) == 1``), copied into that layout if they
+are not. All work is enqueued on the current torch stream.
+
+Method: T. Moon, J. Poulson, "Accelerating eigenvector and pseudospectra
+computation using blocked multi-shift triangular solves" (arXiv 1607.01477):
+Alg 3 (multi-shift solve), Alg 4/5 (safe solve), Alg 6 (triangular
+eigenvectors), Alg 7 (resolvent norms).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import MstError, MstOpts
+
+__all__ = ["mstrsm", "mstrsm_safe", "mstrsm_adjoint", "grad_u", "grad_shift", "residual",
+           "triang_eig", "lanczos_sigma_min", "solve", "MultiShiftSolve", "colmajor",
+           "MstError", "version", "lib_path"]
+
+lib_path = _lib.LIB_PATH
+
+
+def version() -> str:
+    return _lib.load().mst_version().decode()
+
+
+def _opts(nb=0, outer_nb=0, precision=0, max_sweeps=0, omega_log2=0, force_phase2=0):
+    o = MstOpts()
+    o.nb, o.outer_nb, o.precision = int(nb), int(outer_nb), int(precision)
+    o.max_sweeps, o.omega_log2, o.force_phase2 = int(max_sweeps), int(omega_log2), int(force_phase2)
+    return o
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _is_colmajor(t: torch.Tensor) -> bool:
+    if t.dim() != 2:
+        return False
+    m, n = t.shape
+    if m <= 1 or n <= 1:
+        return t.is_contiguous() or t.stride(0) == 1
+    return t.stride(0) == 1 and t.stride(1) >= m
+
+
+def colmajor(t: torch.Tensor, dtype=torch.complex128) -> torch.Tensor:
+    """The same matrix as a column-major (Fortran-ordered) tensor of `dtype`;
+    `t` itself when it already is one."""
+    if t.dtype != dtype:
+        t = t.to(dtype)
+    if _is_colmajor(t):
+        return t
+    return t.t().contiguous().t()
+
+
+def _ld(t: torch.Tensor) -> int:
+    m, n = t.shape
+    if n <= 1 or m <= 1:
+        return max(1, m) if t.stride(0) == 1 or m <= 1 else t.stride(0)
+    return t.stride(1)
+
+
+def _dev(t: torch.Tensor, name: str) -> None:
+    if not t.is_cuda:
+        raise ValueError("%s must be on a ROCm device" % name)
+
+
+def _vec(t: torch.Tensor, n: int, name: str, dtype=torch.complex128) -> torch.Tensor:
+    t = t.reshape(-1)
+    if t.dtype != dtype:
+        t = t.to(dtype)
+    t = t.contiguous()
+    if t.numel() != n:
+        raise ValueError("%s must have %d entries" % (name, n))
+    _dev(t, name)
+    return t
+
+
+def _fcopy(t: torch.Tensor) -> torch.Tensor:
+    """A fresh column-major complex128 copy of matrix t."""
+    m, n = t.shape
+    out = torch.empty_strided((m, n), (1, max(1, m)), dtype=torch.complex128, device=t.device)
+    out.copy_(t)
+    return out
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else None
+
+
+def _mat(t: torch.Tensor, name: str) -> torch.Tensor:
+    if t.dim() != 2:
+        raise ValueError("%s must be a matrix" % name)
+    _dev(t, name)
+    return colmajor(t)
+
+
+def mstrsm(U, shifts, B, *, nb=64, outer_nb=0, precision=0, max_sweeps=2):
+    """X with (U - shifts[j] I) X[:, j] = B[:, j]; B is overwritten when it is
+    already column-major complex128 (the result is returned either way).
+    precision=1: FP32 substitution GEMMs + FP64 refinement (max_sweeps)."""
+    U = _mat(U, "U")
+    X = _mat(B, "B")
+    m, n = X.shape
+    if U.shape != (m, m):
+        raise ValueError("U must be %d x %d" % (m, m))
+    s = _vec(shifts, n, "shifts")
+    o = _opts(nb=nb, outer_nb=outer_nb, precision=precision, max_sweeps=max_sweeps)
+    rc = _lib.load().mstrsm(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), ctypes.byref(o), _stream())
+    _lib.check("mstrsm", rc)
+    return X
+
+
+def mstrsm_safe(U, shifts, B, col_len=None, *, nb=64, outer_nb=0, omega_log2=0):
+    """Safe solve: returns (X, scale, scale_log2) with
+    (U - shifts[j] I) X[:, j] = scale[j] B[:, j], scale[j] = 2^-scale_log2[j]."""
+    U = _mat(U, "U")
+    X = _mat(B, "B")
+    m, n = X.shape
+    if U.shape != (m, m):
+        raise ValueError("U must be %d x %d" % (m, m))
+    s = _vec(shifts, n, "shifts")
+    cl = _vec(col_len, n, "col_len", torch.int32) if col_len is not None else None
+    scale = torch.empty(n, dtype=torch.float64, device=X.device)
+    klog = torch.empty(n, dtype=torch.int32, device=X.device)
+    o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2)
+    rc = _lib.load().mstrsm_safe(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), _p(cl), _p(scale),
+                                 _p(klog), ctypes.byref(o), _stream())
+    _lib.check("mstrsm_safe", rc)
+    return X, scale, klog
+
+
+def mstrsm_adjoint(U, shifts, G, *, nb=64, outer_nb=0):
+    """Y with (U - shifts[j] I)^H Y[:, j] = G[:, j] (G overwritten when column-major)."""
+    U = _mat(U, "U")
+    Y = _mat(G, "G")
+    m, n = Y.shape
+    if U.shape != (m, m):
+        raise ValueError("U must be %d x %d" % (m, m))
+    s = _vec(shifts, n, "shifts")
+    o = _opts(nb=nb, outer_nb=outer_nb)
+    rc = _lib.load().mstrsm_adjoint(m, n, _p(U), _ld(U), _p(s), _p(Y), _ld(Y), ctypes.byref(o),
+                                    _stream())
+    _lib.check("mstrsm_adjoint", rc)
+    return Y
+
+
+def grad_u(Y, X):
+    """-triu(Y X^H) (m x m, strict lower triangle zero)."""
+    Y = _mat(Y, "Y")
+    X = _mat(X, "X")
+    m, n = Y.shape
+    if X.shape != (m, n):
+        raise ValueError("X and Y must have the same shape")
+    gU = torch.empty_strided((m, m), (1, max(1, m)), dtype=torch.complex128, device=Y.device)
+    rc = _lib.load().mst_grad_u(m, n, _p(Y), _ld(Y), _p(X), _ld(X), _p(gU), max(1, m), _stream())
+    _lib.check("mst_grad_u", rc)
+    return gU
+
+
+def grad_shift(X, Y):
+    """sum_i conj(X[i, j]) Y[i, j] for every column j."""
+    X = _mat(X, "X")
+    Y = _mat(Y, "Y")
+    m, n = X.shape
+    if Y.shape != (m, n):
+        raise ValueError("X and Y must have the same shape")
+    out = torch.empty(n, dtype=torch.complex128, device=X.device)
+    rc = _lib.load().mst_grad_shift(m, n, _p(X), _ld(X), _p(Y), _ld(Y), _p(out), _stream())
+    _lib.check("mst_grad_shift", rc)
+    return out
+
+
+def residual(U, shifts, X, B0):
+    """B0 - (U X - X diag(shifts)) in FP64 on the matrix cores."""
+    U = _mat(U, "U")
+    X = _mat(X, "X")
+    B0 = _mat(B0, "B0")
+    m, n = X.shape
+    s = _vec(shifts, n, "shifts")
+    R = torch.empty_strided((m, n), (1, max(1, m)), dtype=torch.complex128, device=X.device)
+    rc = _lib.load().mst_residual(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), _p(B0), _ld(B0), _p(R),
+                                  max(1, m), _stream())
+    _lib.check("mst_residual", rc)
+    return R
+
+
+def triang_eig(T, *, nb=64, outer_nb=0, omega_log2=0):
+    """TriangEig (Alg 6): returns (eigvals, Z, scale_log2) with T Z[:, j] =
+    eigvals[j] Z[:, j], Z upper triangular, Z[j, j] = 2^-scale_log2[j]."""
+    T = _mat(T, "T")
+    m = T.shape[0]
+    if T.shape != (m, m):
+        raise ValueError("T must be square")
+    Z = torch.empty_strided((m, m), (1, max(1, m)), dtype=torch.complex128, device=T.device)
+    ev = torch.empty(m, dtype=torch.complex128, device=T.device)
+    klog = torch.empty(m, dtype=torch.int32, device=T.device)
+    o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2)
+    rc = _lib.load().mst_triang_eig(m, _p(T), _ld(T), _p(Z), max(1, m), _p(ev), _p(klog),
+                                    ctypes.byref(o), _stream())
+    _lib.check("mst_triang_eig", rc)
+    return ev, Z, klog
+
+
+def lanczos_sigma_min(U, z, V0, iters=15, *, nb=64, outer_nb=0):
+    """Inverse-Lanczos estimate of sigma_min(U - z_j I) for every shift
+    (Alg 7, second stage). V0 (m x N start vectors) is not modified.
+    Returns (sigma, alpha, beta, steps); alpha/beta are (N, iters)."""
+    U = _mat(U, "U")
+    V0 = _mat(V0, "V0")
+    m, N = V0.shape
+    V = _fcopy(V0)
+    zz = _vec(z, N, "z")
+    sigma = torch.empty(N, dtype=torch.float64, device=V.device)
+    alpha = torch.empty((N, iters), dtype=torch.float64, device=V.device)
+    beta = torch.empty((N, iters), dtype=torch.float64, device=V.device)
+    steps = torch.empty(N, dtype=torch.int32, device=V.device)
+    o = _opts(nb=nb, outer_nb=outer_nb)
+    rc = _lib.load().mst_lanczos_sigma_min(m, N, _p(U), _ld(U), _p(zz), _p(V), _ld(V), int(iters),
+                                           _p(sigma), _p(alpha), _p(beta), _p(steps),
+                                           ctypes.byref(o), _stream())
+    _lib.check("mst_lanczos_sigma_min", rc)
+    return sigma, alpha, beta, steps
+
+
+class MultiShiftSolve(torch.autograd.Function):
+    """X = solve(U, shifts, B) with (U - shifts_j I) x_j = b_j, differentiable
+    in U (upper triangle), shifts and B. Backward: Y = adjoint solve of dL/dX,
+    gB = Y, gU = -triu(Y X^H), gshift_j = x_j^H y_j (gradient convention
+    dL/dRe z + i dL/dIm z, as torch uses for complex tensors)."""
+
+    @staticmethod
+    def forward(ctx, U, shifts, B, nb, outer_nb, precision, max_sweeps):
+        X = _fcopy(B)
+        mstrsm(U, shifts, X, nb=nb, outer_nb=outer_nb, precision=precision, max_sweeps=max_sweeps)
+        ctx.save_for_backward(U, shifts, X)
+        ctx.nb, ctx.outer_nb = nb, outer_nb
+        return X
+
+    @staticmethod
+    def backward(ctx, gX):
+        U, shifts, X = ctx.saved_tensors
+        Y = _fcopy(gX)
+        mstrsm_adjoint(U, shifts, Y, nb=ctx.nb, outer_nb=ctx.outer_nb)
+        gU = grad_u(Y, X) if ctx.needs_input_grad[0] else None
+        gs = grad_shift(X, Y) if ctx.needs_input_grad[1] else None
+        gB = Y if ctx.needs_input_grad[2] else None
+        return gU, gs, gB, None, None, None, None
+
+
+def solve(U, shifts, B, *, nb=64, outer_nb=0, precision=0, max_sweeps=2):
+    """Differentiable multi-shift solve (see MultiShiftSolve)."""
+    return MultiShiftSolve.apply(U, shifts, B, nb, outer_nb, precision, max_sweeps)
+
+
+class profile:
+    """Context manager timing every kernel the library launches from this
+    thread (HIP events around each launch). After exit, `.result` maps a
+    kernel family to {"ms", "flops", "launches"}."""
+
+    def __enter__(self):
+        _lib.check("mst_profile_start", _lib.load().mst_profile_start())
+        return self
+
+    def __exit__(self, *exc):
+        k = len(_lib.PROF_KINDS)
+        ms = (ctypes.c_double * k)()
+        fl = (ctypes.c_double * k)()
+        ln = (ctypes.c_longlong * k)()
+        rc = _lib.load().mst_profile_stop(ms, fl, ln)
+        self.result = {name: {"ms": ms[i], "flops": fl[i], "launches": ln[i]}
+                       for i, name in enumerate(_lib.PROF_KINDS)}
+        if exc[0] is None:
+            _lib.check("mst_profile_stop", rc)
+        return False

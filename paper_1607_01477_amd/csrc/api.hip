@@ -1,0 +1,570 @@
+// C-ABI of the mstrsm library: argument checking, workspace, and the block
+// loops of the multi-shift solves (Moon & Poulson, arXiv 1607.01477).
+//
+// Block order. Diagonal blocks of nb rows are aligned from the top (row starts
+// 0, nb, 2nb, ...; the bottom block may be partial) and solved bottom to top
+// (top to bottom for the adjoint). Consecutive diagonal blocks are grouped into
+// outer blocks of outer_nb rows: after each diagonal block only the rows of its
+// own outer block are updated (a short GEMM with K = nb), and the rows above
+// the outer block receive one GEMM with K = outer_nb once the whole outer block
+// is solved. This is Alg 3 with the substitution of several consecutive
+// diagonal blocks fused into one longer product: the same arithmetic in
+// another order, with a deeper K per pass over B so the GEMM is not bound by
+// re-reading and re-writing B. outer_nb = nb gives the paper's order exactly.
+//
+// Safe solve (Alg 5): per diagonal block the kernel records the column's
+// exponent k_j after that block; a GEMM brings its B operand rows and its C
+// rows to the current exponent on the fly (exact powers of two), and a final
+// pass rescales each solved block to the final exponent, so scaling never
+// costs an extra sweep over B while no rescaling happens.
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "common.h"
+#include "mstrsm.h"
+
+using namespace mst;
+
+namespace {
+
+thread_local int t_bad_arg = 0;
+thread_local char t_err[256] = "";
+
+mst_status bad(int pos) {
+    t_bad_arg = pos;
+    return MST_EARG;
+}
+
+mst_status fail_hip(hipError_t e, const char* what) {
+    snprintf(t_err, sizeof(t_err), "%s: %s", what, hipGetErrorString(e));
+    return (e == hipErrorOutOfMemory) ? MST_ENOMEM : MST_EHIP;
+}
+
+#define HIPCHK(x)                                             \
+    do {                                                      \
+        hipError_t e_ = (x);                                  \
+        if (e_ != hipSuccess) return fail_hip(e_, #x);        \
+    } while (0)
+
+// ---------------------------------------------------------------- kernel timing
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double flops;
+};
+thread_local bool t_prof = false;
+thread_local std::vector<ProfRec> t_recs;
+thread_local std::vector<hipEvent_t> t_pool;
+
+hipEvent_t pool_event() {
+    if (!t_pool.empty()) {
+        hipEvent_t e = t_pool.back();
+        t_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// Runs launch() bracketed by events when profiling is on.
+template <typename F>
+hipError_t timed(int kind, double flops, hipStream_t s, F&& launch) {
+    if (!t_prof) return launch();
+    ProfRec r{kind, pool_event(), pool_event(), flops};
+    (void)hipEventRecord(r.a, s);
+    hipError_t e = launch();
+    (void)hipEventRecord(r.b, s);
+    t_recs.push_back(r);
+    return e;
+}
+
+double gemm_flops(const GemmArgs& g) { return 8.0 * g.M * (double)g.N * g.K; }
+
+struct Opts {
+    int nb = 64, outer = 256, precision = 0, sweeps = 2, omega_log2 = 960;
+};
+
+// position of opt in the caller's argument list, for error reporting
+mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
+    r = Opts();
+    if (!o) return MST_OK;
+    if (o->nb) r.nb = o->nb;
+    if (r.nb != 16 && r.nb != 32 && r.nb != 64) return bad(pos);
+    r.outer = o->outer_nb ? o->outer_nb : (r.nb > 256 ? r.nb : 256);
+    if (o->outer_nb == 0 && r.outer % r.nb) r.outer = r.nb;
+    if (r.outer < r.nb || r.outer % r.nb || r.outer > 8192) return bad(pos);
+    r.precision = o->precision;
+    if (r.precision != 0 && r.precision != 1) return bad(pos);
+    if (o->max_sweeps) r.sweeps = o->max_sweeps;
+    if (r.sweeps < 1 || r.sweeps > 3) return bad(pos);
+    if (o->omega_log2) r.omega_log2 = o->omega_log2;
+    if (r.omega_log2 < 8 || r.omega_log2 > 1000) return bad(pos);
+    return MST_OK;
+}
+
+// Stream-ordered workspace, released on scope exit (also on error paths).
+struct Workspace {
+    hipStream_t s;
+    std::vector<void*> ptrs;
+    explicit Workspace(hipStream_t st) : s(st) {}
+    ~Workspace() {
+        for (void* p : ptrs) (void)hipFreeAsync(p, s);
+    }
+    hipError_t get(size_t bytes, void** out) {
+        void* p = nullptr;
+        hipError_t e = hipMallocAsync(&p, bytes > 0 ? bytes : 16, s);
+        if (e != hipSuccess) return e;
+        ptrs.push_back(p);
+        *out = p;
+        return hipSuccess;
+    }
+};
+
+template <typename T>
+hipError_t ws_get(Workspace& w, size_t count, T** out) {
+    return w.get(count * sizeof(T), (void**)out);
+}
+
+// ---------------------------------------------------------------- forward block loop
+// FP64 (b32 == nullptr) or mixed: the right-hand side lives in W32 (FP32) for the
+// substitution GEMMs and the diagonal blocks write FP64 X into B.
+hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long ldu32,
+                        const zd* lam, zd* B, long ldb, zf* W32, long ldw, const Opts& o,
+                        const SafeState* safe, const int* col_len, hipStream_t s) {
+    const int nb = o.nb, P = o.outer / o.nb;
+    const int nblk = (m + nb - 1) / nb;
+    const int nob = (nblk + P - 1) / P;
+    const bool mixed = W32 != nullptr;
+    for (int ob = nob - 1; ob >= 0; --ob) {
+        const int qa = ob * P, qb = (qa + P < nblk ? qa + P : nblk) - 1;
+        for (int q = qb; q >= qa; --q) {
+            const int i0 = q * nb, bs = (m - i0 < nb) ? m - i0 : nb;
+            DiagArgs d{};
+            d.m = m; d.n = n; d.i0 = i0; d.bs = bs; d.q = q;
+            d.U = U; d.ldu = ldu; d.lam = lam; d.B = B; d.ldb = ldb;
+            d.b32 = mixed ? W32 : nullptr; d.ldb32 = ldw;
+            d.col_len = col_len;
+            if (safe) {
+                d.safe = *safe;
+                d.use_safe = 1;
+            } else {
+                d.safe.omega_log2 = o.omega_log2;
+            }
+            hipError_t e = timed(MST_PROF_DIAG, 4.0 * bs * bs * (double)n, s, [&] { return launch_diag(nb, false, d, s); });
+            if (e != hipSuccess) return e;
+            if (q > qa) {
+                GemmArgs g{};
+                g.M = i0 - qa * nb; g.N = n; g.K = bs;
+                g.op = GOP_SUB;
+                g.nb = nb; g.b_row0 = i0; g.c_row0 = qa * nb; g.col_len = col_len;
+                if (safe) {
+                    g.kb = safe->kb; g.n_kb = n; g.q_cur = q; g.q_c = (q + 1 < nblk) ? q + 1 : -1;
+                }
+                if (!mixed) {
+                    g.A = U + (long)i0 * ldu + qa * nb; g.lda = ldu;
+                    g.B = B + i0; g.ldb = ldb;
+                    g.C = B + qa * nb; g.ldc = ldb;
+                    e = timed(MST_PROF_GEMM_F64, gemm_flops(g), s, [&] { return launch_gemm_f64(g, s); });
+                } else {
+                    g.A = U32 + (long)i0 * ldu32 + qa * nb; g.lda = ldu32;
+                    g.B = W32 + i0; g.ldb = ldw;
+                    g.C = W32 + qa * nb; g.ldc = ldw;
+                    e = timed(MST_PROF_GEMM_F32, gemm_flops(g), s, [&] { return launch_gemm_f32(g, s); });
+                }
+                if (e != hipSuccess) return e;
+            }
+        }
+        if (qa > 0) {
+            const int r1 = qa * nb;
+            const int end = ((qb + 1) * nb < m) ? (qb + 1) * nb : m;
+            GemmArgs g{};
+            g.M = r1; g.N = n; g.K = end - r1;
+            g.op = GOP_SUB;
+            g.nb = nb; g.b_row0 = r1; g.c_row0 = 0; g.col_len = col_len;
+            if (safe) {
+                g.kb = safe->kb; g.n_kb = n; g.q_cur = qa; g.q_c = (qb + 1 < nblk) ? qb + 1 : -1;
+            }
+            hipError_t e;
+            if (!mixed) {
+                g.A = U + (long)r1 * ldu; g.lda = ldu;
+                g.B = B + r1; g.ldb = ldb;
+                g.C = B; g.ldc = ldb;
+                e = timed(MST_PROF_GEMM_F64, gemm_flops(g), s, [&] { return launch_gemm_f64(g, s); });
+            } else {
+                g.A = U32 + (long)r1 * ldu32; g.lda = ldu32;
+                g.B = W32 + r1; g.ldb = ldw;
+                g.C = W32; g.ldc = ldw;
+                e = timed(MST_PROF_GEMM_F32, gemm_flops(g), s, [&] { return launch_gemm_f32(g, s); });
+            }
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------- adjoint block loop
+hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* G, long ldg,
+                        const Opts& o, hipStream_t s) {
+    const int nb = o.nb, P = o.outer / o.nb;
+    const int nblk = (m + nb - 1) / nb;
+    const int nob = (nblk + P - 1) / P;
+    for (int ob = 0; ob < nob; ++ob) {
+        const int qa = ob * P, qb = (qa + P < nblk ? qa + P : nblk) - 1;
+        const int end = ((qb + 1) * nb < m) ? (qb + 1) * nb : m;
+        for (int q = qa; q <= qb; ++q) {
+            const int i0 = q * nb, bs = (m - i0 < nb) ? m - i0 : nb;
+            const int i1 = i0 + bs;
+            DiagArgs d{};
+            d.m = m; d.n = n; d.i0 = i0; d.bs = bs; d.q = q;
+            d.U = U; d.ldu = ldu; d.lam = lam; d.B = G; d.ldb = ldg;
+            d.safe.omega_log2 = o.omega_log2;
+            hipError_t e = timed(MST_PROF_DIAG, 4.0 * bs * bs * (double)n, s, [&] { return launch_diag(nb, true, d, s); });
+            if (e != hipSuccess) return e;
+            if (q < qb) {
+                // G(i1:end) -= U(i0:i1, i1:end)^H Y(i0:i1)
+                GemmArgs g{};
+                g.M = end - i1; g.N = n; g.K = bs; g.op = GOP_SUB;
+                g.A = U + (long)i1 * ldu + i0; g.lda = ldu; g.a_ct = 1;
+                g.B = G + i0; g.ldb = ldg;
+                g.C = G + i1; g.ldc = ldg;
+                e = timed(MST_PROF_GEMM_F64, gemm_flops(g), s, [&] { return launch_gemm_f64(g, s); });
+                if (e != hipSuccess) return e;
+            }
+        }
+        if (end < m) {
+            const int r0 = qa * nb;
+            GemmArgs g{};
+            g.M = m - end; g.N = n; g.K = end - r0; g.op = GOP_SUB;
+            g.A = U + (long)end * ldu + r0; g.lda = ldu; g.a_ct = 1;
+            g.B = G + r0; g.ldb = ldg;
+            g.C = G + end; g.ldc = ldg;
+            hipError_t e = timed(MST_PROF_GEMM_F64, gemm_flops(g), s, [&] { return launch_gemm_f64(g, s); });
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t residual(int m, int n, const zd* U, long ldu, const zd* lam, const zd* X, long ldx,
+                    const zd* B0, long ldb0, zd* R, long ldr, hipStream_t s) {
+    GemmArgs g{};
+    g.M = m; g.N = n; g.K = m; g.op = GOP_RESID;
+    g.A = U; g.lda = ldu;
+    g.B = X; g.ldb = ldx;
+    g.C = R; g.ldc = ldr;
+    g.B0 = B0; g.ldb0 = ldb0; g.lam = lam;
+    return timed(MST_PROF_RESID, 4.0 * m * (double)m * n, s, [&] { return launch_gemm_f64(g, s); });
+}
+
+mst_status check_mat(const void* p, int ld, int rows, int cols, int ppos, int ldpos) {
+    if (ld < (rows > 1 ? rows : 1)) return bad(ldpos);
+    if ((long)rows * cols > 0 && p == nullptr) return bad(ppos);
+    return MST_OK;
+}
+
+// safe solve into an existing workspace scope
+mst_status safe_solve(int m, int n, const zd* U, long ldu, const zd* lam, zd* B, long ldb,
+                      const int* col_len, double* scale, int* klog, const Opts& o, hipStream_t s,
+                      Workspace& ws) {
+    const int nb = o.nb;
+    const int nblk = (m + nb - 1) / nb;
+    double *G, *cn_in, *above, *colmax, *above_sum, *delta;
+    int *kcur, *kb;
+    HIPCHK(ws_get(ws, (size_t)n, &G));
+    HIPCHK(ws_get(ws, (size_t)n, &kcur));
+    HIPCHK(ws_get(ws, (size_t)nblk * n, &kb));
+    HIPCHK(ws_get(ws, (size_t)m, &cn_in));
+    HIPCHK(ws_get(ws, (size_t)m, &above));
+    HIPCHK(ws_get(ws, (size_t)m, &colmax));
+    HIPCHK(ws_get(ws, (size_t)nblk, &above_sum));
+    HIPCHK(ws_get(ws, (size_t)1, &delta));
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_norms(m, U, ldu, nb, cn_in, above, colmax, above_sum, delta, s); }));
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_colinit(m, n, B, ldb, col_len, G, kcur, s); }));
+    SafeState st{};
+    st.G = G; st.kcur = kcur; st.kb = kb; st.cn_in = cn_in; st.above_sum = above_sum;
+    st.delta = delta; st.omega_log2 = o.omega_log2;
+    HIPCHK(forward_loop(m, n, U, ldu, nullptr, 0, lam, B, ldb, nullptr, 0, o, &st, col_len, s));
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_finalize(m, n, nb, B, ldb, col_len, kcur, kb, scale, klog, s); }));
+    return MST_OK;
+}
+
+mst_status plain_solve(int m, int n, const zd* U, long ldu, const zd* lam, zd* B, long ldb,
+                       const Opts& o, hipStream_t s, Workspace& ws) {
+    if (o.precision == 0) {
+        HIPCHK(forward_loop(m, n, U, ldu, nullptr, 0, lam, B, ldb, nullptr, 0, o, nullptr, nullptr, s));
+        return MST_OK;
+    }
+    // FP32 substitution GEMMs, FP64 diagonal blocks, FP64 refinement
+    zf *U32, *W32;
+    zd *B0, *R;
+    HIPCHK(ws_get(ws, (size_t)m * m, &U32));
+    HIPCHK(ws_get(ws, (size_t)m * n, &W32));
+    HIPCHK(ws_get(ws, (size_t)m * n, &B0));
+    HIPCHK(ws_get(ws, (size_t)m * n, &R));
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_to_f32(m, m, U, ldu, U32, m, true, s); }));
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_copy(m, n, B, ldb, B0, m, s); }));
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_to_f32(m, n, B, ldb, W32, m, false, s); }));
+    HIPCHK(forward_loop(m, n, U, ldu, U32, m, lam, B, ldb, W32, m, o, nullptr, nullptr, s));
+    for (int sw = 0; sw < o.sweeps; ++sw) {
+        HIPCHK(residual(m, n, U, ldu, lam, B, ldb, B0, m, R, m, s));
+        HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_to_f32(m, n, R, m, W32, m, false, s); }));
+        HIPCHK(forward_loop(m, n, U, ldu, U32, m, lam, R, m, W32, m, o, nullptr, nullptr, s));
+        HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_axpy_inplace(m, n, R, m, B, ldb, s); }));
+    }
+    return MST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mst_status mstrsm(int m, int n, const void* U, int ldu, const void* shifts, void* B, int ldb,
+                  const mst_opts* opt, void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    if (n < 0) return bad(2);
+    mst_status st;
+    if ((st = check_mat(U, ldu, m, m, 3, 4)) != MST_OK) return st;
+    if (n > 0 && m > 0 && !shifts) return bad(5);
+    if ((st = check_mat(B, ldb, m, n, 6, 7)) != MST_OK) return st;
+    Opts o;
+    if ((st = read_opts(opt, o, 8)) != MST_OK) return st;
+    if (m == 0 || n == 0) return MST_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace ws(s);
+    return plain_solve(m, n, (const zd*)U, ldu, (const zd*)shifts, (zd*)B, ldb, o, s, ws);
+}
+
+mst_status mstrsm_safe(int m, int n, const void* U, int ldu, const void* shifts, void* B, int ldb,
+                       const int* col_len, double* scale, int* scale_log2, const mst_opts* opt,
+                       void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    if (n < 0) return bad(2);
+    mst_status st;
+    if ((st = check_mat(U, ldu, m, m, 3, 4)) != MST_OK) return st;
+    if (n > 0 && m > 0 && !shifts) return bad(5);
+    if ((st = check_mat(B, ldb, m, n, 6, 7)) != MST_OK) return st;
+    if (n > 0 && !scale) return bad(9);
+    Opts o;
+    if ((st = read_opts(opt, o, 11)) != MST_OK) return st;
+    if (o.precision != 0) return MST_EUNSUPPORTED;
+    if (n == 0) return MST_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace ws(s);
+    if (m == 0) {
+        // no rows: s_j = 1, k_j = 0
+        int* kcur;
+        int* kb;
+        HIPCHK(ws_get(ws, (size_t)n, &kcur));
+        HIPCHK(ws_get(ws, (size_t)n, &kb));
+        HIPCHK(launch_fill_int(n, 0, kcur, s));
+        HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_finalize(0, n, o.nb, (zd*)B, 1, nullptr, kcur, kb, scale, scale_log2, s); }));
+        return MST_OK;
+    }
+    return safe_solve(m, n, (const zd*)U, ldu, (const zd*)shifts, (zd*)B, ldb, col_len, scale,
+                      scale_log2, o, s, ws);
+}
+
+mst_status mstrsm_adjoint(int m, int n, const void* U, int ldu, const void* shifts, void* G, int ldg,
+                          const mst_opts* opt, void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    if (n < 0) return bad(2);
+    mst_status st;
+    if ((st = check_mat(U, ldu, m, m, 3, 4)) != MST_OK) return st;
+    if (n > 0 && m > 0 && !shifts) return bad(5);
+    if ((st = check_mat(G, ldg, m, n, 6, 7)) != MST_OK) return st;
+    Opts o;
+    if ((st = read_opts(opt, o, 8)) != MST_OK) return st;
+    if (o.precision != 0) return MST_EUNSUPPORTED;
+    if (m == 0 || n == 0) return MST_OK;
+    HIPCHK(adjoint_loop(m, n, (const zd*)U, ldu, (const zd*)shifts, (zd*)G, ldg, o, (hipStream_t)stream));
+    return MST_OK;
+}
+
+mst_status mst_grad_u(int m, int n, const void* Y, int ldy, const void* X, int ldx, void* gU, int ldgu,
+                      void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    if (n < 0) return bad(2);
+    mst_status st;
+    if ((st = check_mat(Y, ldy, m, n, 3, 4)) != MST_OK) return st;
+    if ((st = check_mat(X, ldx, m, n, 5, 6)) != MST_OK) return st;
+    if ((st = check_mat(gU, ldgu, m, m, 7, 8)) != MST_OK) return st;
+    if (m == 0) return MST_OK;
+    GemmArgs g{};
+    g.M = m; g.N = m; g.K = n; g.op = GOP_NEG_TRIU;
+    g.A = Y; g.lda = ldy;
+    g.B = X; g.ldb = ldx; g.b_ct = 1;
+    g.C = gU; g.ldc = ldgu;
+    HIPCHK(timed(MST_PROF_RESID, 4.0 * m * (double)m * n, (hipStream_t)stream, [&] { return launch_gemm_f64(g, (hipStream_t)stream); }));
+    return MST_OK;
+}
+
+mst_status mst_grad_shift(int m, int n, const void* X, int ldx, const void* Y, int ldy, void* gshift,
+                          void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    if (n < 0) return bad(2);
+    mst_status st;
+    if ((st = check_mat(X, ldx, m, n, 3, 4)) != MST_OK) return st;
+    if ((st = check_mat(Y, ldy, m, n, 5, 6)) != MST_OK) return st;
+    if (n > 0 && !gshift) return bad(7);
+    if (n == 0) return MST_OK;
+    HIPCHK(timed(MST_PROF_AUX, 8.0 * m * (double)n, (hipStream_t)stream, [&] { return launch_dot(m, n, (const zd*)X, ldx, (const zd*)Y, ldy, (zd*)gshift, (hipStream_t)stream); }));
+    return MST_OK;
+}
+
+mst_status mst_residual(int m, int n, const void* U, int ldu, const void* shifts, const void* X, int ldx,
+                        const void* B0, int ldb0, void* R, int ldr, void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    if (n < 0) return bad(2);
+    mst_status st;
+    if ((st = check_mat(U, ldu, m, m, 3, 4)) != MST_OK) return st;
+    if (n > 0 && m > 0 && !shifts) return bad(5);
+    if ((st = check_mat(X, ldx, m, n, 6, 7)) != MST_OK) return st;
+    if ((st = check_mat(B0, ldb0, m, n, 8, 9)) != MST_OK) return st;
+    if ((st = check_mat(R, ldr, m, n, 10, 11)) != MST_OK) return st;
+    if (R == X && m * n > 0) return bad(10);
+    if (R == B0 && ldr != ldb0) return bad(11);
+    if (m == 0 || n == 0) return MST_OK;
+    HIPCHK(residual(m, n, (const zd*)U, ldu, (const zd*)shifts, (const zd*)X, ldx, (const zd*)B0, ldb0,
+                    (zd*)R, ldr, (hipStream_t)stream));
+    return MST_OK;
+}
+
+mst_status mst_triang_eig(int m, const void* T, int ldt, void* Z, int ldz, void* eigvals, int* scale_log2,
+                          const mst_opts* opt, void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    mst_status st;
+    if ((st = check_mat(T, ldt, m, m, 2, 3)) != MST_OK) return st;
+    if ((st = check_mat(Z, ldz, m, m, 4, 5)) != MST_OK) return st;
+    if (m > 0 && !eigvals) return bad(6);
+    Opts o;
+    if ((st = read_opts(opt, o, 8)) != MST_OK) return st;
+    if (o.precision != 0) return MST_EUNSUPPORTED;
+    if (m == 0) return MST_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace ws(s);
+    int* col_len;
+    double* scale;
+    HIPCHK(ws_get(ws, (size_t)m, &col_len));
+    HIPCHK(ws_get(ws, (size_t)m, &scale));
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_triang_setup(m, (const zd*)T, ldt, (zd*)Z, ldz, (zd*)eigvals, col_len, s); }));
+    st = safe_solve(m, m, (const zd*)T, ldt, (const zd*)eigvals, (zd*)Z, ldz, col_len, scale, scale_log2,
+                    o, s, ws);
+    if (st != MST_OK) return st;
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_triang_diag(m, (zd*)Z, ldz, scale, s); }));
+    return MST_OK;
+}
+
+mst_status mst_lanczos_sigma_min(int m, int N, const void* U, int ldu, const void* z, void* V, int ldv,
+                                 int iters, double* sigma, double* alpha, double* beta, int* steps,
+                                 const mst_opts* opt, void* stream) {
+    t_bad_arg = 0;
+    if (m < 1) return bad(1);
+    if (N < 0) return bad(2);
+    mst_status st;
+    if ((st = check_mat(U, ldu, m, m, 3, 4)) != MST_OK) return st;
+    if (N > 0 && !z) return bad(5);
+    if ((st = check_mat(V, ldv, m, N, 6, 7)) != MST_OK) return st;
+    if (iters < 1 || iters > 64) return bad(8);
+    if (N > 0 && !sigma) return bad(9);
+    Opts o;
+    if ((st = read_opts(opt, o, 13)) != MST_OK) return st;
+    if (o.precision != 0) return MST_EUNSUPPORTED;
+    if (N == 0) return MST_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace ws(s);
+    zd *W, *Vp;
+    int* stp = steps;
+    double *al = alpha, *be = beta;
+    HIPCHK(ws_get(ws, (size_t)m * N, &W));
+    HIPCHK(ws_get(ws, (size_t)m * N, &Vp));
+    if (!stp) HIPCHK(ws_get(ws, (size_t)N, &stp));
+    if (!al) HIPCHK(ws_get(ws, (size_t)iters * N, &al));
+    if (!be) HIPCHK(ws_get(ws, (size_t)iters * N, &be));
+    // steps = iters (no early stop yet); vprev = 0
+    HIPCHK(launch_fill_int(N, iters, stp, s));
+    HIPCHK(launch_zero((long)m * N, Vp, s));
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_normalize_cols(m, N, (zd*)V, ldv, s); }));
+    zd* bufs[3] = {(zd*)V, W, Vp};
+    long lds[3] = {ldv, m, m};
+    int iv = 0, iw = 1, ip = 2;
+    const zd* Uz = (const zd*)U;
+    const zd* zz = (const zd*)z;
+    for (int it = 0; it < iters; ++it) {
+        HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_copy(m, N, bufs[iv], lds[iv], bufs[iw], lds[iw], s); }));
+        HIPCHK(forward_loop(m, N, Uz, ldu, nullptr, 0, zz, bufs[iw], lds[iw], nullptr, 0, o, nullptr,
+                            nullptr, s));
+        HIPCHK(adjoint_loop(m, N, Uz, ldu, zz, bufs[iw], lds[iw], o, s));
+        HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] {
+            return launch_lanczos_step(m, N, it, iters, bufs[iv], lds[iv], bufs[iw], lds[iw], bufs[ip],
+                                       lds[ip], al, be, stp, s);
+        }));
+        const int nv = iw, np = iv, nw = ip;
+        iv = nv; ip = np; iw = nw;
+    }
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_tridiag_max(N, iters, al, be, stp, sigma, s); }));
+    return MST_OK;
+}
+
+mst_status mst_profile_start(void) {
+    for (auto& r : t_recs) {
+        t_pool.push_back(r.a);
+        t_pool.push_back(r.b);
+    }
+    t_recs.clear();
+    t_prof = true;
+    return MST_OK;
+}
+
+mst_status mst_profile_stop(double* ms, double* flops, long long* launches) {
+    t_prof = false;
+    double tms[MST_PROF_KINDS] = {0}, tfl[MST_PROF_KINDS] = {0};
+    long long tl[MST_PROF_KINDS] = {0};
+    mst_status st = MST_OK;
+    for (auto& r : t_recs) {
+        float e = 0.f;
+        hipError_t he = hipEventSynchronize(r.b);
+        if (he == hipSuccess) he = hipEventElapsedTime(&e, r.a, r.b);
+        if (he != hipSuccess) st = fail_hip(he, "hipEventElapsedTime");
+        if (r.kind >= 0 && r.kind < MST_PROF_KINDS) {
+            tms[r.kind] += e;
+            tfl[r.kind] += r.flops;
+            tl[r.kind] += 1;
+        }
+        t_pool.push_back(r.a);
+        t_pool.push_back(r.b);
+    }
+    t_recs.clear();
+    for (int k = 0; k < MST_PROF_KINDS; ++k) {
+        if (ms) ms[k] = tms[k];
+        if (flops) flops[k] = tfl[k];
+        if (launches) launches[k] = tl[k];
+    }
+    return st;
+}
+
+const char* mst_status_string(mst_status s) {
+    switch (s) {
+        case MST_OK: return "MST_OK";
+        case MST_EARG: return "MST_EARG: invalid argument";
+        case MST_EHIP: return "MST_EHIP: HIP runtime error";
+        case MST_ENOMEM: return "MST_ENOMEM: out of device memory";
+        case MST_EUNSUPPORTED: return "MST_EUNSUPPORTED: unsupported option combination";
+        default: return "unknown mst_status";
+    }
+}
+
+int mst_last_bad_arg(void) { return t_bad_arg; }
+const char* mst_last_error(void) { return t_err; }
+const char* mst_version(void) { return "0.1.0"; }
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Internal declarations of the mstrsm HIP library (gfx950). Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mst {
+
+struct zd { double re, im; };   // complex128, interleaved
+struct zf { float re, im; };    // complex64, interleaved
+
+// Safe-solve state kept on the device for one call.
+struct SafeState {
+    double* G;          // n: column growth bound G(j)
+    int* kcur;          // n: current exponent k_j (s_j = 2^-k_j)
+    int* kb;            // nblk x n: exponent of column j right after block q was solved
+    const double* cn_in;      // m: max cabs1 of U above the diagonal inside the diagonal block
+    const double* above_sum;  // nblk: sum over the block's columns of max cabs1 above the block
+    const double* delta;      // 1: replacement for a zero pivot
+    int omega_log2;
+};
+
+// ---------------------------------------------------------------- diagonal blocks
+// Solves the nb-row diagonal block [i0, i0+bs) for all n shifts in place.
+//   adjoint = false: (U(I1,I1) - lambda_j I) x = b        (back substitution, Alg 1)
+//   adjoint = true : (U(I1,I1) - lambda_j I)^H y = g      (forward substitution)
+// safe != nullptr: Alg 4 phase 2 with Alg 5's column bound and decisions, block index q.
+// b32 != nullptr (mixed precision): the right-hand side is read from b32 (FP32),
+// solved in FP64, and written both to B (FP64) and back to b32 (rounded).
+struct DiagArgs {
+    int m, n, i0, bs, q;
+    const zd* U; long ldu;
+    const zd* lam;
+    zd* B; long ldb;
+    zf* b32; long ldb32;
+    const int* col_len;
+    SafeState safe;
+    int use_safe;
+};
+hipError_t launch_diag(int nb, bool adjoint, const DiagArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- MFMA GEMM
+// C(M x N) <- epilogue(acc), acc = A(M x K) * B(K x N), complex.
+enum GemmOp : int {
+    GOP_SUB = 0,      // C = 2^-dk_c * C - acc   (dk from the safe state, else 0)
+    GOP_RESID = 1,    // C = B0 - acc + lam_c * Bop(row, c)   (A upper triangular, global indices)
+    GOP_NEG_TRIU = 2, // C = -acc on and above the diagonal, 0 below
+};
+struct GemmArgs {
+    int M, N, K;
+    const void* A; long lda; int a_ct;   // a_ct: A(r,k) = conj(a[r*lda + k]); else a[k*lda + r]
+    const void* B; long ldb; int b_ct;   // b_ct: B(k,c) = conj(b[k*ldb + c]); else b[c*ldb + k]
+    void* C; long ldc;
+    int op;
+    // GOP_RESID: A is U(0:M, 0:K) (square, upper triangular), Bop is X, B0/lam given
+    const zd* B0; long ldb0; const zd* lam;
+    // safe scaling (GOP_SUB): kb rows of the B operand belong to blocks (b_row0 + k)/nb,
+    // scaled on load by 2^-(kb[q_cur] - kb[q(k)]); C scaled by 2^-(kb[q_cur] - kb[q_c])
+    // (kb[-1] = 0, i.e. q_c < 0 means exponent 0).
+    const int* kb; int n_kb; int q_cur; int q_c; int nb; int b_row0;
+    // variable-length columns: column c uses rows < col_len[c] (global row of C row 0 = c_row0)
+    const int* col_len; int c_row0;
+};
+hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s);
+hipError_t launch_gemm_f32(const GemmArgs& g, hipStream_t s);
+
+// ---------------------------------------------------------------- auxiliary kernels
+hipError_t launch_norms(int m, const zd* U, long ldu, int nb, double* cn_in, double* above,
+                        double* colmax, double* above_sum, double* delta, hipStream_t s);
+hipError_t launch_colinit(int m, int n, const zd* B, long ldb, const int* col_len,
+                          double* G, int* kcur, hipStream_t s);
+hipError_t launch_finalize(int m, int n, int nb, zd* B, long ldb, const int* col_len,
+                           const int* kcur, const int* kb, double* scale, int* klog,
+                           hipStream_t s);
+hipError_t launch_dot(int m, int n, const zd* X, long ldx, const zd* Y, long ldy, zd* out,
+                      hipStream_t s);
+hipError_t launch_to_f32(int rows, int cols, const zd* src, long lds, zf* dst, long ldd,
+                         bool upper_only, hipStream_t s);
+hipError_t launch_copy(int rows, int cols, const zd* src, long lds, zd* dst, long ldd,
+                       hipStream_t s);
+hipError_t launch_axpy_inplace(int rows, int cols, const zd* D, long ldd, zd* X, long ldx,
+                               hipStream_t s);
+hipError_t launch_triang_setup(int m, const zd* T, long ldt, zd* Z, long ldz, zd* eig,
+                               int* col_len, hipStream_t s);
+hipError_t launch_triang_diag(int m, zd* Z, long ldz, const double* scale, hipStream_t s);
+hipError_t launch_normalize_cols(int m, int n, zd* V, long ldv, hipStream_t s);
+hipError_t launch_lanczos_step(int m, int n, int it, int iters, const zd* V, long ldv,
+                               zd* W, long ldw, const zd* Vprev, long ldp,
+                               double* alpha, double* beta, int* steps, hipStream_t s);
+hipError_t launch_fill_int(int n, int v, int* p, hipStream_t s);
+hipError_t launch_zero(long count, zd* p, hipStream_t s);
+hipError_t launch_tridiag_max(int n, int iters, const double* alpha, const double* beta,
+                              const int* steps, double* sigma, hipStream_t s);
+
+}  // namespace mst

@@ -1,0 +1,48 @@
+"""CPU-side checks of the C-ABI library: it loads and exports every symbol the
+public header declares (no compute calls: there is no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "mstrsm.h")) as f:
+        src = f.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(mst\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("mstrsm", "mstrsm_safe", "mstrsm_adjoint"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1607_01477_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1607_01477_amd import build
+        build.build()
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+    assert sorted(_lib.EXPORTS) == declared_symbols()
+    lib.mst_version.restype = ctypes.c_char_p
+    assert lib.mst_version().decode().count(".") == 2
+
+
+def test_argument_errors_without_gpu():
+    # validation happens on the host before any HIP call
+    from paper_1607_01477_amd import _lib
+    lib = _lib.load()
+    assert lib.mstrsm(-1, 1, None, 1, None, None, 1, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 1
+    assert lib.mstrsm(3, 2, None, 3, None, None, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 3
+    assert lib.mstrsm_adjoint(3, 2, None, 2, None, None, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 4
+    assert lib.mstrsm(0, 7, None, 1, None, None, 1, None, None) == _lib.MST_OK
+    assert lib.mst_status_string(_lib.MST_EARG).decode().startswith("MST_EARG")
