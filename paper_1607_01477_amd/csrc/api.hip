@@ -327,7 +327,7 @@ mst_status mstrsm(int m, int n, const void* U, int ldu, const void* shifts, void
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
-    if ((st = check_mat(U, ldu, m, m, 3, 4)) != MST_OK) return st;
+    if ((st = check_mat(U, ldu, m, n > 0 ? m : 0, 3, 4)) != MST_OK) return st;
     if (n > 0 && m > 0 && !shifts) return bad(5);
     if ((st = check_mat(B, ldb, m, n, 6, 7)) != MST_OK) return st;
     Opts o;
@@ -345,7 +345,7 @@ mst_status mstrsm_safe(int m, int n, const void* U, int ldu, const void* shifts,
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
-    if ((st = check_mat(U, ldu, m, m, 3, 4)) != MST_OK) return st;
+    if ((st = check_mat(U, ldu, m, n > 0 ? m : 0, 3, 4)) != MST_OK) return st;
     if (n > 0 && m > 0 && !shifts) return bad(5);
     if ((st = check_mat(B, ldb, m, n, 6, 7)) != MST_OK) return st;
     if (n > 0 && !scale) return bad(9);
@@ -375,7 +375,7 @@ mst_status mstrsm_adjoint(int m, int n, const void* U, int ldu, const void* shif
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
-    if ((st = check_mat(U, ldu, m, m, 3, 4)) != MST_OK) return st;
+    if ((st = check_mat(U, ldu, m, n > 0 ? m : 0, 3, 4)) != MST_OK) return st;
     if (n > 0 && m > 0 && !shifts) return bad(5);
     if ((st = check_mat(G, ldg, m, n, 6, 7)) != MST_OK) return st;
     Opts o;
@@ -425,7 +425,7 @@ mst_status mst_residual(int m, int n, const void* U, int ldu, const void* shifts
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
-    if ((st = check_mat(U, ldu, m, m, 3, 4)) != MST_OK) return st;
+    if ((st = check_mat(U, ldu, m, n > 0 ? m : 0, 3, 4)) != MST_OK) return st;
     if (n > 0 && m > 0 && !shifts) return bad(5);
     if ((st = check_mat(X, ldx, m, n, 6, 7)) != MST_OK) return st;
     if ((st = check_mat(B0, ldb0, m, n, 8, 9)) != MST_OK) return st;
@@ -471,7 +471,7 @@ mst_status mst_lanczos_sigma_min(int m, int N, const void* U, int ldu, const voi
     if (m < 1) return bad(1);
     if (N < 0) return bad(2);
     mst_status st;
-    if ((st = check_mat(U, ldu, m, m, 3, 4)) != MST_OK) return st;
+    if ((st = check_mat(U, ldu, m, N > 0 ? m : 0, 3, 4)) != MST_OK) return st;
     if (N > 0 && !z) return bad(5);
     if ((st = check_mat(V, ldv, m, N, 6, 7)) != MST_OK) return st;
     if (iters < 1 || iters > 64) return bad(8);

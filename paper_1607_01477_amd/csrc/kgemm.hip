@@ -25,9 +25,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Traits;
+// Output lane layout of the 16x16x4 products (measured on gfx950): lane l,
+// item v holds column l % 16 and row (l / 16) + 4 v for FP64, row 4 (l / 16) + v
+// for FP32.
 template <> struct Traits<double> {
     using C = zd;
     using V = v4d;
+    static __device__ inline int out_row(int lq, int v) { return lq + 4 * v; }
     static __device__ inline V mfma(double a, double b, V c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -35,6 +39,7 @@ template <> struct Traits<double> {
 template <> struct Traits<float> {
     using C = zf;
     using V = v4f;
+    static __device__ inline int out_row(int lq, int v) { return 4 * lq + v; }
     static __device__ inline V mfma(float a, float b, V c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -229,7 +234,7 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmArgs g) {
         }
     }
 
-    // epilogue: lane holds rows 4*(lane/16)+v, column lane%16 of each 16x16 tile
+    // epilogue: lane holds column lane%16 of each 16x16 tile, rows per Traits::out_row
     const int lr = lane & 15, lq = lane >> 4;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
@@ -251,7 +256,7 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmArgs g) {
         for (int i = 0; i < 2; ++i) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = r0 + wr * 32 + i * 16 + lq * 4 + v;
+                const int row = r0 + wr * 32 + i * 16 + Tr::out_row(lq, v);
                 if (row >= lim) continue;
                 const T ar = accR[i][j][v], ai = accI[i][j][v];
                 CT* p = &C[(long)col * g.ldc + row];

@@ -47,7 +47,7 @@ def check_plain(oracle_mod, U, lam, B, X, cols=None, resid_tol=1e-13):
     if cols is None:
         cols = np.arange(n)
     cols = np.asarray(cols)
-    Xo = oracle_mod.solve(U, lam, B[:, cols])
+    Xo = oracle_mod.solve(U, lam[cols], B[:, cols])
     rr = oracle_mod.relative_residual(U, lam, X, B, cols=cols)
     assert rr.max() <= resid_tol, rr.max()
     kap = kappa_cols(U, lam, cols[: min(len(cols), 64)]) if m <= 700 else None
