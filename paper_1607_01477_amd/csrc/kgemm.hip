@@ -4,30 +4,35 @@
 //
 // A complex product is four real MFMA products on the same operands:
 //   Re C += Re A Re B - Im A Im B,  Im C += Re A Im B + Im A Re B,
-// which is exactly the 8 real flops per complex multiply-add of the nominal
-// count (no extra flops, same rounding as a plain complex dot product up to
-// order). FP64 uses v_mfma_f64_16x16x4_f64, FP32 v_mfma_f32_16x16x4_f32.
+// exactly the 8 real flops per complex multiply-add of the nominal count.
+// FP64 uses v_mfma_f64_16x16x4_f64, FP32 v_mfma_f32_16x16x4_f32.
 //
-// Workgroup tile 64 x 64 complex, 4 wavefronts of 32 x 32, K staged through
-// LDS 16 complex at a time with double buffering. Operands are read straight
-// from the interleaved column-major storage, optionally conjugate-transposed,
-// so no realified copy of U or X is ever formed in HBM. Tiles are ordered in
-// groups of 8 row tiles and dealt out so that each XCD (own L2) receives a
-// contiguous range of tiles.
+// Workgroup tile 64 x 64 complex, 4 wavefronts of 32 x 32; K is staged
+// through LDS 16 complex at a time, double buffered, rows padded by one
+// element so that the transposing stores do not collide in one bank. Each
+// thread keeps its share of the next K-chunk in registers while the matrix
+// cores work on the current one. Interior tiles take an unmasked path. For
+// the substitution (C = C - A B) the accumulators start from C itself, loaded
+// before the K loop, so the C read latency hides behind the first chunks.
+// Operands are read straight from interleaved column-major storage,
+// optionally conjugate-transposed; no realified copy is formed in HBM. Tiles
+// are ordered in groups of 8 row tiles and dealt out so that each XCD (own L2)
+// receives a contiguous range of tiles.
 #include "common.h"
 
 namespace mst {
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256, PAD = 1;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-template <typename T> struct Traits;
 // Output lane layout of the 16x16x4 products (measured on gfx950): lane l,
-// item v holds column l % 16 and row (l / 16) + 4 v for FP64, row 4 (l / 16) + v
-// for FP32.
+// item v holds column l % 16 and row (l / 16) + 4 v for FP64, row
+// 4 (l / 16) + v for FP32. Inputs: A(i, k) at lane i + 16 k, B(k, j) at
+// lane j + 16 k for both.
+template <typename T> struct Traits;
 template <> struct Traits<double> {
     using C = zd;
     using V = v4d;
@@ -59,13 +64,19 @@ __device__ inline void tile_coords(int TM, int TN, int& tm, int& tn) {
     tn = in / gsz;
 }
 
+template <typename CT>
+__device__ inline CT cconj(CT v) {
+    v.im = -v.im;
+    return v;
+}
+
 template <typename T, bool A_CT, bool B_CT, int OP, bool SAFE, bool VARLEN>
-__global__ __launch_bounds__(NT) void k_gemm(GemmArgs g) {
+__global__ __launch_bounds__(NT, 2) void k_gemm(GemmArgs g) {
     using Tr = Traits<T>;
     using CT = typename Tr::C;
     using V = typename Tr::V;
-    __shared__ CT As[2][BK][BM];
-    __shared__ CT Bs[2][BK][BN];
+    __shared__ CT As[2][BK][BM + PAD];
+    __shared__ CT Bs[2][BK][BN + PAD];
 
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
     int tm, tn;
@@ -73,12 +84,12 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmArgs g) {
     const int r0 = tm * BM, c0 = tn * BN;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wr = wave >> 1, wc = wave & 1;
+    const int lr = lane & 15, lq = lane >> 4;
     const CT* __restrict__ A = (const CT*)g.A;
     const CT* __restrict__ B = (const CT*)g.B;
     CT* __restrict__ C = (CT*)g.C;
 
     if (OP == GOP_NEG_TRIU && r0 > c0 + BN - 1) {
-        // tile strictly below the diagonal: zeros
         for (int e = t; e < BM * BN; e += NT) {
             const int rr = r0 + (e % BM), cc = c0 + (e / BM);
             if (rr < g.M && cc < g.N) C[(long)cc * g.ldc + rr] = CT{0, 0};
@@ -94,162 +105,171 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmArgs g) {
         }
         if (!act) return;
     }
+    const bool full_mn = (r0 + BM <= g.M) && (c0 + BN <= g.N);
 
-    // K range (the residual's A is upper triangular: rows r0.. need k >= r0)
-    int kbeg = 0;
-    if (OP == GOP_RESID) kbeg = (r0 / BK) * BK;
-    const int nchunk = (g.K - kbeg + BK - 1) / BK;
-
-    // per-thread load coordinates (4 complex of A and 4 of B per chunk)
-    CT ra[4], rb[4];
-    auto load_chunk = [&](int k0) {
-        // ---- A
-        if (!A_CT) {
-            const int k = t >> 4, rr = (t & 15) * 4;
-            const int gk = k0 + k;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int gr = r0 + rr + e;
-                CT v{0, 0};
-                if (gk < g.K && gr < g.M) {
-                    if (OP != GOP_RESID || gr <= gk) v = A[(long)gk * g.lda + gr];
-                }
-                ra[e] = v;
-            }
-        } else {
-            const int rr = t >> 2, kk = (t & 3) * 4;
-            const int gr = r0 + rr;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int gk = k0 + kk + e;
-                CT v{0, 0};
-                if (gk < g.K && gr < g.M) {
-                    v = A[(long)gr * g.lda + gk];
-                    v.im = -v.im;
-                }
-                ra[e] = v;
-            }
-        }
-        // ---- B
-        if (!B_CT) {
-            const int cc = t >> 2, kk = (t & 3) * 4;
-            const int gc = c0 + cc;
-            int dsh = 0;
-            int lim = g.K;
-            if (gc < g.N) {
-                if (VARLEN) lim = min(lim, g.col_len[gc] - g.b_row0);
-                if (SAFE && g.kb != nullptr) {
-                    const int q = (g.b_row0 + k0 + kk) / g.nb;
-                    dsh = g.kb[(long)g.q_cur * g.n_kb + gc] - g.kb[(long)q * g.n_kb + gc];
-                }
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int gk = k0 + kk + e;
-                CT v{0, 0};
-                if (gk < lim && gc < g.N) {
-                    v = B[(long)gc * g.ldb + gk];
-                    if (SAFE) {
-                        v.re = ldexp(v.re, -dsh);
-                        v.im = ldexp(v.im, -dsh);
-                    }
-                }
-                rb[e] = v;
-            }
-        } else {
-            const int k = t >> 4, cc = (t & 15) * 4;
-            const int gk = k0 + k;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int gc = c0 + cc + e;
-                CT v{0, 0};
-                if (gk < g.K && gc < g.N) {
-                    v = B[(long)gk * g.ldb + gc];
-                    v.im = -v.im;
-                }
-                rb[e] = v;
-            }
-        }
-    };
-    auto store_chunk = [&](int buf) {
-        if (!A_CT) {
-            const int k = t >> 4, rr = (t & 15) * 4;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) As[buf][k][rr + e] = ra[e];
-        } else {
-            const int rr = t >> 2, kk = (t & 3) * 4;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) As[buf][kk + e][rr] = ra[e];
-        }
-        if (!B_CT) {
-            const int cc = t >> 2, kk = (t & 3) * 4;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) Bs[buf][kk + e][cc] = rb[e];
-        } else {
-            const int k = t >> 4, cc = (t & 15) * 4;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) Bs[buf][k][cc + e] = rb[e];
-        }
-    };
-
+    // ---- accumulators (start from C for the substitution)
     V accR[2][2], accI[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            accR[i][j] = V{0, 0, 0, 0};
-            accI[i][j] = V{0, 0, 0, 0};
-        }
-
-    if (nchunk > 0) {
-        load_chunk(kbeg);
-        store_chunk(0);
-        __syncthreads();
-        const int lr = lane & 15, lk = lane >> 4;
-        for (int kc = 0; kc < nchunk; ++kc) {
-            const int buf = kc & 1;
-            if (kc + 1 < nchunk) load_chunk(kbeg + (kc + 1) * BK);
-#pragma unroll
-            for (int ks = 0; ks < BK / 4; ++ks) {
-                const int kk = ks * 4 + lk;
-                CT a[2], b[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) a[i] = As[buf][kk][wr * 32 + i * 16 + lr];
-#pragma unroll
-                for (int j = 0; j < 2; ++j) b[j] = Bs[buf][kk][wc * 32 + j * 16 + lr];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const T nai = -a[i].im;
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        accR[i][j] = Tr::mfma(a[i].re, b[j].re, accR[i][j]);
-                        accR[i][j] = Tr::mfma(nai, b[j].im, accR[i][j]);
-                        accI[i][j] = Tr::mfma(a[i].re, b[j].im, accI[i][j]);
-                        accI[i][j] = Tr::mfma(a[i].im, b[j].re, accI[i][j]);
-                    }
-                }
-            }
-            if (kc + 1 < nchunk) store_chunk(buf ^ 1);
-            __syncthreads();
-        }
-    }
-
-    // epilogue: lane holds column lane%16 of each 16x16 tile, rows per Traits::out_row
-    const int lr = lane & 15, lq = lane >> 4;
+    int clim0 = g.M, clim1 = g.M;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int col = c0 + wc * 32 + j * 16 + lr;
-        if (col >= g.N) continue;
-        int csh = 0;
-        int lim = g.M;
-        if (OP == GOP_SUB) {
-            if (VARLEN) lim = min(lim, g.col_len[col] - g.c_row0);
+        int csh = 0, clim = g.M;
+        if (OP == GOP_SUB && col < g.N) {
+            if (VARLEN) clim = min(g.M, g.col_len[col] - g.c_row0);
             if (SAFE && g.kb != nullptr) {
                 const int kc = g.kb[(long)g.q_cur * g.n_kb + col];
                 const int kq = (g.q_c >= 0) ? g.kb[(long)g.q_c * g.n_kb + col] : 0;
                 csh = kc - kq;
             }
         }
+        if (j == 0) clim0 = clim; else clim1 = clim;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                accR[i][j][v] = 0;
+                accI[i][j][v] = 0;
+            }
+            if (OP == GOP_SUB) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = r0 + wr * 32 + i * 16 + Tr::out_row(lq, v);
+                    if (col < g.N && row < clim) {
+                        CT c = C[(long)col * g.ldc + row];
+                        if (SAFE) {
+                            c.re = ldexp(c.re, -csh);
+                            c.im = ldexp(c.im, -csh);
+                        }
+                        accR[i][j][v] = c.re;
+                        accI[i][j][v] = c.im;
+                    }
+                }
+            }
+        }
+    }
+
+    // K range (the residual's A is upper triangular: rows r0.. need k >= r0)
+    int kbeg = 0;
+    if (OP == GOP_RESID) kbeg = (r0 / BK) * BK;
+    const int nchunk = (g.K - kbeg + BK - 1) / BK;
+
+    // per-thread staging coordinates
+    //   A, plain:   k = t/16, rows 4*(t%16)..+3      A, conj-T: row = t/4, k = 4*(t%4)..+3
+    //   B, plain:   col = t/4, k = 4*(t%4)..+3       B, conj-T: k = t/16, cols 4*(t%16)..+3
+    const int a_k = A_CT ? 4 * (t & 3) : (t >> 4);
+    const int a_r = A_CT ? (t >> 2) : 4 * (t & 15);
+    const int b_k = B_CT ? (t >> 4) : 4 * (t & 3);
+    const int b_c = B_CT ? 4 * (t & 15) : (t >> 2);
+    int b_lim = g.K;
+    if (VARLEN && !B_CT && c0 + b_c < g.N) b_lim = min(b_lim, g.col_len[c0 + b_c] - g.b_row0);
+    CT ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+
+#define MST_LOAD_A(E, R)                                                                   \
+    {                                                                                      \
+        const int gk = k0 + a_k + (A_CT ? E : 0), gr = r0 + a_r + (A_CT ? 0 : E);          \
+        R = CT{0, 0};                                                                      \
+        if (fast || (gk < g.K && gr < g.M && (OP != GOP_RESID || gr <= gk))) {             \
+            if (A_CT) R = cconj(A[(long)gr * g.lda + gk]);                                 \
+            else R = A[(long)gk * g.lda + gr];                                             \
+        }                                                                                  \
+    }
+#define MST_LOAD_B(E, R)                                                                   \
+    {                                                                                      \
+        const int gk = k0 + b_k + (B_CT ? 0 : E), gc = c0 + b_c + (B_CT ? E : 0);          \
+        R = CT{0, 0};                                                                      \
+        if (B_CT) {                                                                        \
+            if (fast || (gk < g.K && gc < g.N)) R = cconj(B[(long)gk * g.ldb + gc]);       \
+        } else if (fast || (gk < b_lim && gc < g.N)) {                                     \
+            R = B[(long)gc * g.ldb + gk];                                                  \
+            if (SAFE) {                                                                    \
+                R.re = ldexp(R.re, -b_dsh);                                                \
+                R.im = ldexp(R.im, -b_dsh);                                                \
+            }                                                                              \
+        }                                                                                  \
+    }
+#define MST_LOAD_CHUNK(K0)                                                                 \
+    {                                                                                      \
+        const int k0 = (K0);                                                               \
+        const bool fast = full_mn && (k0 + BK <= g.K) && !VARLEN && !SAFE &&               \
+                          (OP != GOP_RESID || k0 >= r0 + BM);                              \
+        int b_dsh = 0;                                                                     \
+        if (SAFE && !B_CT && g.kb != nullptr && c0 + b_c < g.N) {                          \
+            const int q = (g.b_row0 + k0 + b_k) / g.nb;                                    \
+            b_dsh = g.kb[(long)g.q_cur * g.n_kb + c0 + b_c] -                              \
+                    g.kb[(long)q * g.n_kb + c0 + b_c];                                     \
+        }                                                                                  \
+        (void)b_dsh;                                                                       \
+        MST_LOAD_A(0, ra0) MST_LOAD_A(1, ra1) MST_LOAD_A(2, ra2) MST_LOAD_A(3, ra3)        \
+        MST_LOAD_B(0, rb0) MST_LOAD_B(1, rb1) MST_LOAD_B(2, rb2) MST_LOAD_B(3, rb3)        \
+    }
+#define MST_STORE_CHUNK(BUF)                                                               \
+    {                                                                                      \
+        const int bf = (BUF);                                                              \
+        if (!A_CT) {                                                                       \
+            As[bf][a_k][a_r + 0] = ra0; As[bf][a_k][a_r + 1] = ra1;                        \
+            As[bf][a_k][a_r + 2] = ra2; As[bf][a_k][a_r + 3] = ra3;                        \
+        } else {                                                                           \
+            As[bf][a_k + 0][a_r] = ra0; As[bf][a_k + 1][a_r] = ra1;                        \
+            As[bf][a_k + 2][a_r] = ra2; As[bf][a_k + 3][a_r] = ra3;                        \
+        }                                                                                  \
+        if (!B_CT) {                                                                       \
+            Bs[bf][b_k + 0][b_c] = rb0; Bs[bf][b_k + 1][b_c] = rb1;                        \
+            Bs[bf][b_k + 2][b_c] = rb2; Bs[bf][b_k + 3][b_c] = rb3;                        \
+        } else {                                                                           \
+            Bs[bf][b_k][b_c + 0] = rb0; Bs[bf][b_k][b_c + 1] = rb1;                        \
+            Bs[bf][b_k][b_c + 2] = rb2; Bs[bf][b_k][b_c + 3] = rb3;                        \
+        }                                                                                  \
+    }
+
+    if (nchunk > 0) {
+        MST_LOAD_CHUNK(kbeg)
+        MST_STORE_CHUNK(0)
+        __syncthreads();
+        // substitution: the accumulators start at C, so A B is subtracted (A negated)
+        const T s = (OP == GOP_SUB) ? T(-1) : T(1);
+        for (int kc = 0; kc < nchunk; ++kc) {
+            const int buf = kc & 1;
+            if (kc + 1 < nchunk) MST_LOAD_CHUNK(kbeg + (kc + 1) * BK)
+#pragma unroll
+            for (int ks = 0; ks < BK / 4; ++ks) {
+                const int kk = ks * 4 + lq;
+                const CT a0 = As[buf][kk][wr * 32 + lr];
+                const CT a1 = As[buf][kk][wr * 32 + 16 + lr];
+                const CT b0 = Bs[buf][kk][wc * 32 + lr];
+                const CT b1 = Bs[buf][kk][wc * 32 + 16 + lr];
+                const T a0r = s * a0.re, a0i = s * a0.im, a1r = s * a1.re, a1i = s * a1.im;
+                accR[0][0] = Tr::mfma(a0r, b0.re, accR[0][0]);
+                accR[0][1] = Tr::mfma(a0r, b1.re, accR[0][1]);
+                accR[1][0] = Tr::mfma(a1r, b0.re, accR[1][0]);
+                accR[1][1] = Tr::mfma(a1r, b1.re, accR[1][1]);
+                accI[0][0] = Tr::mfma(a0r, b0.im, accI[0][0]);
+                accI[0][1] = Tr::mfma(a0r, b1.im, accI[0][1]);
+                accI[1][0] = Tr::mfma(a1r, b0.im, accI[1][0]);
+                accI[1][1] = Tr::mfma(a1r, b1.im, accI[1][1]);
+                accR[0][0] = Tr::mfma(-a0i, b0.im, accR[0][0]);
+                accR[0][1] = Tr::mfma(-a0i, b1.im, accR[0][1]);
+                accR[1][0] = Tr::mfma(-a1i, b0.im, accR[1][0]);
+                accR[1][1] = Tr::mfma(-a1i, b1.im, accR[1][1]);
+                accI[0][0] = Tr::mfma(a0i, b0.re, accI[0][0]);
+                accI[0][1] = Tr::mfma(a0i, b1.re, accI[0][1]);
+                accI[1][0] = Tr::mfma(a1i, b0.re, accI[1][0]);
+                accI[1][1] = Tr::mfma(a1i, b1.re, accI[1][1]);
+            }
+            if (kc + 1 < nchunk) MST_STORE_CHUNK(buf ^ 1)
+            __syncthreads();
+        }
+    }
+#undef MST_LOAD_A
+#undef MST_LOAD_B
+#undef MST_LOAD_CHUNK
+#undef MST_STORE_CHUNK
+
+    // ---- epilogue
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = c0 + wc * 32 + j * 16 + lr;
+        if (col >= g.N) continue;
+        const int clim = (j == 0) ? clim0 : clim1;
         CT lamc{0, 0};
         if (OP == GOP_RESID) lamc = CT{(T)g.lam[col].re, (T)g.lam[col].im};
 #pragma unroll
@@ -257,16 +277,12 @@ __global__ __launch_bounds__(NT) void k_gemm(GemmArgs g) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = r0 + wr * 32 + i * 16 + Tr::out_row(lq, v);
-                if (row >= lim) continue;
+                if (!full_mn && row >= g.M) continue;
                 const T ar = accR[i][j][v], ai = accI[i][j][v];
                 CT* p = &C[(long)col * g.ldc + row];
                 if (OP == GOP_SUB) {
-                    CT c = *p;
-                    if (SAFE) {
-                        c.re = ldexp(c.re, -csh);
-                        c.im = ldexp(c.im, -csh);
-                    }
-                    *p = CT{c.re - ar, c.im - ai};
+                    if (VARLEN && row >= clim) continue;
+                    *p = CT{ar, ai};
                 } else if (OP == GOP_RESID) {
                     const CT b0 = ((const CT*)g.B0)[(long)col * g.ldb0 + row];
                     const CT x = B[(long)col * g.ldb + row];
