@@ -55,7 +55,11 @@ typedef struct {
                           values force rescaling at small sizes (testing). Range 8..1000. */
     int force_phase2;  /* accepted for interface compatibility: the GPU safe solve always
                           runs the checked back substitution, which gives the same result */
-    int reserved[4];
+    int fuse_blocks;   /* 0 (default): an outer block of at most 256 rows is solved by one
+                          fused kernel (diagonal blocks plus the substitution between them);
+                          -1: one kernel per diagonal block plus separate GEMMs (same
+                          arithmetic, kept for testing and for outer_nb > 256). */
+    int reserved[3];
 } mst_opts;
 
 /*

@@ -26,7 +26,8 @@ PROF_KINDS = ["gemm_f64", "gemm_f32", "diag", "resid", "aux"]
 class MstOpts(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int), ("outer_nb", ctypes.c_int), ("precision", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("omega_log2", ctypes.c_int),
-                ("force_phase2", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("force_phase2", ctypes.c_int), ("fuse_blocks", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
 
 
 class MstError(RuntimeError):

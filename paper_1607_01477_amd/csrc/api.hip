@@ -85,6 +85,7 @@ double gemm_flops(const GemmArgs& g) { return 8.0 * g.M * (double)g.N * g.K; }
 
 struct Opts {
     int nb = 64, outer = 256, precision = 0, sweeps = 2, omega_log2 = 960;
+    bool fuse = true;
 };
 
 // position of opt in the caller's argument list, for error reporting
@@ -102,6 +103,8 @@ mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
     if (r.sweeps < 1 || r.sweeps > 3) return bad(pos);
     if (o->omega_log2) r.omega_log2 = o->omega_log2;
     if (r.omega_log2 < 8 || r.omega_log2 > 1000) return bad(pos);
+    if (o->fuse_blocks != 0 && o->fuse_blocks != -1) return bad(pos);
+    r.fuse = o->fuse_blocks == 0;
     return MST_OK;
 }
 
@@ -138,9 +141,27 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
     const int nblk = (m + nb - 1) / nb;
     const int nob = (nblk + P - 1) / P;
     const bool mixed = W32 != nullptr;
+    const bool fused = o.fuse && o.outer <= block_rows_max();
     for (int ob = nob - 1; ob >= 0; --ob) {
         const int qa = ob * P, qb = (qa + P < nblk ? qa + P : nblk) - 1;
-        for (int q = qb; q >= qa; --q) {
+        if (fused) {
+            BlockArgs b{};
+            b.m = m; b.n = n; b.nb = nb; b.qa = qa; b.iS = qa * nb;
+            b.rows = (((qb + 1) * nb < m) ? (qb + 1) * nb : m) - qa * nb;
+            b.U = U; b.ldu = ldu; b.lam = lam; b.B = B; b.ldb = ldb;
+            b.b32 = mixed ? W32 : nullptr; b.ldb32 = ldw;
+            b.col_len = col_len;
+            if (safe) {
+                b.safe = *safe;
+                b.use_safe = 1;
+            } else {
+                b.safe.omega_log2 = o.omega_log2;
+            }
+            const double fl = 4.0 * b.rows * (double)b.rows * n;
+            hipError_t e = timed(MST_PROF_DIAG, fl, s, [&] { return launch_block(false, b, s); });
+            if (e != hipSuccess) return e;
+        }
+        for (int q = qb; q >= qa && !fused; --q) {
             const int i0 = q * nb, bs = (m - i0 < nb) ? m - i0 : nb;
             DiagArgs d{};
             d.m = m; d.n = n; d.i0 = i0; d.bs = bs; d.q = q;
@@ -211,10 +232,20 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
     const int nb = o.nb, P = o.outer / o.nb;
     const int nblk = (m + nb - 1) / nb;
     const int nob = (nblk + P - 1) / P;
+    const bool fused = o.fuse && o.outer <= block_rows_max();
     for (int ob = 0; ob < nob; ++ob) {
         const int qa = ob * P, qb = (qa + P < nblk ? qa + P : nblk) - 1;
         const int end = ((qb + 1) * nb < m) ? (qb + 1) * nb : m;
-        for (int q = qa; q <= qb; ++q) {
+        if (fused) {
+            BlockArgs b{};
+            b.m = m; b.n = n; b.nb = nb; b.qa = qa; b.iS = qa * nb; b.rows = end - qa * nb;
+            b.U = U; b.ldu = ldu; b.lam = lam; b.B = G; b.ldb = ldg;
+            b.safe.omega_log2 = o.omega_log2;
+            const double fl = 4.0 * b.rows * (double)b.rows * n;
+            hipError_t e = timed(MST_PROF_DIAG, fl, s, [&] { return launch_block(true, b, s); });
+            if (e != hipSuccess) return e;
+        }
+        for (int q = qa; q <= qb && !fused; ++q) {
             const int i0 = q * nb, bs = (m - i0 < nb) ? m - i0 : nb;
             const int i1 = i0 + bs;
             DiagArgs d{};

@@ -39,6 +39,22 @@ struct DiagArgs {
 };
 hipError_t launch_diag(int nb, bool adjoint, const DiagArgs& a, hipStream_t s);
 
+// Whole outer block [iS, iS+rows) (rows <= block_rows_max(), iS a multiple of nb,
+// first diagonal block index qa) for all n shifts: the diagonal blocks in
+// order and the substitution between them, in one launch.
+struct BlockArgs {
+    int m, n, nb, qa, iS, rows;
+    const zd* U; long ldu;
+    const zd* lam;
+    zd* B; long ldb;
+    zf* b32; long ldb32;
+    const int* col_len;
+    SafeState safe;
+    int use_safe;
+};
+int block_rows_max();
+hipError_t launch_block(bool adjoint, const BlockArgs& a, hipStream_t s);
+
 // ---------------------------------------------------------------- MFMA GEMM
 // C(M x N) <- epilogue(acc), acc = A(M x K) * B(K x N), complex.
 enum GemmOp : int {

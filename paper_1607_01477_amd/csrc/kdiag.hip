@@ -1,26 +1,39 @@
 // Diagonal-block step of the blocked multi-shift solve (the xTRSV call inside
 // Alg 3 / Alg 5 of Moon & Poulson, arXiv 1607.01477), for gfx950.
 //
-// One workgroup stages the nb x nb diagonal block of U in LDS once and every
-// wavefront of it solves a group of shifts against it: lane r of a group of nb
-// lanes owns row r of the block, the pivot U(r,r) - lambda_j is formed on the
-// fly, and each of the nb sequential steps broadcasts the new solution entry
-// to the group (v_readlane for nb = 64, ds_bpermute otherwise) followed by one
-// complex multiply-add per lane. Several shifts are interleaved per wavefront
-// to hide the dependency latency of the step chain.
+// Back substitution on one nb x nb diagonal block: a workgroup stages the block
+// of U in LDS once and every wavefront solves a group of shifts against it.
+// Lane r of a group of nb lanes owns row r of the block, the pivot
+// U(r,r) - lambda_j is formed on the fly, and each of the nb sequential steps
+// broadcasts the new solution entry to the group (v_readlane for nb = 64,
+// ds_bpermute otherwise) followed by one complex multiply-add per lane (the
+// staged block is zero outside the rows a step updates, so no lane masking).
+// Several shifts are interleaved per wavefront to hide the step latency.
 //
 // Safe variant: Alg 4 phase 2 (checked back substitution) on the block, then
-// the column growth bound and rescaling decision of Alg 5. All scale factors
-// are powers of two 2^-k, tracked as integer exponents; rows outside the block
-// are rescaled lazily (in the substitution GEMM epilogue and a final pass).
-// The fast path of Alg 4 (phase 1) is not used: when it would apply, phase 2
-// performs no rescaling and computes the same result.
+// the column growth bound and rescaling decision of Alg 5. Scale factors are
+// powers of two 2^-k tracked as integer exponents; rows outside the block are
+// rescaled lazily (by the consumer of the block and a final pass). The fast
+// path of Alg 4 (phase 1) is not used: where it applies, phase 2 performs no
+// rescaling and computes the same result.
+//
+// Two kernels use this step:
+//   k_diag  - one diagonal block for all shifts (the paper's loop order);
+//   k_block - a whole outer block of up to 256 rows for 16 shifts per
+//             workgroup: the right-hand sides of the outer block stay in LDS,
+//             each diagonal block is solved as above and the rows of the
+//             outer block still to be solved are updated right away with
+//             FP64 MFMA products (U panel from L2, solution from LDS). This
+//             fuses nb-row diagonal solves and their short substitution GEMMs
+//             into one launch per outer block.
 #include "common.h"
 
 namespace mst {
 namespace {
 
 constexpr int kWG = 256;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ inline double cabs1(double re, double im) { return fabs(re) + fabs(im); }
 
@@ -75,126 +88,88 @@ __device__ inline double group_max(double v) {
     return v;
 }
 
-template <int NB, int SPW, bool ADJ, bool SAFE, bool MIXED, bool VARLEN>
-__global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
-    __shared__ zd Us[NB * NB];
-    const int bs = a.bs, i0 = a.i0;
-    // Us[i*NB + r]: coefficient of unknown i in row r of the block system
-    //   forward: U(i0+r, i0+i) for r <= i;  adjoint: conj(U(i0+i, i0+r)) for r >= i
-    // all loads of this thread are issued before any LDS store, so their
-    // latencies overlap
+// Us[i*NB + r]: coefficient of unknown i in row r of the block system, zero on
+// and outside the triangle that the substitution uses:
+//   forward: U(i0+r, i0+i) for r < i;  adjoint: conj(U(i0+i, i0+r)) for r > i.
+// Ud[r]: the diagonal U(i0+r, i0+r) (conjugated for the adjoint).
+// All loads of a thread are issued before its LDS stores so their latencies overlap.
+template <int NB, bool ADJ>
+__device__ inline void stage_diag(zd* Us, zd* Ud, const zd* U, long ldu, int i0, int bs) {
     constexpr int PER = (NB * NB) / kWG;
-    zd stage[PER];
+    zd st[PER];
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const int t = threadIdx.x + e * kWG;
         const int c = t / NB, rr = t - c * NB;
-        stage[e] = zd{0.0, 0.0};
-        if (rr <= c && c < bs) stage[e] = a.U[(long)(i0 + c) * a.ldu + i0 + rr];
+        st[e] = zd{0.0, 0.0};
+        if (rr <= c && c < bs) st[e] = U[(long)(i0 + c) * ldu + i0 + rr];
     }
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const int t = threadIdx.x + e * kWG;
         const int c = t / NB, rr = t - c * NB;
-        if (!ADJ) {
-            Us[c * NB + rr] = stage[e];
+        const zd v = ADJ ? zd{st[e].re, -st[e].im} : st[e];
+        if (rr == c) {
+            Ud[rr] = v;
+            Us[c * NB + rr] = zd{0.0, 0.0};
+        } else if (!ADJ) {
+            Us[c * NB + rr] = v;
         } else {
-            Us[rr * NB + c] = zd{stage[e].re, -stage[e].im};
+            Us[rr * NB + c] = v;
         }
     }
-    __syncthreads();
+}
 
-    constexpr int G = 64 / NB;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int grp = lane / NB, r = lane - grp * NB, base = grp * NB;
-    const int jw = (blockIdx.x * (kWG / 64) + wave) * (G * SPW);
-    if (jw >= a.n) return;
+// Per-wavefront solve of SPW interleaved shifts (per group of NB lanes) against
+// the staged block. b holds the right-hand side rows (lane r = row r) and
+// receives the solution; kblk the block's scale exponent (safe variant).
+template <int NB, int SPW, bool ADJ, bool SAFE>
+struct BlockSolve {
+    double br[SPW], bi[SPW], pr[SPW], pi[SPW], cdl[SPW], Gs[SPW], Ms[SPW];
+    int pe[SPW], kblk[SPW];
 
-    const int w = a.safe.omega_log2;
-    const double omega = ldexp(1.0, w);
-    const double delta = SAFE ? *a.safe.delta : 0.0;
-    const double cn_l = (SAFE && r < bs) ? a.safe.cn_in[i0 + r] : 0.0;
-
-    double br[SPW], bi[SPW], pr[SPW], pi[SPW], cdl[SPW];
-    int pe[SPW], jj[SPW], Lr[SPW];
-    double Gs[SPW], Ms[SPW];
-    int kblk[SPW];
-    bool any_active = false;
+    // pivot d = U(r,r) - lambda (forward) or its conjugate (adjoint); exact
+    // zeros replaced by delta in the safe variant
+    __device__ __forceinline__ void pivots(const zd* Ud, int r, int bs, const zd (&lam)[SPW],
+                                           const bool (&jv)[SPW], double delta) {
 #pragma unroll
-    for (int s = 0; s < SPW; ++s) {
-        const int j = jw + s * G + grp;
-        jj[s] = j;
-        int L = a.m;
-        if (VARLEN && j < a.n) {
-            L = a.col_len[j];
-            L = L < 0 ? 0 : (L > a.m ? a.m : L);
-        }
-        Lr[s] = (j < a.n) ? L : 0;
-        const bool rv = (r < bs) && (i0 + r < Lr[s]);
-        any_active |= (j < a.n) && (i0 < Lr[s]);
-        double xr = 0.0, xi = 0.0;
-        if (rv) {
-            if (MIXED) {
-                const zf v = a.b32[(long)j * a.ldb32 + i0 + r];
-                xr = v.re;
-                xi = v.im;
+        for (int s = 0; s < SPW; ++s) {
+            double dr = 1.0, di = 0.0;
+            if (r < bs && jv[s]) {
+                const zd u = Ud[r];
+                dr = u.re - lam[s].re;
+                di = ADJ ? (u.im + lam[s].im) : (u.im - lam[s].im);
+                if (SAFE && dr == 0.0 && di == 0.0) dr = delta;
+            }
+            cdl[s] = cabs1(dr, di);
+            // scaled reciprocal: d = 2^e d', 1/d = 2^-e conj(d')/|d'|^2
+            const double am = fmax(fabs(dr), fabs(di));
+            const int e = (am > 0.0) ? ilogb(am) : 0;
+            const double sr = ldexp(dr, -e), si = ldexp(di, -e);
+            const double den = sr * sr + si * si;
+            if (SAFE) {
+                pr[s] = sr / den;
+                pi[s] = -si / den;
+                pe[s] = e;
             } else {
-                const zd v = a.B[(long)j * a.ldb + i0 + r];
-                xr = v.re;
-                xi = v.im;
+                // plain solve: 1/d itself (overflows only for |d| < 2^-1022, a
+                // singular system for this solver)
+                pr[s] = ldexp(sr / den, -e);
+                pi[s] = ldexp(-si / den, -e);
+                pe[s] = 0;
             }
+            kblk[s] = 0;
+            Ms[s] = 0.0;
+            Gs[s] = 0.0;
         }
-        br[s] = xr;
-        bi[s] = xi;
-        // pivot d = U(r,r) - lambda (forward) or its conjugate (adjoint)
-        double dr = 1.0, di = 0.0;
-        if (r < bs && j < a.n) {
-            const zd l = a.lam[j];
-            const zd u = Us[r * NB + r];
-            dr = u.re - l.re;
-            di = ADJ ? (u.im + l.im) : (u.im - l.im);
-            if (SAFE && dr == 0.0 && di == 0.0) dr = delta;
-        }
-        cdl[s] = cabs1(dr, di);
-        // scaled reciprocal: d = 2^e d', 1/d = 2^-e conj(d')/|d'|^2
-        const double am = fmax(fabs(dr), fabs(di));
-        const int e = (am > 0.0) ? ilogb(am) : 0;
-        const double sr = ldexp(dr, -e), si = ldexp(di, -e);
-        const double den = sr * sr + si * si;
         if (SAFE) {
-            pr[s] = sr / den;
-            pi[s] = -si / den;
-            pe[s] = e;
-        } else {
-            // plain solve: 1/d itself (overflows only for |d| < 2^-1022, a
-            // singular system for this solver)
-            pr[s] = ldexp(sr / den, -e);
-            pi[s] = ldexp(-si / den, -e);
-            pe[s] = 0;
-        }
-        kblk[s] = 0;
-        Ms[s] = 0.0;
-        Gs[s] = 0.0;
-    }
-
-    if (SAFE && VARLEN) {
-        // every shift of this wavefront has all its rows above the block: nothing
-        // to solve; the exponent record of the block is the current exponent
-        if (!__any(any_active)) {
 #pragma unroll
-            for (int s = 0; s < SPW; ++s) {
-                const int j = jj[s];
-                if (r == 0 && j < a.n) a.safe.kb[(long)a.q * a.n + j] = a.safe.kcur[j];
-            }
-            return;
+            for (int s = 0; s < SPW; ++s) Gs[s] = group_max<NB>(cabs1(br[s], bi[s]));
         }
     }
-    if (SAFE) {
-#pragma unroll
-        for (int s = 0; s < SPW; ++s) Gs[s] = group_max<NB>(cabs1(br[s], bi[s]));
-    }
 
-    auto step = [&](int i) {
+    __device__ __forceinline__ void step(const zd* Us, int i, int r, int base, double cn_l, int w,
+                                         double omega) {
         const zd u = Us[i * NB + r];
         const double cni = SAFE ? bcast<NB>(cn_l, i, base) : 0.0;
 #pragma unroll
@@ -218,8 +193,9 @@ __global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
                 }
                 Ms[s] = M;
             }
-            double xl_r = br[s] * pr[s] - bi[s] * pi[s];
-            double xl_i = br[s] * pi[s] + bi[s] * pr[s];
+            // every lane forms its own quotient b_r / d_r; lane i's is x_i
+            double xl_r = fma(br[s], pr[s], -bi[s] * pi[s]);
+            double xl_i = fma(br[s], pi[s], bi[s] * pr[s]);
             if (SAFE) {
                 xl_r = ldexp(xl_r, -pe[s]);
                 xl_i = ldexp(xl_i, -pe[s]);
@@ -232,48 +208,126 @@ __global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
                 if (kk > 0) {
                     br[s] = ldexp(br[s], -kk);
                     bi[s] = ldexp(bi[s], -kk);
+                    xl_r = ldexp(xl_r, -kk);
+                    xl_i = ldexp(xl_i, -kk);
                     xr = ldexp(xr, -kk);
                     xi = ldexp(xi, -kk);
                     kblk[s] += kk;
                 }
                 Gs[s] = Gn;
             }
-            const double nr = br[s] - (u.re * xr - u.im * xi);
-            const double ni = bi[s] - (u.re * xi + u.im * xr);
-            const bool upd = ADJ ? (r > i) : (r < i);
-            br[s] = upd ? nr : (r == i ? xr : br[s]);
-            bi[s] = upd ? ni : (r == i ? xi : bi[s]);
+            // u is zero outside the rows still to be updated (and on the pivot row)
+            const double nr = fma(-u.re, xr, fma(u.im, xi, br[s]));
+            const double ni = fma(-u.re, xi, fma(-u.im, xr, bi[s]));
+            br[s] = (r == i) ? xl_r : nr;
+            bi[s] = (r == i) ? xl_i : ni;
         }
-    };
-    if (!ADJ) {
-        for (int i = bs - 1; i >= 0; --i) step(i);
-    } else {
-        for (int i = 0; i < bs; ++i) step(i);
     }
+
+    __device__ __forceinline__ void run(const zd* Us, int bs, int r, int base, double cn_l, int w,
+                                        double omega) {
+        if (!ADJ) {
+            for (int i = bs - 1; i >= 0; --i) step(Us, i, r, base, cn_l, w, omega);
+        } else {
+            for (int i = 0; i < bs; ++i) step(Us, i, r, base, cn_l, w, omega);
+        }
+    }
+
+    // Column bound of Alg 5 for slot s after the block: G(j) = 2^-kblk G(j) +
+    // above_sum * max cabs1 x; rescale when it reaches Omega. Returns the total
+    // exponent change of the column in this block. All lanes of the group call it.
+    __device__ __forceinline__ int column_bound(int s, bool active, double asum, double* G, int w,
+                                                double omega) {
+        const double xn = group_max<NB>(cabs1(br[s], bi[s]));
+        if (!active) return 0;
+        double Gn;
+        const int k2 = bound_add(ldexp(*G, -kblk[s]), asum, xn, w, omega, &Gn);
+        if (k2 > 0) {
+            br[s] = ldexp(br[s], -k2);
+            bi[s] = ldexp(bi[s], -k2);
+        }
+        Gs[s] = Gn;   // new G(j), returned to the caller through Gs
+        return kblk[s] + k2;
+    }
+};
+
+template <int NB, int SPW, bool ADJ, bool SAFE, bool MIXED, bool VARLEN>
+__global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
+    __shared__ zd Us[NB * NB];
+    __shared__ zd Ud[NB];
+    const int bs = a.bs, i0 = a.i0;
+    stage_diag<NB, ADJ>(Us, Ud, a.U, a.ldu, i0, bs);
+    __syncthreads();
+
+    constexpr int G = 64 / NB;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane / NB, r = lane - grp * NB, base = grp * NB;
+    const int jw = (blockIdx.x * (kWG / 64) + wave) * (G * SPW);
+    if (jw >= a.n) return;
+
+    const int w = a.safe.omega_log2;
+    const double omega = ldexp(1.0, w);
+    const double delta = SAFE ? *a.safe.delta : 0.0;
+    const double cn_l = (SAFE && r < bs) ? a.safe.cn_in[i0 + r] : 0.0;
+
+    BlockSolve<NB, SPW, ADJ, SAFE> S;
+    int jj[SPW], Lr[SPW];
+    zd lam[SPW];
+    bool jv[SPW];
+    bool any_active = false;
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+        const int j = jw + s * G + grp;
+        jj[s] = j;
+        jv[s] = j < a.n;
+        int L = a.m;
+        if (VARLEN && jv[s]) {
+            L = a.col_len[j];
+            L = L < 0 ? 0 : (L > a.m ? a.m : L);
+        }
+        Lr[s] = jv[s] ? L : 0;
+        lam[s] = jv[s] ? a.lam[j] : zd{0.0, 0.0};
+        any_active |= jv[s] && (i0 < Lr[s]);
+        double xr = 0.0, xi = 0.0;
+        if (r < bs && i0 + r < Lr[s]) {
+            if (MIXED) {
+                const zf v = a.b32[(long)j * a.ldb32 + i0 + r];
+                xr = v.re;
+                xi = v.im;
+            } else {
+                const zd v = a.B[(long)j * a.ldb + i0 + r];
+                xr = v.re;
+                xi = v.im;
+            }
+        }
+        S.br[s] = xr;
+        S.bi[s] = xi;
+    }
+    if (SAFE && VARLEN && !__any(any_active)) {
+        // every shift of this wavefront has all its rows above the block:
+        // nothing to solve; the exponent record of the block is the current one
+#pragma unroll
+        for (int s = 0; s < SPW; ++s)
+            if (r == 0 && jv[s]) a.safe.kb[(long)a.q * a.n + jj[s]] = a.safe.kcur[jj[s]];
+        return;
+    }
+    S.pivots(Ud, r, bs, lam, jv, delta);
+    S.run(Us, bs, r, base, cn_l, w, omega);
 
     if (SAFE) {
         const double asum = a.safe.above_sum[a.q];
 #pragma unroll
         for (int s = 0; s < SPW; ++s) {
             const int j = jj[s];
-            const double xn = group_max<NB>(cabs1(br[s], bi[s]));
-            if (j >= a.n) continue;
-            if (i0 >= Lr[s]) {
-                // the block lies below the column's rows: skipped, state unchanged
-                if (r == 0) a.safe.kb[(long)a.q * a.n + j] = a.safe.kcur[j];
-                continue;
-            }
-            double Gj = ldexp(a.safe.G[j], -kblk[s]);
-            double Gn;
-            const int k2 = bound_add(Gj, asum, xn, w, omega, &Gn);
-            if (k2 > 0) {
-                br[s] = ldexp(br[s], -k2);
-                bi[s] = ldexp(bi[s], -k2);
-            }
-            if (r == 0) {
-                const int kc = a.safe.kcur[j] + kblk[s] + k2;
-                a.safe.G[j] = Gn;
-                a.safe.kcur[j] = kc;
+            const bool active = jv[s] && (i0 < Lr[s]);
+            double Gj = jv[s] ? a.safe.G[j] : 0.0;
+            const int dk = S.column_bound(s, active, asum, &Gj, w, omega);
+            if (r == 0 && jv[s]) {
+                const int kc = a.safe.kcur[j] + dk;
+                if (active) {
+                    a.safe.G[j] = S.Gs[s];
+                    a.safe.kcur[j] = kc;
+                }
                 a.safe.kb[(long)a.q * a.n + j] = kc;
             }
         }
@@ -281,9 +335,224 @@ __global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
         const int j = jj[s];
-        if (j < a.n && r < bs && i0 + r < Lr[s]) {
-            a.B[(long)j * a.ldb + i0 + r] = zd{br[s], bi[s]};
-            if (MIXED) a.b32[(long)j * a.ldb32 + i0 + r] = zf{(float)br[s], (float)bi[s]};
+        if (jv[s] && r < bs && i0 + r < Lr[s]) {
+            a.B[(long)j * a.ldb + i0 + r] = zd{S.br[s], S.bi[s]};
+            if (MIXED) a.b32[(long)j * a.ldb32 + i0 + r] = zf{(float)S.br[s], (float)S.bi[s]};
+        }
+    }
+}
+
+// ---------------------------------------------------------------- fused outer block
+constexpr int kRowsMax = 256;          // rows of one outer block
+constexpr int kCols = 16;              // shifts per workgroup (4 per wavefront)
+constexpr int kSP = kRowsMax + 1;      // padded LDS column stride (bank spread)
+
+template <int NB, bool ADJ, bool SAFE, bool MIXED, bool VARLEN>
+__global__ __launch_bounds__(kWG) void k_block(BlockArgs a) {
+    constexpr int G = 64 / NB, SPW = 4 / G;
+    __shared__ zd Bl[kCols * kSP];
+    __shared__ zd Us[NB * NB];
+    __shared__ zd Ud[NB];
+    __shared__ double Gl[kCols];
+    __shared__ int kcl[kCols], dkl[kCols], Ll[kCols];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col0 = blockIdx.x * kCols;
+    const int iS = a.iS, rows = a.rows;
+    const int w = a.safe.omega_log2;
+    const double omega = ldexp(1.0, w);
+    const double delta = SAFE ? *a.safe.delta : 0.0;
+
+    if (tid < kCols) {
+        const int j = col0 + tid;
+        int L = 0;
+        if (j < a.n) {
+            L = a.m;
+            if (VARLEN) {
+                L = a.col_len[j];
+                L = L < 0 ? 0 : (L > a.m ? a.m : L);
+            }
+        }
+        Ll[tid] = L;
+        dkl[tid] = 0;
+        if (SAFE) {
+            Gl[tid] = (j < a.n) ? a.safe.G[j] : 0.0;
+            kcl[tid] = (j < a.n) ? a.safe.kcur[j] : 0;
+        }
+    }
+    // right-hand sides of the outer block -> LDS (rows outside the column: 0)
+    {
+        constexpr int PER = kCols * kRowsMax / kWG;
+        zd st[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * kWG;
+            const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
+            const int j = col0 + c;
+            int L = 0;
+            if (j < a.n) {
+                L = a.m;
+                if (VARLEN) {
+                    L = a.col_len[j];
+                    L = L < 0 ? 0 : (L > a.m ? a.m : L);
+                }
+            }
+            st[e] = zd{0.0, 0.0};
+            if (rr < rows && iS + rr < L) {
+                if (MIXED) {
+                    const zf v = a.b32[(long)j * a.ldb32 + iS + rr];
+                    st[e] = zd{v.re, v.im};
+                } else {
+                    st[e] = a.B[(long)j * a.ldb + iS + rr];
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * kWG;
+            const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
+            Bl[c * kSP + rr] = st[e];
+        }
+    }
+    __syncthreads();
+
+    const int grp = lane / NB, r = lane - grp * NB, base = grp * NB;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int nsub = (rows + NB - 1) / NB;
+    for (int stp = 0; stp < nsub; ++stp) {
+        const int ql = ADJ ? stp : nsub - 1 - stp;
+        const int q = a.qa + ql;
+        const int lr0 = ql * NB;
+        const int i0 = iS + lr0;
+        const int bs = min(NB, rows - lr0);
+        stage_diag<NB, ADJ>(Us, Ud, a.U, a.ldu, i0, bs);
+        __syncthreads();
+
+        // ---- diagonal block: each wavefront solves its 4 shifts
+        {
+            BlockSolve<NB, SPW, ADJ, SAFE> S;
+            int cc[SPW];
+            zd lam[SPW];
+            bool jv[SPW], act[SPW];
+#pragma unroll
+            for (int s = 0; s < SPW; ++s) {
+                const int c = wave * 4 + s * G + grp;
+                const int j = col0 + c;
+                cc[s] = c;
+                jv[s] = j < a.n;
+                act[s] = jv[s] && (i0 < Ll[c]);
+                lam[s] = jv[s] ? a.lam[j] : zd{0.0, 0.0};
+                zd b{0.0, 0.0};
+                if (r < bs) b = Bl[c * kSP + lr0 + r];
+                S.br[s] = b.re;
+                S.bi[s] = b.im;
+            }
+            const double cn_l = (SAFE && r < bs) ? a.safe.cn_in[i0 + r] : 0.0;
+            S.pivots(Ud, r, bs, lam, jv, delta);
+            S.run(Us, bs, r, base, cn_l, w, omega);
+            if (SAFE) {
+                const double asum = a.safe.above_sum[q];
+#pragma unroll
+                for (int s = 0; s < SPW; ++s) {
+                    const int c = cc[s];
+                    double Gj = Gl[c];
+                    const int dk = S.column_bound(s, act[s], asum, &Gj, w, omega);
+                    if (r == 0 && jv[s]) {
+                        const int kc = kcl[c] + dk;
+                        if (act[s]) {
+                            Gl[c] = S.Gs[s];
+                            kcl[c] = kc;
+                        }
+                        dkl[c] = dk;
+                        a.safe.kb[(long)q * a.n + col0 + c] = kc;
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < SPW; ++s)
+                if (r < bs) Bl[cc[s] * kSP + lr0 + r] = zd{S.br[s], S.bi[s]};
+        }
+        __syncthreads();
+
+        // ---- rows of the outer block still to be solved: C -= U_panel * X(block)
+        const int ubeg = ADJ ? lr0 + bs : 0;
+        const int uend = ADJ ? rows : lr0;
+        const int ntile = (uend - ubeg + 15) / 16;
+        if (ntile > 0) {
+            constexpr int KS = NB / 4;
+            zd xb[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = ks * 4 + lq;
+                xb[ks] = (k < bs) ? Bl[lr * kSP + lr0 + k] : zd{0.0, 0.0};
+            }
+            const int dsh = SAFE ? dkl[lr] : 0;
+            for (int tile = wave; tile < ntile; tile += kWG / 64) {
+                const int rb = ubeg + tile * 16;
+                zd af[KS];
+                const int arow = rb + lr;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const int k = ks * 4 + lq;
+                    zd v{0.0, 0.0};
+                    if (k < bs && arow < uend) {
+                        if (!ADJ) {
+                            v = a.U[(long)(i0 + k) * a.ldu + iS + arow];
+                        } else {
+                            v = a.U[(long)(iS + arow) * a.ldu + i0 + k];
+                            v.im = -v.im;
+                        }
+                    }
+                    af[ks] = v;
+                }
+                v4d accR, accI;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rb + lq + 4 * v;
+                    zd c{0.0, 0.0};
+                    if (row < uend) c = Bl[lr * kSP + row];
+                    if (SAFE) {
+                        c.re = ldexp(c.re, -dsh);
+                        c.im = ldexp(c.im, -dsh);
+                    }
+                    accR[v] = c.re;
+                    accI[v] = c.im;
+                }
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const double ar = -af[ks].re, ai = -af[ks].im;
+                    accR = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb[ks].re, accR, 0, 0, 0);
+                    accI = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb[ks].im, accI, 0, 0, 0);
+                    accR = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, xb[ks].im, accR, 0, 0, 0);
+                    accI = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xb[ks].re, accI, 0, 0, 0);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rb + lq + 4 * v;
+                    if (row < uend) Bl[lr * kSP + row] = zd{accR[v], accI[v]};
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- solution of the outer block -> HBM; safe state back
+    if (SAFE && tid < kCols && col0 + tid < a.n) {
+        a.safe.G[col0 + tid] = Gl[tid];
+        a.safe.kcur[col0 + tid] = kcl[tid];
+    }
+    {
+        constexpr int PER = kCols * kRowsMax / kWG;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * kWG;
+            const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
+            const int j = col0 + c;
+            if (j < a.n && rr < rows && iS + rr < Ll[c]) {
+                const zd v = Bl[c * kSP + rr];
+                a.B[(long)j * a.ldb + iS + rr] = v;
+                if (MIXED) a.b32[(long)j * a.ldb32 + iS + rr] = zf{(float)v.re, (float)v.im};
+            }
         }
     }
 }
@@ -314,6 +583,31 @@ hipError_t launch_nb(const DiagArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int NB, bool ADJ>
+hipError_t launch_blk(const BlockArgs& a, hipStream_t s) {
+    const dim3 grid((a.n + kCols - 1) / kCols);
+    const bool safe = a.use_safe != 0;
+    const bool mixed = a.b32 != nullptr;
+    const bool varlen = a.col_len != nullptr;
+    if (ADJ) {
+        if (safe || mixed || varlen) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_block<NB, true, false, false, false>), grid, dim3(kWG), 0, s, a);
+    } else if (safe) {
+        if (mixed) return hipErrorInvalidValue;
+        if (varlen)
+            hipLaunchKernelGGL((k_block<NB, false, true, false, true>), grid, dim3(kWG), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_block<NB, false, true, false, false>), grid, dim3(kWG), 0, s, a);
+    } else {
+        if (varlen) return hipErrorInvalidValue;
+        if (mixed)
+            hipLaunchKernelGGL((k_block<NB, false, false, true, false>), grid, dim3(kWG), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_block<NB, false, false, false, false>), grid, dim3(kWG), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_diag(int nb, bool adjoint, const DiagArgs& a, hipStream_t s) {
@@ -322,6 +616,18 @@ hipError_t launch_diag(int nb, bool adjoint, const DiagArgs& a, hipStream_t s) {
         case 64: return adjoint ? launch_nb<64, 4, true>(a, s) : launch_nb<64, 4, false>(a, s);
         case 32: return adjoint ? launch_nb<32, 2, true>(a, s) : launch_nb<32, 2, false>(a, s);
         case 16: return adjoint ? launch_nb<16, 1, true>(a, s) : launch_nb<16, 1, false>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int block_rows_max() { return kRowsMax; }
+
+hipError_t launch_block(bool adjoint, const BlockArgs& a, hipStream_t s) {
+    if (a.rows <= 0 || a.rows > kRowsMax || a.n <= 0 || a.iS % a.nb) return hipErrorInvalidValue;
+    switch (a.nb) {
+        case 64: return adjoint ? launch_blk<64, true>(a, s) : launch_blk<64, false>(a, s);
+        case 32: return adjoint ? launch_blk<32, true>(a, s) : launch_blk<32, false>(a, s);
+        case 16: return adjoint ? launch_blk<16, true>(a, s) : launch_blk<16, false>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -390,3 +390,31 @@ def test_abi_errors(P):
     sc = dev(np.zeros(4), dtype=__import__("torch").float64)
     assert lib.mstrsm_safe(4, 4, P._p(x), 4, P._p(x), P._p(x), 4, None, P._p(sc), None,
                            ctypes.byref(mixed), None) == P._lib.MST_EUNSUPPORTED
+
+
+# ------------------------------------------------------------------ fused vs per-block paths
+
+@pytest.mark.parametrize("nb,outer", [(64, 256), (32, 96), (16, 64)])
+def test_unfused_and_fused_agree(P, oracle_mod, nb, outer):
+    """One launch per diagonal block plus separate GEMMs (the paper's loop
+    order) and the fused outer-block kernel solve the same systems."""
+    w = W.c1_plain(seed=55 + nb, m=333, n=70)
+    Xf = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, outer_nb=outer))
+    Xu = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, outer_nb=outer, fuse=False))
+    check_plain(oracle_mod, w.U, w.shifts, w.B, Xf)
+    check_plain(oracle_mod, w.U, w.shifts, w.B, Xu)
+    Yf = host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, outer_nb=outer))
+    Yu = host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, outer_nb=outer, fuse=False))
+    Yo = oracle_mod.solve_adjoint(w.U, w.shifts, w.B)
+    assert colerr(Yf, Yo).max() <= 1e-10 and colerr(Yu, Yo).max() <= 1e-10
+    U, lam, B = _growth(77, 300, 40)
+    for fuse in (True, False):
+        X, s, k = P.mstrsm_safe(dev(U), dev(lam), dev(B), nb=nb, outer_nb=outer, omega_log2=40,
+                                fuse=fuse)
+        _check_safe(oracle_mod, U, lam, B, host(X), host(s), host(k), nb, 40)
+
+
+def test_large_outer_block_uses_per_block_path(P, oracle_mod):
+    w = W.c1_plain(seed=58, m=700, n=50)
+    X = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=64, outer_nb=512))
+    check_plain(oracle_mod, w.U, w.shifts, w.B, X)
