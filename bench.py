@@ -53,7 +53,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--m", type=int, default=4096)
     ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--nb", type=int, default=64)
+    ap.add_argument("--nb", type=int, default=32)
     ap.add_argument("--outer-nb", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")

@@ -42,7 +42,7 @@ typedef enum {
 
 /* Options. A NULL mst_opts* means all defaults; a zero field means its default. */
 typedef struct {
-    int nb;            /* diagonal-block (and scaling-decision) size: 16, 32 or 64; default 64 */
+    int nb;            /* diagonal-block (and scaling-decision) size: 16, 32 or 64; default 32 */
     int outer_nb;      /* rows per deferred substitution step, a multiple of nb; default 256.
                           Equal to nb gives the paper's right-looking order (Alg 3 / Alg 5). */
     int precision;     /* 0: all FP64.
@@ -59,7 +59,10 @@ typedef struct {
                           fused kernel (diagonal blocks plus the substitution between them);
                           -1: one kernel per diagonal block plus separate GEMMs (same
                           arithmetic, kept for testing and for outer_nb > 256). */
-    int reserved[3];
+    int gemm_staged;   /* 0 (default): substitution GEMM without LDS staging (each wavefront
+                          streams its operands from L1/L2); 1: LDS-staged GEMM. Same results
+                          up to summation order; kept for testing. */
+    int reserved[2];
 } mst_opts;
 
 /*

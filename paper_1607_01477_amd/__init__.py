@@ -1,6 +1,7 @@
 """Blocked multi-shift triangular solves on AMD MI355X (gfx950).
 
 Python binding of ``libmstrsm.so`` (C-ABI declared in ``include/mstrsm.h``).
+Keyword options left at 0 take the library's defaults (nb = 32, outer_nb = 256).
 Every function here only marshals arguments: tensors must be complex128 (int32
 for ``col_len``) on a ROCm device; matrices are passed column-major (a
 Fortran-ordered view, ``t.stride(0) == 1``), copied into that layout if they
@@ -31,8 +32,10 @@ def version() -> str:
     return _lib.load().mst_version().decode()
 
 
-def _opts(nb=0, outer_nb=0, precision=0, max_sweeps=0, omega_log2=0, force_phase2=0, fuse=True):
+def _opts(nb=0, outer_nb=0, precision=0, max_sweeps=0, omega_log2=0, force_phase2=0, fuse=True,
+          staged=False):
     o = MstOpts()
+    o.gemm_staged = 1 if staged else 0
     o.nb, o.outer_nb, o.precision = int(nb), int(outer_nb), int(precision)
     o.max_sweeps, o.omega_log2, o.force_phase2 = int(max_sweeps), int(omega_log2), int(force_phase2)
     o.fuse_blocks = 0 if fuse else -1
@@ -104,7 +107,7 @@ def _mat(t: torch.Tensor, name: str) -> torch.Tensor:
     return colmajor(t)
 
 
-def mstrsm(U, shifts, B, *, nb=64, outer_nb=0, precision=0, max_sweeps=2, fuse=True):
+def mstrsm(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2, fuse=True, staged=False):
     """X with (U - shifts[j] I) X[:, j] = B[:, j]; B is overwritten when it is
     already column-major complex128 (the result is returned either way).
     precision=1: FP32 substitution GEMMs + FP64 refinement (max_sweeps)."""
@@ -114,13 +117,15 @@ def mstrsm(U, shifts, B, *, nb=64, outer_nb=0, precision=0, max_sweeps=2, fuse=T
     if U.shape != (m, m):
         raise ValueError("U must be %d x %d" % (m, m))
     s = _vec(shifts, n, "shifts")
-    o = _opts(nb=nb, outer_nb=outer_nb, precision=precision, max_sweeps=max_sweeps, fuse=fuse)
+    o = _opts(nb=nb, outer_nb=outer_nb, precision=precision, max_sweeps=max_sweeps, fuse=fuse,
+              staged=staged)
     rc = _lib.load().mstrsm(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), ctypes.byref(o), _stream())
     _lib.check("mstrsm", rc)
     return X
 
 
-def mstrsm_safe(U, shifts, B, col_len=None, *, nb=64, outer_nb=0, omega_log2=0, fuse=True):
+def mstrsm_safe(U, shifts, B, col_len=None, *, nb=0, outer_nb=0, omega_log2=0, fuse=True,
+                staged=False):
     """Safe solve: returns (X, scale, scale_log2) with
     (U - shifts[j] I) X[:, j] = scale[j] B[:, j], scale[j] = 2^-scale_log2[j]."""
     U = _mat(U, "U")
@@ -132,14 +137,14 @@ def mstrsm_safe(U, shifts, B, col_len=None, *, nb=64, outer_nb=0, omega_log2=0, 
     cl = _vec(col_len, n, "col_len", torch.int32) if col_len is not None else None
     scale = torch.empty(n, dtype=torch.float64, device=X.device)
     klog = torch.empty(n, dtype=torch.int32, device=X.device)
-    o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2, fuse=fuse)
+    o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2, fuse=fuse, staged=staged)
     rc = _lib.load().mstrsm_safe(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), _p(cl), _p(scale),
                                  _p(klog), ctypes.byref(o), _stream())
     _lib.check("mstrsm_safe", rc)
     return X, scale, klog
 
 
-def mstrsm_adjoint(U, shifts, G, *, nb=64, outer_nb=0, fuse=True):
+def mstrsm_adjoint(U, shifts, G, *, nb=0, outer_nb=0, fuse=True):
     """Y with (U - shifts[j] I)^H Y[:, j] = G[:, j] (G overwritten when column-major)."""
     U = _mat(U, "U")
     Y = _mat(G, "G")
@@ -194,7 +199,7 @@ def residual(U, shifts, X, B0):
     return R
 
 
-def triang_eig(T, *, nb=64, outer_nb=0, omega_log2=0):
+def triang_eig(T, *, nb=0, outer_nb=0, omega_log2=0):
     """TriangEig (Alg 6): returns (eigvals, Z, scale_log2) with T Z[:, j] =
     eigvals[j] Z[:, j], Z upper triangular, Z[j, j] = 2^-scale_log2[j]."""
     T = _mat(T, "T")
@@ -211,7 +216,7 @@ def triang_eig(T, *, nb=64, outer_nb=0, omega_log2=0):
     return ev, Z, klog
 
 
-def lanczos_sigma_min(U, z, V0, iters=15, *, nb=64, outer_nb=0):
+def lanczos_sigma_min(U, z, V0, iters=15, *, nb=0, outer_nb=0):
     """Inverse-Lanczos estimate of sigma_min(U - z_j I) for every shift
     (Alg 7, second stage). V0 (m x N start vectors) is not modified.
     Returns (sigma, alpha, beta, steps); alpha/beta are (N, iters)."""
@@ -257,7 +262,7 @@ class MultiShiftSolve(torch.autograd.Function):
         return gU, gs, gB, None, None, None, None
 
 
-def solve(U, shifts, B, *, nb=64, outer_nb=0, precision=0, max_sweeps=2):
+def solve(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2):
     """Differentiable multi-shift solve (see MultiShiftSolve)."""
     return MultiShiftSolve.apply(U, shifts, B, nb, outer_nb, precision, max_sweeps)
 

@@ -84,8 +84,9 @@ hipError_t timed(int kind, double flops, hipStream_t s, F&& launch) {
 double gemm_flops(const GemmArgs& g) { return 8.0 * g.M * (double)g.N * g.K; }
 
 struct Opts {
-    int nb = 64, outer = 256, precision = 0, sweeps = 2, omega_log2 = 960;
+    int nb = 32, outer = 256, precision = 0, sweeps = 2, omega_log2 = 960;
     bool fuse = true;
+    int staged = 0;
 };
 
 // position of opt in the caller's argument list, for error reporting
@@ -105,6 +106,8 @@ mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
     if (r.omega_log2 < 8 || r.omega_log2 > 1000) return bad(pos);
     if (o->fuse_blocks != 0 && o->fuse_blocks != -1) return bad(pos);
     r.fuse = o->fuse_blocks == 0;
+    if (o->gemm_staged != 0 && o->gemm_staged != 1) return bad(pos);
+    r.staged = o->gemm_staged;
     return MST_OK;
 }
 
@@ -179,7 +182,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             if (q > qa) {
                 GemmArgs g{};
                 g.M = i0 - qa * nb; g.N = n; g.K = bs;
-                g.op = GOP_SUB;
+                g.op = GOP_SUB; g.staged = o.staged;
                 g.nb = nb; g.b_row0 = i0; g.c_row0 = qa * nb; g.col_len = col_len;
                 if (safe) {
                     g.kb = safe->kb; g.n_kb = n; g.q_cur = q; g.q_c = (q + 1 < nblk) ? q + 1 : -1;
@@ -203,7 +206,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             const int end = ((qb + 1) * nb < m) ? (qb + 1) * nb : m;
             GemmArgs g{};
             g.M = r1; g.N = n; g.K = end - r1;
-            g.op = GOP_SUB;
+            g.op = GOP_SUB; g.staged = o.staged;
             g.nb = nb; g.b_row0 = r1; g.c_row0 = 0; g.col_len = col_len;
             if (safe) {
                 g.kb = safe->kb; g.n_kb = n; g.q_cur = qa; g.q_c = (qb + 1 < nblk) ? qb + 1 : -1;

@@ -76,6 +76,8 @@ struct GemmArgs {
     const int* kb; int n_kb; int q_cur; int q_c; int nb; int b_row0;
     // variable-length columns: column c uses rows < col_len[c] (global row of C row 0 = c_row0)
     const int* col_len; int c_row0;
+    // substitution (GOP_SUB, plain operands): 1 = LDS-staged kernel, 0 = barrier-free kernel
+    int staged;
 };
 hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s);
 hipError_t launch_gemm_f32(const GemmArgs& g, hipStream_t s);

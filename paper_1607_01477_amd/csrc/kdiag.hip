@@ -20,7 +20,8 @@
 // Two kernels use this step:
 //   k_diag  - one diagonal block for all shifts (the paper's loop order);
 //   k_block - a whole outer block of up to 256 rows for 16 shifts per
-//             workgroup: the right-hand sides of the outer block stay in LDS,
+//             workgroup of 8 wavefronts: the right-hand sides of the outer
+//             block stay in LDS,
 //             each diagonal block is solved as above and the rows of the
 //             outer block still to be solved are updated right away with
 //             FP64 MFMA products (U panel from L2, solution from LDS). This
@@ -344,12 +345,18 @@ __global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
 
 // ---------------------------------------------------------------- fused outer block
 constexpr int kRowsMax = 256;          // rows of one outer block
-constexpr int kCols = 16;              // shifts per workgroup (4 per wavefront)
+constexpr int kCols = 16;              // shifts per workgroup
 constexpr int kSP = kRowsMax + 1;      // padded LDS column stride (bank spread)
+constexpr int kWGB = 512;              // threads of the fused kernel (2 wavefronts per SIMD)
 
 template <int NB, bool ADJ, bool SAFE, bool MIXED, bool VARLEN>
-__global__ __launch_bounds__(kWG) void k_block(BlockArgs a) {
-    constexpr int G = 64 / NB, SPW = 4 / G;
+__global__ __launch_bounds__(kWGB) void k_block(BlockArgs a) {
+    constexpr int G = 64 / NB;
+    constexpr int NWAVE = kWGB / 64;
+    constexpr int AWAVES = (NB == 16) ? 4 : NWAVE;       // wavefronts solving diagonal blocks
+    constexpr int SPW = kCols / (AWAVES * G);            // interleaved shifts per lane group
+    constexpr int PERU = (NB * NB + kWGB - 1) / kWGB;    // diagonal-block elements per thread
+    static_assert(SPW * G * AWAVES == kCols, "column split");
     __shared__ zd Bl[kCols * kSP];
     __shared__ zd Us[NB * NB];
     __shared__ zd Ud[NB];
@@ -382,11 +389,11 @@ __global__ __launch_bounds__(kWG) void k_block(BlockArgs a) {
     }
     // right-hand sides of the outer block -> LDS (rows outside the column: 0)
     {
-        constexpr int PER = kCols * kRowsMax / kWG;
+        constexpr int PER = kCols * kRowsMax / kWGB;
         zd st[PER];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-            const int idx = tid + e * kWG;
+            const int idx = tid + e * kWGB;
             const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
             const int j = col0 + c;
             int L = 0;
@@ -409,34 +416,65 @@ __global__ __launch_bounds__(kWG) void k_block(BlockArgs a) {
         }
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-            const int idx = tid + e * kWG;
+            const int idx = tid + e * kWGB;
             const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
             Bl[c * kSP + rr] = st[e];
         }
     }
+
+    // diagonal block staging: loads into registers, stores to LDS later
+    const int nsub = (rows + NB - 1) / NB;
+    zd ust[PERU];
+    auto ustage_load = [&](int stp) __attribute__((always_inline)) {
+        const int ql = ADJ ? stp : nsub - 1 - stp;
+        const int i0 = iS + ql * NB, bs = min(NB, rows - ql * NB);
+#pragma unroll
+        for (int e = 0; e < PERU; ++e) {
+            const int t = tid + e * kWGB;
+            const int c = t / NB, rr = t - c * NB;
+            ust[e] = zd{0.0, 0.0};
+            if (t < NB * NB && rr <= c && c < bs) ust[e] = a.U[(long)(i0 + c) * a.ldu + i0 + rr];
+        }
+    };
+    auto ustage_store = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int e = 0; e < PERU; ++e) {
+            const int t = tid + e * kWGB;
+            if (t >= NB * NB) continue;
+            const int c = t / NB, rr = t - c * NB;
+            const zd v = ADJ ? zd{ust[e].re, -ust[e].im} : ust[e];
+            if (rr == c) {
+                Ud[rr] = v;
+                Us[c * NB + rr] = zd{0.0, 0.0};
+            } else if (!ADJ) {
+                Us[c * NB + rr] = v;
+            } else {
+                Us[rr * NB + c] = v;
+            }
+        }
+    };
+    ustage_load(0);
+    ustage_store();
     __syncthreads();
 
     const int grp = lane / NB, r = lane - grp * NB, base = grp * NB;
     const int lr = lane & 15, lq = lane >> 4;
-    const int nsub = (rows + NB - 1) / NB;
     for (int stp = 0; stp < nsub; ++stp) {
         const int ql = ADJ ? stp : nsub - 1 - stp;
         const int q = a.qa + ql;
         const int lr0 = ql * NB;
         const int i0 = iS + lr0;
         const int bs = min(NB, rows - lr0);
-        stage_diag<NB, ADJ>(Us, Ud, a.U, a.ldu, i0, bs);
-        __syncthreads();
 
-        // ---- diagonal block: each wavefront solves its 4 shifts
-        {
+        // ---- diagonal block: each solving wavefront takes SPW * G shifts
+        if (wave < AWAVES) {
             BlockSolve<NB, SPW, ADJ, SAFE> S;
             int cc[SPW];
             zd lam[SPW];
             bool jv[SPW], act[SPW];
 #pragma unroll
             for (int s = 0; s < SPW; ++s) {
-                const int c = wave * 4 + s * G + grp;
+                const int c = (wave * SPW + s) * G + grp;
                 const int j = col0 + c;
                 cc[s] = c;
                 jv[s] = j < a.n;
@@ -473,24 +511,20 @@ __global__ __launch_bounds__(kWG) void k_block(BlockArgs a) {
                 if (r < bs) Bl[cc[s] * kSP + lr0 + r] = zd{S.br[s], S.bi[s]};
         }
         __syncthreads();
+        if (stp + 1 < nsub) ustage_load(stp + 1);   // next diagonal block, in flight during the update
 
         // ---- rows of the outer block still to be solved: C -= U_panel * X(block)
         const int ubeg = ADJ ? lr0 + bs : 0;
         const int uend = ADJ ? rows : lr0;
         const int ntile = (uend - ubeg + 15) / 16;
-        if (ntile > 0) {
+        if (wave < ntile) {
             constexpr int KS = NB / 4;
-            zd xb[KS];
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const int k = ks * 4 + lq;
-                xb[ks] = (k < bs) ? Bl[lr * kSP + lr0 + k] : zd{0.0, 0.0};
-            }
             const int dsh = SAFE ? dkl[lr] : 0;
-            for (int tile = wave; tile < ntile; tile += kWG / 64) {
-                const int rb = ubeg + tile * 16;
-                zd af[KS];
-                const int arow = rb + lr;
+            // next tile's U fragments are prefetched when registers allow (nb <= 32)
+            constexpr bool PREF = KS <= 8;
+            zd af[KS], an[KS];
+            auto aload = [&](zd (&dst)[KS], int tile) __attribute__((always_inline)) {
+                const int arow = ubeg + tile * 16 + lr;
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
                     const int k = ks * 4 + lq;
@@ -503,8 +537,19 @@ __global__ __launch_bounds__(kWG) void k_block(BlockArgs a) {
                             v.im = -v.im;
                         }
                     }
-                    af[ks] = v;
+                    dst[ks] = v;
                 }
+            };
+            if (PREF) aload(an, wave);
+            for (int tile = wave; tile < ntile; tile += NWAVE) {
+                if (PREF) {
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) af[ks] = an[ks];
+                    if (tile + NWAVE < ntile) aload(an, tile + NWAVE);
+                } else {
+                    aload(af, tile);
+                }
+                const int rb = ubeg + tile * 16;
                 v4d accR, accI;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -520,11 +565,14 @@ __global__ __launch_bounds__(kWG) void k_block(BlockArgs a) {
                 }
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
+                    // X(block) fragment from LDS: row k = 4 ks + lane/16, column lane%16
+                    const int k = ks * 4 + lq;
+                    const zd xb = (k < bs) ? Bl[lr * kSP + lr0 + k] : zd{0.0, 0.0};
                     const double ar = -af[ks].re, ai = -af[ks].im;
-                    accR = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb[ks].re, accR, 0, 0, 0);
-                    accI = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb[ks].im, accI, 0, 0, 0);
-                    accR = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, xb[ks].im, accR, 0, 0, 0);
-                    accI = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xb[ks].re, accI, 0, 0, 0);
+                    accR = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb.re, accR, 0, 0, 0);
+                    accI = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb.im, accI, 0, 0, 0);
+                    accR = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, xb.im, accR, 0, 0, 0);
+                    accI = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xb.re, accI, 0, 0, 0);
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -533,6 +581,7 @@ __global__ __launch_bounds__(kWG) void k_block(BlockArgs a) {
                 }
             }
         }
+        if (stp + 1 < nsub) ustage_store();
         __syncthreads();
     }
 
@@ -542,10 +591,10 @@ __global__ __launch_bounds__(kWG) void k_block(BlockArgs a) {
         a.safe.kcur[col0 + tid] = kcl[tid];
     }
     {
-        constexpr int PER = kCols * kRowsMax / kWG;
+        constexpr int PER = kCols * kRowsMax / kWGB;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-            const int idx = tid + e * kWG;
+            const int idx = tid + e * kWGB;
             const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
             const int j = col0 + c;
             if (j < a.n && rr < rows && iS + rr < Ll[c]) {
@@ -591,19 +640,19 @@ hipError_t launch_blk(const BlockArgs& a, hipStream_t s) {
     const bool varlen = a.col_len != nullptr;
     if (ADJ) {
         if (safe || mixed || varlen) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_block<NB, true, false, false, false>), grid, dim3(kWG), 0, s, a);
+        hipLaunchKernelGGL((k_block<NB, true, false, false, false>), grid, dim3(kWGB), 0, s, a);
     } else if (safe) {
         if (mixed) return hipErrorInvalidValue;
         if (varlen)
-            hipLaunchKernelGGL((k_block<NB, false, true, false, true>), grid, dim3(kWG), 0, s, a);
+            hipLaunchKernelGGL((k_block<NB, false, true, false, true>), grid, dim3(kWGB), 0, s, a);
         else
-            hipLaunchKernelGGL((k_block<NB, false, true, false, false>), grid, dim3(kWG), 0, s, a);
+            hipLaunchKernelGGL((k_block<NB, false, true, false, false>), grid, dim3(kWGB), 0, s, a);
     } else {
         if (varlen) return hipErrorInvalidValue;
         if (mixed)
-            hipLaunchKernelGGL((k_block<NB, false, false, true, false>), grid, dim3(kWG), 0, s, a);
+            hipLaunchKernelGGL((k_block<NB, false, false, true, false>), grid, dim3(kWGB), 0, s, a);
         else
-            hipLaunchKernelGGL((k_block<NB, false, false, false, false>), grid, dim3(kWG), 0, s, a);
+            hipLaunchKernelGGL((k_block<NB, false, false, false, false>), grid, dim3(kWGB), 0, s, a);
     }
     return hipGetLastError();
 }

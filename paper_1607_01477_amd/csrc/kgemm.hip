@@ -297,10 +297,175 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(GemmArgs g) {
     }
 }
 
+// ---------------------------------------------------------------- barrier-free substitution GEMM
+// C -= A B for plain (not conjugate-transposed) FP64 operands, the form of the
+// substitution step. Every wavefront owns a 32 x 32 complex tile of C and
+// reads its MFMA operands straight from global memory (L1/L2) in the lane
+// layout of the matrix cores: A(row, k) at lane row%16 + 16 k, B(k, col) at
+// lane col%16 + 16 k. Loads run DEPTH k-steps ahead of the matrix cores in a
+// register ring, so no LDS staging and no workgroup barrier are needed and each
+// wavefront keeps its matrix pipe fed on its own. The 4 wavefronts of a
+// workgroup cover a 64 x 64 tile and share A rows / B columns through L1.
+template <int DEPTH, bool SAFE, bool VARLEN>
+__global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
+    using V = v4d;
+    const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
+    int tm, tn;
+    tile_coords(TM, TN, tm, tn);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int rw = tm * BM + wr * 32, cw = tn * BN + wc * 32;
+    const zd* __restrict__ A = (const zd*)g.A;
+    const zd* __restrict__ B = (const zd*)g.B;
+    zd* __restrict__ C = (zd*)g.C;
+
+    if (VARLEN) {
+        // a wavefront whose columns all end above the B operand's rows has nothing to do
+        const int cc = cw + (lane & 31);
+        const bool act = cc < g.N && g.col_len[cc] > g.b_row0;
+        if (!__any(act)) return;
+    }
+    const bool full = (rw + 32 <= g.M) && (cw + 32 <= g.N);
+
+    // ---- accumulators start from C
+    V accR[2][2], accI[2][2];
+    int clim0 = g.M, clim1 = g.M, blim0 = g.K, blim1 = g.K, dshq = -1;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = cw + j * 16 + lr;
+        int csh = 0, cl = g.M, bl = g.K;
+        if (col < g.N) {
+            if (VARLEN) {
+                cl = min(g.M, g.col_len[col] - g.c_row0);
+                bl = min(g.K, g.col_len[col] - g.b_row0);
+            }
+            if (SAFE && g.kb != nullptr) {
+                const int kc = g.kb[(long)g.q_cur * g.n_kb + col];
+                const int kq = (g.q_c >= 0) ? g.kb[(long)g.q_c * g.n_kb + col] : 0;
+                csh = kc - kq;
+            }
+        } else {
+            bl = 0;
+        }
+        if (j == 0) {
+            clim0 = cl;
+            blim0 = bl;
+        } else {
+            clim1 = cl;
+            blim1 = bl;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = rw + i * 16 + lq + 4 * v;
+                zd c{0.0, 0.0};
+                if (col < g.N && row < cl) {
+                    c = C[(long)col * g.ldc + row];
+                    if (SAFE) {
+                        c.re = ldexp(c.re, -csh);
+                        c.im = ldexp(c.im, -csh);
+                    }
+                }
+                accR[i][j][v] = c.re;
+                accI[i][j][v] = c.im;
+            }
+        }
+    }
+
+    const int nks = (g.K + 3) / 4;
+    zd pa0[DEPTH], pa1[DEPTH], pb0[DEPTH], pb1[DEPTH];
+    int bsh0 = 0, bsh1 = 0;   // exponent shift of the B operand rows (safe), per column
+    auto load = [&](int ks, zd& a0, zd& a1, zd& b0, zd& b1) __attribute__((always_inline)) {
+        const int k = ks * 4 + lq;
+        const bool kin = k < g.K;
+        const bool fast = full && (ks * 4 + 4 <= g.K) && !VARLEN && !SAFE;
+        const zd* ap = A + (long)k * g.lda + rw + lr;
+        const zd* bp = B + (long)(cw + lr) * g.ldb + k;
+        a0 = zd{0.0, 0.0};
+        a1 = zd{0.0, 0.0};
+        b0 = zd{0.0, 0.0};
+        b1 = zd{0.0, 0.0};
+        if (fast || (kin && rw + lr < g.M)) a0 = ap[0];
+        if (fast || (kin && rw + 16 + lr < g.M)) a1 = ap[16];
+        if (fast || (k < blim0)) b0 = bp[0];
+        if (fast || (k < blim1)) b1 = bp[16 * g.ldb];
+        if (SAFE && g.kb != nullptr) {
+            // rows of one diagonal block share an exponent: look it up when the block changes
+            const int q = (g.b_row0 + k) / g.nb;
+            if (q != dshq) {
+                dshq = q;
+                const int col0 = cw + lr, col1 = cw + 16 + lr;
+                bsh0 = (col0 < g.N) ? g.kb[(long)g.q_cur * g.n_kb + col0] - g.kb[(long)q * g.n_kb + col0] : 0;
+                bsh1 = (col1 < g.N) ? g.kb[(long)g.q_cur * g.n_kb + col1] - g.kb[(long)q * g.n_kb + col1] : 0;
+            }
+            b0.re = ldexp(b0.re, -bsh0); b0.im = ldexp(b0.im, -bsh0);
+            b1.re = ldexp(b1.re, -bsh1); b1.im = ldexp(b1.im, -bsh1);
+        }
+    };
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d)
+        if (d < nks) load(d, pa0[d], pa1[d], pb0[d], pb1[d]);
+
+    for (int ks0 = 0; ks0 < nks; ks0 += DEPTH) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) {
+            const int ks = ks0 + d;
+            if (ks < nks) {
+                const zd a0 = pa0[d], a1 = pa1[d], b0 = pb0[d], b1 = pb1[d];
+                if (ks + DEPTH < nks) load(ks + DEPTH, pa0[d], pa1[d], pb0[d], pb1[d]);
+                // acc = C - A B: A negated
+                const double a0r = -a0.re, a0i = -a0.im, a1r = -a1.re, a1i = -a1.im;
+                accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b0.re, accR[0][0], 0, 0, 0);
+                accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b1.re, accR[0][1], 0, 0, 0);
+                accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b0.re, accR[1][0], 0, 0, 0);
+                accR[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b1.re, accR[1][1], 0, 0, 0);
+                accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b0.im, accI[0][0], 0, 0, 0);
+                accI[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b1.im, accI[0][1], 0, 0, 0);
+                accI[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b0.im, accI[1][0], 0, 0, 0);
+                accI[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b1.im, accI[1][1], 0, 0, 0);
+                accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0i, b0.im, accR[0][0], 0, 0, 0);
+                accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0i, b1.im, accR[0][1], 0, 0, 0);
+                accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1i, b0.im, accR[1][0], 0, 0, 0);
+                accR[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1i, b1.im, accR[1][1], 0, 0, 0);
+                accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0i, b0.re, accI[0][0], 0, 0, 0);
+                accI[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0i, b1.re, accI[0][1], 0, 0, 0);
+                accI[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1i, b0.re, accI[1][0], 0, 0, 0);
+                accI[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1i, b1.re, accI[1][1], 0, 0, 0);
+            }
+        }
+    }
+
+    // ---- epilogue: lane holds column lane%16, rows lane/16 + 4 v of each 16 x 16 block
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = cw + j * 16 + lr;
+        if (col >= g.N) continue;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = rw + i * 16 + lq + 4 * v;
+                if (!full && row >= g.M) continue;
+                if (VARLEN && row >= (j == 0 ? clim0 : clim1)) continue;
+                C[(long)col * g.ldc + row] = zd{accR[i][j][v], accI[i][j][v]};
+            }
+        }
+    }
+}
+
 template <typename T, bool A_CT, bool B_CT, int OP, bool SAFE, bool VARLEN>
 hipError_t go(const GemmArgs& g, hipStream_t s) {
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
     hipLaunchKernelGGL((k_gemm<T, A_CT, B_CT, OP, SAFE, VARLEN>), dim3(TM * TN), dim3(NT), 0, s, g);
+    return hipGetLastError();
+}
+
+template <bool SAFE, bool VARLEN>
+hipError_t go_direct(const GemmArgs& g, hipStream_t s) {
+    const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
+    hipLaunchKernelGGL((k_gemm_direct<4, SAFE, VARLEN>), dim3(TM * TN), dim3(NT), 0, s, g);
     return hipGetLastError();
 }
 
@@ -317,10 +482,16 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
                 if (safe || varlen) return hipErrorInvalidValue;
                 return go<double, true, false, GOP_SUB, false, false>(g, s);
             }
-            if (safe && varlen) return go<double, false, false, GOP_SUB, true, true>(g, s);
-            if (safe) return go<double, false, false, GOP_SUB, true, false>(g, s);
+            if (g.staged) {
+                if (safe && varlen) return go<double, false, false, GOP_SUB, true, true>(g, s);
+                if (safe) return go<double, false, false, GOP_SUB, true, false>(g, s);
+                if (varlen) return hipErrorInvalidValue;
+                return go<double, false, false, GOP_SUB, false, false>(g, s);
+            }
+            if (safe && varlen) return go_direct<true, true>(g, s);
+            if (safe) return go_direct<true, false>(g, s);
             if (varlen) return hipErrorInvalidValue;
-            return go<double, false, false, GOP_SUB, false, false>(g, s);
+            return go_direct<false, false>(g, s);
         case GOP_RESID:
             if (g.a_ct || g.b_ct || safe || varlen) return hipErrorInvalidValue;
             return go<double, false, false, GOP_RESID, false, false>(g, s);

@@ -240,7 +240,7 @@ def test_safe_col_len(P, oracle_mod):
 def test_triang_eig_c2_config(P, oracle_mod):
     w = W.c2_triang_eig()
     announce("c2 triangular eigenvectors 2048")
-    ev, Z, k = P.triang_eig(dev(w.U))
+    ev, Z, k = P.triang_eig(dev(w.U), nb=64)
     ev, Z, k = host(ev), host(Z), host(k)
     lo, Zo, ko = oracle_mod.triang_eig(w.U, nb=64)
     assert np.array_equal(ev, lo)
@@ -418,3 +418,27 @@ def test_large_outer_block_uses_per_block_path(P, oracle_mod):
     w = W.c1_plain(seed=58, m=700, n=50)
     X = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=64, outer_nb=512))
     check_plain(oracle_mod, w.U, w.shifts, w.B, X)
+
+
+@pytest.mark.parametrize("safe", [False, True])
+def test_staged_and_direct_gemm_agree(P, oracle_mod, safe):
+    """LDS-staged and barrier-free substitution GEMMs solve the same systems."""
+    if not safe:
+        w = W.c1_plain(seed=59, m=530, n=140)
+        for staged in (False, True):
+            for fuse in (True, False):
+                X = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=32, outer_nb=128,
+                                  staged=staged, fuse=fuse))
+                check_plain(oracle_mod, w.U, w.shifts, w.B, X)
+    else:
+        U, lam, B = _growth(79, 450, 60)
+        L = W.rng(790).integers(0, 451, 60).astype(np.int32)
+        import torch
+        for staged in (False, True):
+            X, s, k = P.mstrsm_safe(dev(U), dev(lam), dev(B), nb=32, outer_nb=64, omega_log2=40,
+                                    staged=staged)
+            _check_safe(oracle_mod, U, lam, B, host(X), host(s), host(k), 32, 40)
+            X, s, k = P.mstrsm_safe(dev(U), dev(lam), dev(B), col_len=dev(L, dtype=torch.int32),
+                                    nb=32, outer_nb=64, omega_log2=40, staged=staged)
+            Xo, so, ko = oracle_mod.solve_safe(U, lam, B, col_len=L, nb=32, omega_log2=40)
+            assert np.array_equal(host(k), ko)
