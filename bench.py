@@ -30,6 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA_TF = 78.6
+# HBM bytes per launch of the substitution GEMM at this workload, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs scaled by a 512 MiB copy (profiles/k_gemm_direct_solve_m4096_n4096.md).
+# Valid only for the GEMM source it was measured on (sha1 prefix of csrc/kgemm.hip).
+GEMM_TRAFFIC = {"kgemm_sha1": "c7191d12866604e9", "bytes_per_launch": 447.1e6, "m": 4096, "n": 4096,
+                "nb": 32, "outer_nb": 256}
 PEAK_FP32_MFMA_TF = 157.3
 METRIC = "complex128 multi-shift solve GFLOP/s at m=n=4096 and % of MFMA peak vs plain FP64"
 
@@ -43,6 +48,79 @@ def dev(a, torch):
     a = np.asfortranarray(a)
     out = torch.empty_strided(a.shape, (1, a.shape[0]), dtype=torch.complex128, device="cuda")
     out.copy_(torch.from_numpy(a))
+    return out
+
+
+def gemm_traffic(m, n, nb, outer_nb):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1607_01477_amd", "csrc", "kgemm.hip")
+    try:
+        h = hashlib.sha1(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    t = GEMM_TRAFFIC
+    if h != t["kgemm_sha1"] or (m, n, nb, outer_nb) != (t["m"], t["n"], t["nb"], t["outer_nb"]):
+        return None
+    return t["bytes_per_launch"]
+
+
+def _time(fn, torch, reps):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def other_workloads(P, W, torch, np) -> dict:
+    """Triangular eigenvectors (safe solve, variable-length columns), inverse
+    Lanczos on a 100x100 shift grid, and forward + backward through the solve."""
+    out = {}
+    # triangular eigenvectors, m = 2048: sum_j 4 j^2 flops
+    w = W.c2_triang_eig()
+    T = dev(w.U, torch)
+    ms = _time(lambda: P.triang_eig(T), torch, 3)
+    ev, Z, k = P.triang_eig(T)
+    fl = W.nominal_flops(w.m, w.n, w.col_len)
+    out["c2_triang_eig_m2048"] = {"ms": round(ms, 3), "gflops": round(fl / (ms * 1e-3) / 1e9, 2),
+                                  "rescaled_columns": int((k > 0).sum().item())}
+    log("triangular eigenvectors m=2048: %.3f ms" % ms)
+    del T, Z
+    # pseudospectra: 15 Lanczos steps = 30 solves of 2000 x 10000
+    w = W.c4_pseudospectra()
+    Ud = dev(w.U, torch)
+    z = torch.from_numpy(w.shifts).cuda()
+    V0 = dev(w.B, torch)
+    ms = _time(lambda: P.lanczos_sigma_min(Ud, z, V0, iters=15), torch, 2)
+    fl = 30 * W.nominal_flops(w.m, w.n)
+    out["c4_lanczos_m2000_N10000"] = {"ms": round(ms, 3), "gflops": round(fl / (ms * 1e-3) / 1e9, 2),
+                                      "ms_per_shift_us": round(ms * 1e3 / w.n, 3)}
+    log("pseudospectra 2000 x 10000 shifts, 15 steps: %.3f ms" % ms)
+    del Ud, V0
+    # forward + backward through the solve, m = 4096, n = 2048
+    w = W.c5_adjoint()
+    U = dev(w.U, torch).requires_grad_(True)
+    s = torch.from_numpy(w.shifts).cuda().requires_grad_(True)
+    B = dev(w.B, torch).requires_grad_(True)
+    Wt = torch.from_numpy(np.asfortranarray(w.extra["W"])).cuda()
+
+    def fwd_bwd():
+        U.grad = s.grad = B.grad = None
+        X = P.solve(U, s, B)
+        (Wt * (X.real ** 2 + X.imag ** 2)).sum().backward()
+
+    def fwd():
+        with torch.no_grad():
+            P.mstrsm(U.detach(), s.detach(), B.detach().clone())
+
+    ms_f = _time(fwd, torch, 3)
+    ms_fb = _time(fwd_bwd, torch, 3)
+    ffl = W.nominal_flops(w.m, w.n)
+    out["c5_fwd_bwd_m4096_n2048"] = {"fwd_ms": round(ms_f, 3), "fwd_bwd_ms": round(ms_fb, 3),
+                                     "fwd_bwd_gflops": round(3 * ffl / (ms_fb * 1e-3) / 1e9, 2)}
+    log("forward %.3f ms, forward+backward %.3f ms" % (ms_f, ms_fb))
     return out
 
 
@@ -71,9 +149,8 @@ def main() -> int:
         print(json.dumps({"copy_calibration_bytes_per_copy": src.numel() * 8 * 2}))
         return 0
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(shifts would be sharded across GPUs with no communication; see DESIGN.md)",
-              file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (the shifts would be "
+              "sharded across GPUs with U replicated and no communication)", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -144,7 +221,7 @@ def main() -> int:
         "peak": PEAK_FP64_MFMA_TF,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP64_MFMA_TF, 4),
-        "traffic": None,
+        "traffic": gemm_traffic(m, n, args.nb, args.outer_nb),
         "kernel": "k_gemm<double> (substitution GEMM, FP64 MFMA 16x16x4)",
         "avg_launch_us": round(g["ms"] * 1e3 / max(1, g["launches"]), 2),
         "flops_per_launch": g["flops"] / max(1, g["launches"]),
@@ -195,6 +272,10 @@ def main() -> int:
             del Xs
             log("fp32+%d sweeps: %.3f ms, rel diff vs fp64 %.2e" % (sweeps, ms, fe))
         line["secondary"] = sec
+
+    # ---- the other workloads of the path (each timed on inputs resident in HBM)
+    if not args.no_secondary:
+        line["workloads"] = other_workloads(P, W, torch, np)
 
     # ---- CPU oracle baseline on a bounded sample of the same workload
     if not args.no_cpu:
