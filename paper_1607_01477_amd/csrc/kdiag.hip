@@ -5,8 +5,8 @@
 // of U in LDS once and every wavefront solves a group of shifts against it.
 // Lane r of a group of nb lanes owns row r of the block, the pivot
 // U(r,r) - lambda_j is formed on the fly, and each of the nb sequential steps
-// broadcasts the new solution entry to the group (v_readlane for nb = 64,
-// ds_bpermute otherwise) followed by one complex multiply-add per lane (the
+// broadcasts the new solution entry to the group (v_readlane, or DPP
+// row_newbcast for nb = 16) followed by one complex multiply-add per lane (the
 // staged block is zero outside the rows a step updates, so no lane masking).
 // Several shifts are interleaved per wavefront to hide the step latency.
 //
@@ -71,15 +71,26 @@ __device__ inline double quotient(double a, double b) {
     return a / b;
 }
 
+// Value of lane i of each group of NB lanes, to every lane of that group.
+//   NB = 64: v_readlane into scalar registers (measured faster than a pair of
+//            readlanes plus a select for NB = 32, which uses ds_bpermute);
+//   NB = 16: DPP row_newbcast (one VALU move per 32-bit word) — needs i as an
+//            immediate, see bcast16 and BlockSolve::run.
 template <int NB>
 __device__ inline double bcast(double v, int i, int base) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
     if constexpr (NB == 64) {
-        int lo = __builtin_amdgcn_readlane(__double2loint(v), i);
-        int hi = __builtin_amdgcn_readlane(__double2hiint(v), i);
-        return __hiloint2double(hi, lo);
+        return __hiloint2double(__builtin_amdgcn_readlane(hi, i), __builtin_amdgcn_readlane(lo, i));
     } else {
         return __shfl(v, base + i, 64);
     }
+}
+
+template <int I>
+__device__ inline double bcast16(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + I, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + I, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
 }
 
 template <int NB>
@@ -169,15 +180,16 @@ struct BlockSolve {
         }
     }
 
-    __device__ __forceinline__ void step(const zd* Us, int i, int r, int base, double cn_l, int w,
-                                         double omega) {
+    template <typename BC>
+    __device__ __forceinline__ void step(const zd* Us, int i, int r, double cn_l, int w,
+                                         double omega, BC bc) {
         const zd u = Us[i * NB + r];
-        const double cni = SAFE ? bcast<NB>(cn_l, i, base) : 0.0;
+        const double cni = SAFE ? bc(cn_l) : 0.0;
 #pragma unroll
         for (int s = 0; s < SPW; ++s) {
             if (SAFE) {
-                const double cb = bcast<NB>(cabs1(br[s], bi[s]), i, base);
-                const double cd = bcast<NB>(cdl[s], i, base);
+                const double cb = bc(cabs1(br[s], bi[s]));
+                const double cd = bc(cdl[s]);
                 double M = quotient(cb, cd);
                 if (M >= omega) {
                     const bool ov = isinf(M);
@@ -187,7 +199,7 @@ struct BlockSolve {
                     kblk[s] += kk;
                     Gs[s] = ldexp(Gs[s], -kk);
                     if (ov) {
-                        M = quotient(bcast<NB>(cabs1(br[s], bi[s]), i, base), cd);
+                        M = quotient(bc(cabs1(br[s], bi[s])), cd);
                     } else {
                         M = ldexp(M, -kk);
                     }
@@ -201,8 +213,8 @@ struct BlockSolve {
                 xl_r = ldexp(xl_r, -pe[s]);
                 xl_i = ldexp(xl_i, -pe[s]);
             }
-            double xr = bcast<NB>(xl_r, i, base);
-            double xi = bcast<NB>(xl_i, i, base);
+            double xr = bc(xl_r);
+            double xi = bc(xl_i);
             if (SAFE) {
                 double Gn;
                 const int kk = bound_add(Gs[s], Ms[s], cni, w, omega, &Gn);
@@ -225,12 +237,25 @@ struct BlockSolve {
         }
     }
 
+    template <int I>
+    __device__ __forceinline__ void run16(const zd* Us, int bs, int r, double cn_l, int w,
+                                          double omega) {
+        // steps with compile-time lane index (DPP immediates): 15..0 forward, 0..15 adjoint
+        constexpr int STEP = ADJ ? I : 15 - I;
+        if (STEP < bs) step(Us, STEP, r, cn_l, w, omega, [](double v) { return bcast16<STEP>(v); });
+        if constexpr (I < 15) run16<I + 1>(Us, bs, r, cn_l, w, omega);
+    }
+
     __device__ __forceinline__ void run(const zd* Us, int bs, int r, int base, double cn_l, int w,
                                         double omega) {
-        if (!ADJ) {
-            for (int i = bs - 1; i >= 0; --i) step(Us, i, r, base, cn_l, w, omega);
+        if constexpr (NB == 16) {
+            run16<0>(Us, bs, r, cn_l, w, omega);
+        } else if (!ADJ) {
+            for (int i = bs - 1; i >= 0; --i)
+                step(Us, i, r, cn_l, w, omega, [&](double v) { return bcast<NB>(v, i, base); });
         } else {
-            for (int i = 0; i < bs; ++i) step(Us, i, r, base, cn_l, w, omega);
+            for (int i = 0; i < bs; ++i)
+                step(Us, i, r, cn_l, w, omega, [&](double v) { return bcast<NB>(v, i, base); });
         }
     }
 
@@ -459,12 +484,42 @@ __global__ __launch_bounds__(kWGB) void k_block(BlockArgs a) {
 
     const int grp = lane / NB, r = lane - grp * NB, base = grp * NB;
     const int lr = lane & 15, lq = lane >> 4;
+    constexpr int KS = NB / 4;
+    // U fragments of the update phase: A(row, k) for row = tile*16 + lane%16,
+    // k = 4 ks + lane/16 (forward: U(iS+row, i0+k); adjoint: conj(U(i0+k, iS+row)))
+    auto aload = [&](zd (&dst)[KS], int ubeg, int uend, int i0, int bs, int tile)
+        __attribute__((always_inline)) {
+        const int arow = ubeg + tile * 16 + lr;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int k = ks * 4 + lq;
+            zd v{0.0, 0.0};
+            if (k < bs && arow < uend) {
+                if (!ADJ) {
+                    v = a.U[(long)(i0 + k) * a.ldu + iS + arow];
+                } else {
+                    v = a.U[(long)(iS + arow) * a.ldu + i0 + k];
+                    v.im = -v.im;
+                }
+            }
+            dst[ks] = v;
+        }
+    };
+    zd af[KS], an[KS];
     for (int stp = 0; stp < nsub; ++stp) {
         const int ql = ADJ ? stp : nsub - 1 - stp;
         const int q = a.qa + ql;
         const int lr0 = ql * NB;
         const int i0 = iS + lr0;
         const int bs = min(NB, rows - lr0);
+        const int ubeg = ADJ ? lr0 + bs : 0;
+        const int uend = ADJ ? rows : lr0;
+        const int ntile = (uend - ubeg + 15) / 16;
+        // the first update tile's U fragments do not depend on this diagonal
+        // solve: load them now so the update phase starts without waiting
+        // (when registers allow: nb <= 32)
+        constexpr bool PREF = KS <= 8;
+        if (PREF && wave < ntile) aload(an, ubeg, uend, i0, bs, wave);
 
         // ---- diagonal block: each solving wavefront takes SPW * G shifts
         if (wave < AWAVES) {
@@ -514,40 +569,15 @@ __global__ __launch_bounds__(kWGB) void k_block(BlockArgs a) {
         if (stp + 1 < nsub) ustage_load(stp + 1);   // next diagonal block, in flight during the update
 
         // ---- rows of the outer block still to be solved: C -= U_panel * X(block)
-        const int ubeg = ADJ ? lr0 + bs : 0;
-        const int uend = ADJ ? rows : lr0;
-        const int ntile = (uend - ubeg + 15) / 16;
         if (wave < ntile) {
-            constexpr int KS = NB / 4;
             const int dsh = SAFE ? dkl[lr] : 0;
-            // next tile's U fragments are prefetched when registers allow (nb <= 32)
-            constexpr bool PREF = KS <= 8;
-            zd af[KS], an[KS];
-            auto aload = [&](zd (&dst)[KS], int tile) __attribute__((always_inline)) {
-                const int arow = ubeg + tile * 16 + lr;
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    const int k = ks * 4 + lq;
-                    zd v{0.0, 0.0};
-                    if (k < bs && arow < uend) {
-                        if (!ADJ) {
-                            v = a.U[(long)(i0 + k) * a.ldu + iS + arow];
-                        } else {
-                            v = a.U[(long)(iS + arow) * a.ldu + i0 + k];
-                            v.im = -v.im;
-                        }
-                    }
-                    dst[ks] = v;
-                }
-            };
-            if (PREF) aload(an, wave);
             for (int tile = wave; tile < ntile; tile += NWAVE) {
                 if (PREF) {
 #pragma unroll
                     for (int ks = 0; ks < KS; ++ks) af[ks] = an[ks];
-                    if (tile + NWAVE < ntile) aload(an, tile + NWAVE);
+                    if (tile + NWAVE < ntile) aload(an, ubeg, uend, i0, bs, tile + NWAVE);
                 } else {
-                    aload(af, tile);
+                    aload(af, ubeg, uend, i0, bs, tile);
                 }
                 const int rb = ubeg + tile * 16;
                 v4d accR, accI;
