@@ -20,6 +20,8 @@
 // receives a contiguous range of tiles.
 #include "common.h"
 
+#include <type_traits>
+
 namespace mst {
 namespace {
 
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
 
     // ---- accumulators start from C
     V accR[2][2], accI[2][2];
-    int clim0 = g.M, clim1 = g.M, blim0 = g.K, blim1 = g.K, dshq = -1;
+    int clim0 = g.M, clim1 = g.M, blim0 = g.K, blim1 = g.K;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int col = cw + j * 16 + lr;
@@ -374,68 +376,106 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
         }
     }
 
+    // Operand positions of this lane, clamped into the matrices so that every
+    // load is in bounds and none needs a branch: with straight-line loads the
+    // wait before each k-step covers only that step's loads, not the ones in
+    // flight for later steps. Elements outside the product are zeroed where
+    // they are consumed (the clamped load may return anything, even NaN).
     const int nks = (g.K + 3) / 4;
-    zd pa0[DEPTH], pa1[DEPTH], pb0[DEPTH], pb1[DEPTH];
-    int bsh0 = 0, bsh1 = 0;   // exponent shift of the B operand rows (safe), per column
-    auto load = [&](int ks, zd& a0, zd& a1, zd& b0, zd& b1) __attribute__((always_inline)) {
-        const int k = ks * 4 + lq;
-        const bool kin = k < g.K;
-        const bool fast = full && (ks * 4 + 4 <= g.K) && !VARLEN && !SAFE;
-        const zd* ap = A + (long)k * g.lda + rw + lr;
-        const zd* bp = B + (long)(cw + lr) * g.ldb + k;
-        a0 = zd{0.0, 0.0};
-        a1 = zd{0.0, 0.0};
-        b0 = zd{0.0, 0.0};
-        b1 = zd{0.0, 0.0};
-        if (fast || (kin && rw + lr < g.M)) a0 = ap[0];
-        if (fast || (kin && rw + 16 + lr < g.M)) a1 = ap[16];
-        if (fast || (k < blim0)) b0 = bp[0];
-        if (fast || (k < blim1)) b1 = bp[16 * g.ldb];
-        if (SAFE && g.kb != nullptr) {
-            // rows of one diagonal block share an exponent: look it up when the block changes
-            const int q = (g.b_row0 + k) / g.nb;
-            if (q != dshq) {
-                dshq = q;
-                const int col0 = cw + lr, col1 = cw + 16 + lr;
-                bsh0 = (col0 < g.N) ? g.kb[(long)g.q_cur * g.n_kb + col0] - g.kb[(long)q * g.n_kb + col0] : 0;
-                bsh1 = (col1 < g.N) ? g.kb[(long)g.q_cur * g.n_kb + col1] - g.kb[(long)q * g.n_kb + col1] : 0;
-            }
-            b0.re = ldexp(b0.re, -bsh0); b0.im = ldexp(b0.im, -bsh0);
-            b1.re = ldexp(b1.re, -bsh1); b1.im = ldexp(b1.im, -bsh1);
-        }
-    };
-#pragma unroll
-    for (int d = 0; d < DEPTH; ++d)
-        if (d < nks) load(d, pa0[d], pa1[d], pb0[d], pb1[d]);
-
-    for (int ks0 = 0; ks0 < nks; ks0 += DEPTH) {
-#pragma unroll
-        for (int d = 0; d < DEPTH; ++d) {
-            const int ks = ks0 + d;
-            if (ks < nks) {
-                const zd a0 = pa0[d], a1 = pa1[d], b0 = pb0[d], b1 = pb1[d];
-                if (ks + DEPTH < nks) load(ks + DEPTH, pa0[d], pa1[d], pb0[d], pb1[d]);
-                // acc = C - A B: A negated
-                const double a0r = -a0.re, a0i = -a0.im, a1r = -a1.re, a1i = -a1.im;
-                accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b0.re, accR[0][0], 0, 0, 0);
-                accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b1.re, accR[0][1], 0, 0, 0);
-                accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b0.re, accR[1][0], 0, 0, 0);
-                accR[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b1.re, accR[1][1], 0, 0, 0);
-                accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b0.im, accI[0][0], 0, 0, 0);
-                accI[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b1.im, accI[0][1], 0, 0, 0);
-                accI[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b0.im, accI[1][0], 0, 0, 0);
-                accI[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b1.im, accI[1][1], 0, 0, 0);
-                accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0i, b0.im, accR[0][0], 0, 0, 0);
-                accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0i, b1.im, accR[0][1], 0, 0, 0);
-                accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1i, b0.im, accR[1][0], 0, 0, 0);
-                accR[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1i, b1.im, accR[1][1], 0, 0, 0);
-                accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0i, b0.re, accI[0][0], 0, 0, 0);
-                accI[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0i, b1.re, accI[0][1], 0, 0, 0);
-                accI[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1i, b0.re, accI[1][0], 0, 0, 0);
-                accI[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1i, b1.re, accI[1][1], 0, 0, 0);
-            }
-        }
+    const int ra0 = min(rw + lr, g.M - 1), ra1 = min(rw + 16 + lr, g.M - 1);
+    const int cb0 = min(cw + lr, g.N - 1), cb1 = min(cw + 16 + lr, g.N - 1);
+    const bool oka0 = rw + lr < g.M, oka1 = rw + 16 + lr < g.M;
+    // safe form: exponent of the current outer block per column; the B rows of
+    // diagonal block q carry exponent kb[q] and are brought to it exactly
+    int kq0 = 0, kq1 = 0;
+    if (SAFE) {
+        kq0 = g.kb[(long)g.q_cur * g.n_kb + cb0];
+        kq1 = g.kb[(long)g.q_cur * g.n_kb + cb1];
     }
+
+    auto kloop = [&](auto mask_tag) __attribute__((always_inline)) {
+        constexpr bool MASK = decltype(mask_tag)::value;
+        zd pa0[DEPTH], pa1[DEPTH], pb0[DEPTH], pb1[DEPTH];
+        int qe0[DEPTH] = {}, qe1[DEPTH] = {};
+        auto load = [&](int ks, zd& a0, zd& a1, zd& b0, zd& b1, int& e0, int& e1)
+            __attribute__((always_inline)) {
+            const int k = MASK ? min(ks * 4 + lq, g.K - 1) : ks * 4 + lq;
+            const zd* ap = A + (long)k * g.lda;
+            a0 = ap[ra0];
+            a1 = ap[ra1];
+            b0 = B[(long)cb0 * g.ldb + k];
+            b1 = B[(long)cb1 * g.ldb + k];
+            if (SAFE) {
+                const int q = (g.b_row0 + k) / g.nb;
+                e0 = g.kb[(long)q * g.n_kb + cb0];
+                e1 = g.kb[(long)q * g.n_kb + cb1];
+            }
+        };
+        auto mma = [&](int ks, zd a0, zd a1, zd b0, zd b1, int e0, int e1)
+            __attribute__((always_inline)) {
+            if (MASK) {
+                const int k = ks * 4 + lq;
+                const bool kin = k < g.K;
+                const bool u0 = kin && oka0, u1 = kin && oka1, v0 = k < blim0, v1 = k < blim1;
+                a0.re = u0 ? a0.re : 0.0; a0.im = u0 ? a0.im : 0.0;
+                a1.re = u1 ? a1.re : 0.0; a1.im = u1 ? a1.im : 0.0;
+                b0.re = v0 ? b0.re : 0.0; b0.im = v0 ? b0.im : 0.0;
+                b1.re = v1 ? b1.re : 0.0; b1.im = v1 ? b1.im : 0.0;
+            }
+            if (SAFE) {
+                b0.re = ldexp(b0.re, e0 - kq0); b0.im = ldexp(b0.im, e0 - kq0);
+                b1.re = ldexp(b1.re, e1 - kq1); b1.im = ldexp(b1.im, e1 - kq1);
+            }
+            // acc = C - A B: A negated
+            const double a0r = -a0.re, a0i = -a0.im, a1r = -a1.re, a1i = -a1.im;
+            accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b0.re, accR[0][0], 0, 0, 0);
+            accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b1.re, accR[0][1], 0, 0, 0);
+            accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b0.re, accR[1][0], 0, 0, 0);
+            accR[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b1.re, accR[1][1], 0, 0, 0);
+            accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b0.im, accI[0][0], 0, 0, 0);
+            accI[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b1.im, accI[0][1], 0, 0, 0);
+            accI[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b0.im, accI[1][0], 0, 0, 0);
+            accI[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b1.im, accI[1][1], 0, 0, 0);
+            accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0i, b0.im, accR[0][0], 0, 0, 0);
+            accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0i, b1.im, accR[0][1], 0, 0, 0);
+            accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1i, b0.im, accR[1][0], 0, 0, 0);
+            accR[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1i, b1.im, accR[1][1], 0, 0, 0);
+            accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0i, b0.re, accI[0][0], 0, 0, 0);
+            accI[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0i, b1.re, accI[0][1], 0, 0, 0);
+            accI[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1i, b0.re, accI[1][0], 0, 0, 0);
+            accI[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1i, b1.re, accI[1][1], 0, 0, 0);
+        };
+        if (nks == 0) return;
+        // The ring is refilled without a condition (past the end the last
+        // k-step is loaded again, in bounds and unused), so the main loop is
+        // straight-line code; only the last nks % DEPTH steps are guarded.
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d)
+            load(min(d, nks - 1), pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
+        int ks0 = 0;
+        for (; ks0 + DEPTH <= nks; ks0 += DEPTH) {
+#pragma unroll
+            for (int d = 0; d < DEPTH; ++d) {
+                // Step d consumes ring slot d, then refills it. The scheduling
+                // fences pin that order: hoisting the refill above the products
+                // gives it other registers, and the copy back into the ring at
+                // the loop's end then waits for every load in flight; left free,
+                // the scheduler also gathers all refills at the end of the body.
+                mma(ks0 + d, pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
+                __builtin_amdgcn_sched_barrier(0);
+                load(min(ks0 + d + DEPTH, nks - 1), pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d)
+            if (ks0 + d < nks) mma(ks0 + d, pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
+    };
+    // interior tiles of the plain form need no masking at all
+    if (full && (g.K & 3) == 0 && !VARLEN && !SAFE)
+        kloop(std::false_type{});
+    else
+        kloop(std::true_type{});
 
     // ---- epilogue: lane holds column lane%16, rows lane/16 + 4 v of each 16 x 16 block
 #pragma unroll
