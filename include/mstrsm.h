@@ -62,7 +62,14 @@ typedef struct {
     int gemm_staged;   /* 0 (default): substitution GEMM without LDS staging (each wavefront
                           streams its operands from L1/L2); 1: LDS-staged GEMM. Same results
                           up to summation order; kept for testing. */
-    int reserved[2];
+    int overlap;       /* 0 (default): with fused outer blocks, the substitution of an outer
+                          block's solution into the rows of the next outer block up runs
+                          ahead on a second stream of the library, together with that
+                          block's diagonal solve, while the GEMM for all rows further up
+                          runs on the caller's stream (ordered by events; the call stays
+                          asynchronous on the caller's stream). -1: everything on the
+                          caller's stream. Results are identical bit for bit. */
+    int reserved[1];
 } mst_opts;
 
 /*

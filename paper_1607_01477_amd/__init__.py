@@ -33,8 +33,9 @@ def version() -> str:
 
 
 def _opts(nb=0, outer_nb=0, precision=0, max_sweeps=0, omega_log2=0, force_phase2=0, fuse=True,
-          staged=False):
+          staged=False, overlap=True):
     o = MstOpts()
+    o.overlap = 0 if overlap else -1
     o.gemm_staged = 1 if staged else 0
     o.nb, o.outer_nb, o.precision = int(nb), int(outer_nb), int(precision)
     o.max_sweeps, o.omega_log2, o.force_phase2 = int(max_sweeps), int(omega_log2), int(force_phase2)
@@ -107,7 +108,8 @@ def _mat(t: torch.Tensor, name: str) -> torch.Tensor:
     return colmajor(t)
 
 
-def mstrsm(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2, fuse=True, staged=False):
+def mstrsm(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2, fuse=True, staged=False,
+           overlap=True):
     """X with (U - shifts[j] I) X[:, j] = B[:, j]; B is overwritten when it is
     already column-major complex128 (the result is returned either way).
     precision=1: FP32 substitution GEMMs + FP64 refinement (max_sweeps)."""
@@ -118,14 +120,14 @@ def mstrsm(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2, fuse=Tr
         raise ValueError("U must be %d x %d" % (m, m))
     s = _vec(shifts, n, "shifts")
     o = _opts(nb=nb, outer_nb=outer_nb, precision=precision, max_sweeps=max_sweeps, fuse=fuse,
-              staged=staged)
+              staged=staged, overlap=overlap)
     rc = _lib.load().mstrsm(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), ctypes.byref(o), _stream())
     _lib.check("mstrsm", rc)
     return X
 
 
 def mstrsm_safe(U, shifts, B, col_len=None, *, nb=0, outer_nb=0, omega_log2=0, fuse=True,
-                staged=False):
+                staged=False, overlap=True):
     """Safe solve: returns (X, scale, scale_log2) with
     (U - shifts[j] I) X[:, j] = scale[j] B[:, j], scale[j] = 2^-scale_log2[j]."""
     U = _mat(U, "U")
@@ -137,14 +139,15 @@ def mstrsm_safe(U, shifts, B, col_len=None, *, nb=0, outer_nb=0, omega_log2=0, f
     cl = _vec(col_len, n, "col_len", torch.int32) if col_len is not None else None
     scale = torch.empty(n, dtype=torch.float64, device=X.device)
     klog = torch.empty(n, dtype=torch.int32, device=X.device)
-    o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2, fuse=fuse, staged=staged)
+    o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2, fuse=fuse, staged=staged,
+              overlap=overlap)
     rc = _lib.load().mstrsm_safe(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), _p(cl), _p(scale),
                                  _p(klog), ctypes.byref(o), _stream())
     _lib.check("mstrsm_safe", rc)
     return X, scale, klog
 
 
-def mstrsm_adjoint(U, shifts, G, *, nb=0, outer_nb=0, fuse=True):
+def mstrsm_adjoint(U, shifts, G, *, nb=0, outer_nb=0, fuse=True, overlap=True):
     """Y with (U - shifts[j] I)^H Y[:, j] = G[:, j] (G overwritten when column-major)."""
     U = _mat(U, "U")
     Y = _mat(G, "G")
@@ -152,7 +155,7 @@ def mstrsm_adjoint(U, shifts, G, *, nb=0, outer_nb=0, fuse=True):
     if U.shape != (m, m):
         raise ValueError("U must be %d x %d" % (m, m))
     s = _vec(shifts, n, "shifts")
-    o = _opts(nb=nb, outer_nb=outer_nb, fuse=fuse)
+    o = _opts(nb=nb, outer_nb=outer_nb, fuse=fuse, overlap=overlap)
     rc = _lib.load().mstrsm_adjoint(m, n, _p(U), _ld(U), _p(s), _p(Y), _ld(Y), ctypes.byref(o),
                                     _stream())
     _lib.check("mstrsm_adjoint", rc)

@@ -27,7 +27,8 @@ class MstOpts(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int), ("outer_nb", ctypes.c_int), ("precision", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("omega_log2", ctypes.c_int),
                 ("force_phase2", ctypes.c_int), ("fuse_blocks", ctypes.c_int),
-                ("gemm_staged", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
+                ("gemm_staged", ctypes.c_int), ("overlap", ctypes.c_int),
+                ("reserved", ctypes.c_int * 1)]
 
 
 class MstError(RuntimeError):

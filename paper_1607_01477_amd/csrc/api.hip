@@ -87,6 +87,7 @@ struct Opts {
     int nb = 32, outer = 256, precision = 0, sweeps = 2, omega_log2 = 960;
     bool fuse = true;
     int staged = 0;
+    bool overlap = true;
 };
 
 // position of opt in the caller's argument list, for error reporting
@@ -108,6 +109,8 @@ mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
     r.fuse = o->fuse_blocks == 0;
     if (o->gemm_staged != 0 && o->gemm_staged != 1) return bad(pos);
     r.staged = o->gemm_staged;
+    if (o->overlap != 0 && o->overlap != -1) return bad(pos);
+    r.overlap = o->overlap == 0;
     return MST_OK;
 }
 
@@ -134,6 +137,40 @@ hipError_t ws_get(Workspace& w, size_t count, T** out) {
     return w.get(count * sizeof(T), (void**)out);
 }
 
+// ---------------------------------------------------------------- lookahead stream
+// A second stream per thread and device for the lookahead chain, with events
+// to order it against the caller's stream. Created on first use and kept until
+// the process ends (default priority, non-blocking).
+struct Aux {
+    int dev = -1;
+    hipStream_t stream = nullptr;
+    std::vector<hipEvent_t> ev;
+};
+thread_local std::vector<Aux> t_aux;
+
+hipError_t aux_get(int nev, Aux** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    Aux* ax = nullptr;
+    for (Aux& a : t_aux)
+        if (a.dev == dev) ax = &a;
+    if (!ax) {
+        Aux a;
+        a.dev = dev;
+        if ((e = hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking)) != hipSuccess) return e;
+        t_aux.push_back(a);
+        ax = &t_aux.back();
+    }
+    while ((int)ax->ev.size() < nev) {
+        hipEvent_t ev = nullptr;
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+        ax->ev.push_back(ev);
+    }
+    *out = ax;
+    return hipSuccess;
+}
+
 // ---------------------------------------------------------------- forward block loop
 // FP64 (b32 == nullptr) or mixed: the right-hand side lives in W32 (FP32) for the
 // substitution GEMMs and the diagonal blocks write FP64 X into B.
@@ -144,24 +181,94 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
     const int nblk = (m + nb - 1) / nb;
     const int nob = (nblk + P - 1) / P;
     const bool mixed = W32 != nullptr;
-    const bool fused = o.fuse && o.outer <= block_rows_max();
-    for (int ob = nob - 1; ob >= 0; --ob) {
-        const int qa = ob * P, qb = (qa + P < nblk ? qa + P : nblk) - 1;
-        if (fused) {
-            BlockArgs b{};
-            b.m = m; b.n = n; b.nb = nb; b.qa = qa; b.iS = qa * nb;
-            b.rows = (((qb + 1) * nb < m) ? (qb + 1) * nb : m) - qa * nb;
-            b.U = U; b.ldu = ldu; b.lam = lam; b.B = B; b.ldb = ldb;
-            b.b32 = mixed ? W32 : nullptr; b.ldb32 = ldw;
-            b.col_len = col_len;
-            if (safe) {
-                b.safe = *safe;
-                b.use_safe = 1;
-            } else {
-                b.safe.omega_log2 = o.omega_log2;
+    const bool fused = o.fuse && o.outer <= block_rows_max() && block_fusable(o.nb);
+    auto q_first = [&](int ob) { return ob * P; };
+    auto q_last = [&](int ob) { return (ob * P + P < nblk ? ob * P + P : nblk) - 1; };
+    auto row_end = [&](int ob) { return ((q_last(ob) + 1) * nb < m) ? (q_last(ob) + 1) * nb : m; };
+
+    // B(r0:r1, :) -= U(r0:r1, x0:x1) X(x0:x1, :) with X the solved rows of outer
+    // block ob (x0:x1 are its rows); the safe form brings C from the exponent of
+    // the outer block below ob to that of ob
+    auto substitute = [&](int ob, int r0, int r1, hipStream_t st) -> hipError_t {
+        if (r1 <= r0) return hipSuccess;
+        const int qa = q_first(ob), qb = q_last(ob);
+        const int x0 = qa * nb, x1 = row_end(ob);
+        GemmArgs g{};
+        g.M = r1 - r0; g.N = n; g.K = x1 - x0;
+        g.op = GOP_SUB; g.staged = o.staged;
+        g.nb = nb; g.b_row0 = x0; g.c_row0 = r0; g.col_len = col_len;
+        if (safe) {
+            g.kb = safe->kb; g.n_kb = n; g.q_cur = qa; g.q_c = (qb + 1 < nblk) ? qb + 1 : -1;
+        }
+        if (!mixed) {
+            g.A = U + (long)x0 * ldu + r0; g.lda = ldu;
+            g.B = B + x0; g.ldb = ldb;
+            g.C = B + r0; g.ldc = ldb;
+            return timed(MST_PROF_GEMM_F64, gemm_flops(g), st, [&] { return launch_gemm_f64(g, st); });
+        }
+        g.A = U32 + (long)x0 * ldu32 + r0; g.lda = ldu32;
+        g.B = W32 + x0; g.ldb = ldw;
+        g.C = W32 + r0; g.ldc = ldw;
+        return timed(MST_PROF_GEMM_F32, gemm_flops(g), st, [&] { return launch_gemm_f32(g, st); });
+    };
+    // all diagonal blocks of outer block ob, with the substitution between them, in one kernel
+    auto solve_outer = [&](int ob, hipStream_t st) -> hipError_t {
+        const int qa = q_first(ob);
+        BlockArgs b{};
+        b.m = m; b.n = n; b.nb = nb; b.qa = qa; b.iS = qa * nb;
+        b.rows = row_end(ob) - qa * nb;
+        b.U = U; b.ldu = ldu; b.lam = lam; b.B = B; b.ldb = ldb;
+        b.b32 = mixed ? W32 : nullptr; b.ldb32 = ldw;
+        b.col_len = col_len;
+        if (safe) {
+            b.safe = *safe;
+            b.use_safe = 1;
+        } else {
+            b.safe.omega_log2 = o.omega_log2;
+        }
+        const double fl = 4.0 * b.rows * (double)b.rows * n;
+        return timed(MST_PROF_DIAG, fl, st, [&] { return launch_block(false, b, st); });
+    };
+
+    if (fused && o.overlap && nob > 2) {
+        // Lookahead. The library's second stream K carries the critical chain:
+        // X of outer block ob+1 into the rows of ob, then the solve of ob. The
+        // caller's stream S carries the bulk: X of ob into all rows above ob-1.
+        // Per element the updates keep their order (outer blocks bottom to
+        // top), so the result is that of the one-stream order bit for bit.
+        //   K, substitute(ob+1 -> rows of ob): after S's GEMM of ob+2, the last
+        //      earlier writer of those rows;
+        //   S, GEMM of ob: after K's solve of ob (it reads X of ob).
+        Aux* ax = nullptr;
+        hipError_t e = aux_get(2 * nob + 2, &ax);
+        if (e != hipSuccess) return e;
+        hipStream_t k = ax->stream;
+        hipEvent_t* evG = ax->ev.data();          // evG[ob]: S's GEMM of ob done
+        hipEvent_t* evK = ax->ev.data() + nob;    // evK[ob]: K's solve of ob done
+        hipEvent_t evFork = ax->ev[2 * nob], evJoin = ax->ev[2 * nob + 1];
+        if ((e = hipEventRecord(evFork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(k, evFork, 0)) != hipSuccess) return e;
+        for (int ob = nob - 1; ob >= 0; --ob) {
+            if (ob + 1 < nob) {
+                if (ob + 2 < nob && (e = hipStreamWaitEvent(k, evG[ob + 2], 0)) != hipSuccess) return e;
+                if ((e = substitute(ob + 1, q_first(ob) * nb, row_end(ob), k)) != hipSuccess) return e;
             }
-            const double fl = 4.0 * b.rows * (double)b.rows * n;
-            hipError_t e = timed(MST_PROF_DIAG, fl, s, [&] { return launch_block(false, b, s); });
+            if ((e = solve_outer(ob, k)) != hipSuccess) return e;
+            if ((e = hipEventRecord(evK[ob], k)) != hipSuccess) return e;
+            if (ob >= 2) {
+                if ((e = hipStreamWaitEvent(s, evK[ob], 0)) != hipSuccess) return e;
+                if ((e = substitute(ob, 0, q_first(ob - 1) * nb, s)) != hipSuccess) return e;
+                if ((e = hipEventRecord(evG[ob], s)) != hipSuccess) return e;
+            }
+        }
+        if ((e = hipEventRecord(evJoin, k)) != hipSuccess) return e;
+        return hipStreamWaitEvent(s, evJoin, 0);
+    }
+
+    for (int ob = nob - 1; ob >= 0; --ob) {
+        const int qa = q_first(ob), qb = q_last(ob);
+        if (fused) {
+            hipError_t e = solve_outer(ob, s);
             if (e != hipSuccess) return e;
         }
         for (int q = qb; q >= qa && !fused; --q) {
@@ -202,27 +309,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             }
         }
         if (qa > 0) {
-            const int r1 = qa * nb;
-            const int end = ((qb + 1) * nb < m) ? (qb + 1) * nb : m;
-            GemmArgs g{};
-            g.M = r1; g.N = n; g.K = end - r1;
-            g.op = GOP_SUB; g.staged = o.staged;
-            g.nb = nb; g.b_row0 = r1; g.c_row0 = 0; g.col_len = col_len;
-            if (safe) {
-                g.kb = safe->kb; g.n_kb = n; g.q_cur = qa; g.q_c = (qb + 1 < nblk) ? qb + 1 : -1;
-            }
-            hipError_t e;
-            if (!mixed) {
-                g.A = U + (long)r1 * ldu; g.lda = ldu;
-                g.B = B + r1; g.ldb = ldb;
-                g.C = B; g.ldc = ldb;
-                e = timed(MST_PROF_GEMM_F64, gemm_flops(g), s, [&] { return launch_gemm_f64(g, s); });
-            } else {
-                g.A = U32 + (long)r1 * ldu32; g.lda = ldu32;
-                g.B = W32 + r1; g.ldb = ldw;
-                g.C = W32; g.ldc = ldw;
-                e = timed(MST_PROF_GEMM_F32, gemm_flops(g), s, [&] { return launch_gemm_f32(g, s); });
-            }
+            hipError_t e = substitute(ob, 0, qa * nb, s);
             if (e != hipSuccess) return e;
         }
     }
@@ -235,7 +322,7 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
     const int nb = o.nb, P = o.outer / o.nb;
     const int nblk = (m + nb - 1) / nb;
     const int nob = (nblk + P - 1) / P;
-    const bool fused = o.fuse && o.outer <= block_rows_max();
+    const bool fused = o.fuse && o.outer <= block_rows_max() && block_fusable(o.nb);
     for (int ob = 0; ob < nob; ++ob) {
         const int qa = ob * P, qb = (qa + P < nblk ? qa + P : nblk) - 1;
         const int end = ((qb + 1) * nb < m) ? (qb + 1) * nb : m;

@@ -53,6 +53,7 @@ struct BlockArgs {
     int use_safe;
 };
 int block_rows_max();
+bool block_fusable(int nb);   // nb handled by the fused kernel (16 or 32)
 hipError_t launch_block(bool adjoint, const BlockArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- MFMA GEMM

@@ -93,6 +93,15 @@ __device__ inline double bcast16(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// bcast16 without a previous-value operand: row_newbcast writes every lane,
+// so no register has to be initialised for lanes the move would skip
+template <int I>
+__device__ inline double bcast16m(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + I, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + I, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 template <int NB>
 __device__ inline double group_max(double v) {
 #pragma unroll
@@ -180,10 +189,10 @@ struct BlockSolve {
         }
     }
 
+    // u: coefficient of unknown i in this lane's row (zero outside the rows the step updates)
     template <typename BC>
-    __device__ __forceinline__ void step(const zd* Us, int i, int r, double cn_l, int w,
+    __device__ __forceinline__ void step(const zd u, int i, int r, double cn_l, int w,
                                          double omega, BC bc) {
-        const zd u = Us[i * NB + r];
         const double cni = SAFE ? bc(cn_l) : 0.0;
 #pragma unroll
         for (int s = 0; s < SPW; ++s) {
@@ -238,24 +247,75 @@ struct BlockSolve {
     }
 
     template <int I>
-    __device__ __forceinline__ void run16(const zd* Us, int bs, int r, double cn_l, int w,
+    __device__ __forceinline__ void run16(const zd (&uu)[16], int bs, int r, double cn_l, int w,
                                           double omega) {
         // steps with compile-time lane index (DPP immediates): 15..0 forward, 0..15 adjoint
         constexpr int STEP = ADJ ? I : 15 - I;
-        if (STEP < bs) step(Us, STEP, r, cn_l, w, omega, [](double v) { return bcast16<STEP>(v); });
-        if constexpr (I < 15) run16<I + 1>(Us, bs, r, cn_l, w, omega);
+        if (STEP < bs) step(uu[STEP], STEP, r, cn_l, w, omega, [](double v) { return bcast16<STEP>(v); });
+        if constexpr (I < 15) run16<I + 1>(uu, bs, r, cn_l, w, omega);
     }
 
+    // Plain solve, nb = 16, rows scaled by their pivot reciprocals first:
+    // with b'(r) = b(r)/d(r) and u'(r,i) = u(r,i)/d(r) the substitution is
+    // x(i) = b'(i), b'(r) -= u'(r,i) x(i) — the same quotients, computed off the
+    // dependent chain, which is then one broadcast and one complex
+    // multiply-add per step. Lane i keeps x(i) unchanged (u'(i,i) = 0), and
+    // steps past a partial block move zeros (b = 0 there, u = 0), so all 16
+    // steps run unconditionally.
+    template <int I>
+    __device__ __forceinline__ void run16s(const zd (&uu)[16]) {
+        constexpr int STEP = ADJ ? I : 15 - I;
+#pragma unroll
+        for (int s = 0; s < SPW; ++s) {
+            const double xr = bcast16m<STEP>(br[s]), xi = bcast16m<STEP>(bi[s]);
+            br[s] = fma(-uu[STEP].re, xr, fma(uu[STEP].im, xi, br[s]));
+            bi[s] = fma(-uu[STEP].re, xi, fma(-uu[STEP].im, xr, bi[s]));
+        }
+        if constexpr (I < 15) run16s<I + 1>(uu);
+    }
+
+    // The coefficients come from LDS ahead of the dependent chain of steps:
+    // all nb of them for nb = 16, one step ahead otherwise.
     __device__ __forceinline__ void run(const zd* Us, int bs, int r, int base, double cn_l, int w,
                                         double omega) {
-        if constexpr (NB == 16) {
-            run16<0>(Us, bs, r, cn_l, w, omega);
+        if constexpr (NB == 16 && !SAFE && SPW == 1) {
+            zd uu[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) uu[i] = Us[i * NB + r];
+            // b' = b / d, u' = u / d (pr, pi: 1 / d of this lane's row)
+            const double b_r = br[0], b_i = bi[0];
+            br[0] = fma(b_r, pr[0], -b_i * pi[0]);
+            bi[0] = fma(b_r, pi[0], b_i * pr[0]);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const double u_r = uu[i].re, u_i = uu[i].im;
+                uu[i].re = fma(u_r, pr[0], -u_i * pi[0]);
+                uu[i].im = fma(u_r, pi[0], u_i * pr[0]);
+            }
+            run16s<0>(uu);
+        } else if constexpr (NB == 16) {
+            zd uu[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) uu[i] = Us[i * NB + r];
+            // keep the loads here: left alone the compiler sinks each into its
+            // step's branch and every step then waits for LDS
+#pragma unroll
+            for (int i = 0; i < 16; ++i) asm volatile("" : "+v"(uu[i].re), "+v"(uu[i].im));
+            run16<0>(uu, bs, r, cn_l, w, omega);
         } else if (!ADJ) {
-            for (int i = bs - 1; i >= 0; --i)
-                step(Us, i, r, cn_l, w, omega, [&](double v) { return bcast<NB>(v, i, base); });
+            zd un = Us[(bs - 1) * NB + r];
+            for (int i = bs - 1; i >= 0; --i) {
+                const zd u = un;
+                un = Us[(i > 0 ? i - 1 : 0) * NB + r];
+                step(u, i, r, cn_l, w, omega, [&](double v) { return bcast<NB>(v, i, base); });
+            }
         } else {
-            for (int i = 0; i < bs; ++i)
-                step(Us, i, r, cn_l, w, omega, [&](double v) { return bcast<NB>(v, i, base); });
+            zd un = Us[r];
+            for (int i = 0; i < bs; ++i) {
+                const zd u = un;
+                un = Us[(i + 1 < bs ? i + 1 : i) * NB + r];
+                step(u, i, r, cn_l, w, omega, [&](double v) { return bcast<NB>(v, i, base); });
+            }
         }
     }
 
@@ -368,25 +428,65 @@ __global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
     }
 }
 
+// b(r) -= sum_k uo(k) x(k) for nb = 16, x(k) held by lane k of each 16-lane
+// group (DPP broadcast); two partial sums per shift
+template <int SPW, int K>
+__device__ __forceinline__ void couple16(const zd (&uo)[16], const double (&xr)[SPW],
+                                         const double (&xi)[SPW], double (&ar)[SPW][2],
+                                         double (&ai)[SPW][2]) {
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+        const double yr = bcast16<K>(xr[s]), yi = bcast16<K>(xi[s]);
+        ar[s][K & 1] = fma(uo[K].re, yr, fma(-uo[K].im, yi, ar[s][K & 1]));
+        ai[s][K & 1] = fma(uo[K].re, yi, fma(uo[K].im, yr, ai[s][K & 1]));
+    }
+    if constexpr (K < 15) couple16<SPW, K + 1>(uo, xr, xi, ar, ai);
+}
+
 // ---------------------------------------------------------------- fused outer block
 constexpr int kRowsMax = 256;          // rows of one outer block
 constexpr int kCols = 16;              // shifts per workgroup
 constexpr int kSP = kRowsMax + 1;      // padded LDS column stride (bank spread)
-constexpr int kWGB = 512;              // threads of the fused kernel (2 wavefronts per SIMD)
+// threads of the fused kernel: 4 solving wavefronts plus 8 updating ones for
+// the plain forward solve with nb = 16 (three wavefronts per SIMD, two of them
+// on the matrix cores); 4 plus 4 where the register use leaves room for two
+// wavefronts per SIMD only (nb = 32, safe, adjoint)
+constexpr int block_threads(int nb, bool adj, bool safe) {
+    return (nb == 16 && !adj && !safe) ? 768 : 512;
+}
+constexpr int kAW = 4;                 // wavefronts that solve diagonal blocks; the others update
 
+// One outer block (rows [iS, iS+rows)) for kCols shifts, with the right-hand
+// sides resident in LDS. Diagonal blocks are solved one per round with a
+// one-block lookahead: in the round that solves block q, the solving
+// wavefronts first apply the solution of the block solved in the round before
+// (block p, adjacent to q) to q's own rows (a short product with the coupling
+// block U(q, p), staged in LDS) and then run the back substitution of q, while
+// the other wavefronts apply the same solution of p to all rows of the outer
+// block beyond q with FP64 MFMA products. The two parts touch disjoint rows, so
+// each round needs one barrier, and the matrix-core work runs beside the
+// latency-bound substitution instead of after it. Diagonal and coupling blocks
+// of the next round are loaded during the current one (double-buffered LDS).
+// Per element the updates keep the order of the blocks.
 template <int NB, bool ADJ, bool SAFE, bool MIXED, bool VARLEN>
-__global__ __launch_bounds__(kWGB) void k_block(BlockArgs a) {
+__global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArgs a) {
+    static_assert(NB == 16 || NB == 32, "fused outer block: nb 16 or 32");
     constexpr int G = 64 / NB;
+    constexpr int kWGB = block_threads(NB, ADJ, SAFE);
     constexpr int NWAVE = kWGB / 64;
-    constexpr int AWAVES = (NB == 16) ? 4 : NWAVE;       // wavefronts solving diagonal blocks
-    constexpr int SPW = kCols / (AWAVES * G);            // interleaved shifts per lane group
-    constexpr int PERU = (NB * NB + kWGB - 1) / kWGB;    // diagonal-block elements per thread
-    static_assert(SPW * G * AWAVES == kCols, "column split");
+    constexpr int NUW = NWAVE - kAW;                     // updating wavefronts
+    constexpr int SPW = kCols / (kAW * G);               // interleaved shifts per lane group
+    constexpr int NBB = NB * NB;
+    constexpr int PERS = (2 * NBB + kWGB - 1) / kWGB;    // staged elements per thread
+    constexpr int KS = NB / 4;
+    static_assert(SPW * G * kAW == kCols, "column split");
     __shared__ zd Bl[kCols * kSP];
-    __shared__ zd Us[NB * NB];
-    __shared__ zd Ud[NB];
+    __shared__ zd Us[2][NBB];      // diagonal block, strict triangle (see stage_diag)
+    __shared__ zd Uo[2][NBB];      // coupling block: Uo[k*NB + r] = coefficient of x_p(k) in row r of q
+    __shared__ zd Ud[2][NB];
     __shared__ double Gl[kCols];
-    __shared__ int kcl[kCols], dkl[kCols], Ll[kCols];
+    __shared__ int kcl[kCols], dkl[2][kCols], Ll[kCols];
+    __shared__ int tctr[2];        // next update tile to claim, per round parity
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col0 = blockIdx.x * kCols;
@@ -395,6 +495,7 @@ __global__ __launch_bounds__(kWGB) void k_block(BlockArgs a) {
     const double omega = ldexp(1.0, w);
     const double delta = SAFE ? *a.safe.delta : 0.0;
 
+    if (tid == 0) tctr[0] = NUW;
     if (tid < kCols) {
         const int j = col0 + tid;
         int L = 0;
@@ -406,7 +507,8 @@ __global__ __launch_bounds__(kWGB) void k_block(BlockArgs a) {
             }
         }
         Ll[tid] = L;
-        dkl[tid] = 0;
+        dkl[0][tid] = 0;
+        dkl[1][tid] = 0;
         if (SAFE) {
             Gl[tid] = (j < a.n) ? a.safe.G[j] : 0.0;
             kcl[tid] = (j < a.n) ? a.safe.kcur[j] : 0;
@@ -414,7 +516,7 @@ __global__ __launch_bounds__(kWGB) void k_block(BlockArgs a) {
     }
     // right-hand sides of the outer block -> LDS (rows outside the column: 0)
     {
-        constexpr int PER = kCols * kRowsMax / kWGB;
+        constexpr int PER = (kCols * kRowsMax + kWGB - 1) / kWGB;
         zd st[PER];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
@@ -422,7 +524,7 @@ __global__ __launch_bounds__(kWGB) void k_block(BlockArgs a) {
             const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
             const int j = col0 + c;
             int L = 0;
-            if (j < a.n) {
+            if (idx < kCols * kRowsMax && j < a.n) {
                 L = a.m;
                 if (VARLEN) {
                     L = a.col_len[j];
@@ -443,106 +545,198 @@ __global__ __launch_bounds__(kWGB) void k_block(BlockArgs a) {
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * kWGB;
             const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
-            Bl[c * kSP + rr] = st[e];
+            if (idx < kCols * kRowsMax) Bl[c * kSP + rr] = st[e];
         }
     }
 
-    // diagonal block staging: loads into registers, stores to LDS later
+    // ---- geometry of round stp: block ql solved, block qp (solved in the round
+    // before) applied; rows of the outer block relative to iS
     const int nsub = (rows + NB - 1) / NB;
-    zd ust[PERU];
-    auto ustage_load = [&](int stp) __attribute__((always_inline)) {
-        const int ql = ADJ ? stp : nsub - 1 - stp;
-        const int i0 = iS + ql * NB, bs = min(NB, rows - ql * NB);
-#pragma unroll
-        for (int e = 0; e < PERU; ++e) {
-            const int t = tid + e * kWGB;
-            const int c = t / NB, rr = t - c * NB;
-            ust[e] = zd{0.0, 0.0};
-            if (t < NB * NB && rr <= c && c < bs) ust[e] = a.U[(long)(i0 + c) * a.ldu + i0 + rr];
-        }
+    struct Round {
+        int lr0, bs;      // rows of the block solved in this round
+        int p0, bsp;      // rows of the block applied in this round (bsp = 0: none)
+        int ubeg, uend;   // rows updated by the matrix cores in this round
     };
-    auto ustage_store = [&]() __attribute__((always_inline)) {
+    auto round_of = [&](int stp) __attribute__((always_inline)) {
+        Round g;
+        const int ql = ADJ ? stp : nsub - 1 - stp;
+        g.lr0 = ql * NB;
+        g.bs = min(NB, rows - g.lr0);
+        if (stp > 0) {
+            const int qp = ADJ ? ql - 1 : ql + 1;
+            g.p0 = qp * NB;
+            g.bsp = min(NB, rows - g.p0);
+            g.ubeg = ADJ ? g.lr0 + g.bs : 0;
+            g.uend = ADJ ? rows : g.lr0;
+        } else {
+            g.p0 = g.lr0;
+            g.bsp = 0;
+            g.ubeg = g.uend = 0;
+        }
+        return g;
+    };
+
+    // ---- staging of the diagonal and coupling blocks of a round: loads into
+    // registers, stores to LDS later (the latency hides behind a round's work)
+    zd ust[PERS];
+    auto stage_load = [&](int stp) __attribute__((always_inline)) {
+        const Round g = round_of(stp);
+        const int i0 = iS + g.lr0, p0 = iS + g.p0;
 #pragma unroll
-        for (int e = 0; e < PERU; ++e) {
+        for (int e = 0; e < PERS; ++e) {
             const int t = tid + e * kWGB;
-            if (t >= NB * NB) continue;
-            const int c = t / NB, rr = t - c * NB;
-            const zd v = ADJ ? zd{ust[e].re, -ust[e].im} : ust[e];
-            if (rr == c) {
-                Ud[rr] = v;
-                Us[c * NB + rr] = zd{0.0, 0.0};
-            } else if (!ADJ) {
-                Us[c * NB + rr] = v;
-            } else {
-                Us[rr * NB + c] = v;
+            ust[e] = zd{0.0, 0.0};
+            if (t < NBB) {
+                const int c = t / NB, rr = t - c * NB;
+                if (rr <= c && c < g.bs) ust[e] = a.U[(long)(i0 + c) * a.ldu + i0 + rr];
+            } else if (t < 2 * NBB) {
+                const int t2 = t - NBB;
+                if (!ADJ) {
+                    // coefficient of x_p(k) in row r: U(i0 + r, p0 + k)
+                    const int k = t2 / NB, r = t2 - k * NB;
+                    if (r < g.bs && k < g.bsp) ust[e] = a.U[(long)(p0 + k) * a.ldu + i0 + r];
+                } else {
+                    // adjoint: conj(U(p0 + k, i0 + r))
+                    const int r = t2 / NB, k = t2 - r * NB;
+                    if (r < g.bs && k < g.bsp) {
+                        const zd v = a.U[(long)(i0 + r) * a.ldu + p0 + k];
+                        ust[e] = zd{v.re, -v.im};
+                    }
+                }
             }
         }
     };
-    ustage_load(0);
-    ustage_store();
+    auto stage_store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int e = 0; e < PERS; ++e) {
+            const int t = tid + e * kWGB;
+            if (t < NBB) {
+                const int c = t / NB, rr = t - c * NB;
+                const zd v = ADJ ? zd{ust[e].re, -ust[e].im} : ust[e];
+                if (rr == c) {
+                    Ud[buf][rr] = v;
+                    Us[buf][c * NB + rr] = zd{0.0, 0.0};
+                } else if (!ADJ) {
+                    Us[buf][c * NB + rr] = v;
+                } else {
+                    Us[buf][rr * NB + c] = v;
+                }
+            } else if (t < 2 * NBB) {
+                const int t2 = t - NBB;
+                int k, r;
+                if (!ADJ) {
+                    k = t2 / NB;
+                    r = t2 - k * NB;
+                } else {
+                    r = t2 / NB;
+                    k = t2 - r * NB;
+                }
+                Uo[buf][k * NB + r] = ust[e];
+            }
+        }
+    };
+    stage_load(0);
+    stage_store(0);
     __syncthreads();
 
     const int grp = lane / NB, r = lane - grp * NB, base = grp * NB;
     const int lr = lane & 15, lq = lane >> 4;
-    constexpr int KS = NB / 4;
-    // U fragments of the update phase: A(row, k) for row = tile*16 + lane%16,
-    // k = 4 ks + lane/16 (forward: U(iS+row, i0+k); adjoint: conj(U(i0+k, iS+row)))
-    auto aload = [&](zd (&dst)[KS], int ubeg, int uend, int i0, int bs, int tile)
-        __attribute__((always_inline)) {
-        const int arow = ubeg + tile * 16 + lr;
+    // solving wavefronts: fixed column slots
+    int cc[SPW];
+    zd lam[SPW];
+    bool jv[SPW];
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+        const int c = ((wave % kAW) * SPW + s) * G + grp;
+        cc[s] = c;
+        jv[s] = col0 + c < a.n;
+        lam[s] = (wave < kAW && jv[s]) ? a.lam[col0 + c] : zd{0.0, 0.0};
+    }
+
+    // U fragments of the matrix-core update: A(row, k) for row = ubeg + tile*16 +
+    // lane%16, k = 4 ks + lane/16 (forward: U(iS+row, iS+p0+k); adjoint:
+    // conj(U(iS+p0+k, iS+row)))
+    auto aload = [&](zd (&dst)[KS], const Round& g, int tile) __attribute__((always_inline)) {
+        const int arow = g.ubeg + tile * 16 + lr;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int k = ks * 4 + lq;
             zd v{0.0, 0.0};
-            if (k < bs && arow < uend) {
+            if (k < g.bsp && arow < g.uend) {
                 if (!ADJ) {
-                    v = a.U[(long)(i0 + k) * a.ldu + iS + arow];
+                    v = a.U[(long)(iS + g.p0 + k) * a.ldu + iS + arow];
                 } else {
-                    v = a.U[(long)(iS + arow) * a.ldu + i0 + k];
+                    v = a.U[(long)(iS + arow) * a.ldu + iS + g.p0 + k];
                     v.im = -v.im;
                 }
             }
             dst[ks] = v;
         }
     };
-    zd af[KS], an[KS];
-    for (int stp = 0; stp < nsub; ++stp) {
-        const int ql = ADJ ? stp : nsub - 1 - stp;
-        const int q = a.qa + ql;
-        const int lr0 = ql * NB;
-        const int i0 = iS + lr0;
-        const int bs = min(NB, rows - lr0);
-        const int ubeg = ADJ ? lr0 + bs : 0;
-        const int uend = ADJ ? rows : lr0;
-        const int ntile = (uend - ubeg + 15) / 16;
-        // the first update tile's U fragments do not depend on this diagonal
-        // solve: load them now so the update phase starts without waiting
-        // (when registers allow: nb <= 32)
-        constexpr bool PREF = KS <= 8;
-        if (PREF && wave < ntile) aload(an, ubeg, uend, i0, bs, wave);
+    zd an[KS];   // first fragment of a round, loaded at the end of the round before
+    double xpr[SPW], xpi[SPW];   // solving wavefronts: solution of the block of the round before
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) xpr[s] = xpi[s] = 0.0;
 
-        // ---- diagonal block: each solving wavefront takes SPW * G shifts
-        if (wave < AWAVES) {
+    for (int stp = 0; stp < nsub; ++stp) {
+        const int buf = stp & 1;
+        const Round g = round_of(stp);
+        const int q = a.qa + (ADJ ? stp : nsub - 1 - stp);
+        const int i0 = iS + g.lr0;
+        if (stp + 1 < nsub) stage_load(stp + 1);
+
+        if (wave < kAW) {
+            // ---- rows of block q: apply x of block p, then back substitution
             BlockSolve<NB, SPW, ADJ, SAFE> S;
-            int cc[SPW];
-            zd lam[SPW];
-            bool jv[SPW], act[SPW];
+            bool act[SPW];
 #pragma unroll
             for (int s = 0; s < SPW; ++s) {
-                const int c = (wave * SPW + s) * G + grp;
-                const int j = col0 + c;
-                cc[s] = c;
-                jv[s] = j < a.n;
+                const int c = cc[s];
                 act[s] = jv[s] && (i0 < Ll[c]);
-                lam[s] = jv[s] ? a.lam[j] : zd{0.0, 0.0};
                 zd b{0.0, 0.0};
-                if (r < bs) b = Bl[c * kSP + lr0 + r];
+                if (r < g.bs) b = Bl[c * kSP + g.lr0 + r];
+                if (SAFE && g.bsp > 0) {
+                    // the rows still carry the exponent from before block p
+                    const int dk = dkl[buf ^ 1][c];
+                    b.re = ldexp(b.re, -dk);
+                    b.im = ldexp(b.im, -dk);
+                }
                 S.br[s] = b.re;
                 S.bi[s] = b.im;
             }
-            const double cn_l = (SAFE && r < bs) ? a.safe.cn_in[i0 + r] : 0.0;
-            S.pivots(Ud, r, bs, lam, jv, delta);
-            S.run(Us, bs, r, base, cn_l, w, omega);
+            if (g.bsp > 0) {
+                // b(r) -= sum_k Uo(r, k) x_p(k), two partial sums per shift
+                double ar[SPW][2], ai[SPW][2];
+#pragma unroll
+                for (int s = 0; s < SPW; ++s) ar[s][0] = ar[s][1] = ai[s][0] = ai[s][1] = 0.0;
+                if constexpr (NB == 16) {
+                    // x_p(k) is still in lane k of each group from the round before
+                    zd uo[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) uo[k] = Uo[buf][k * NB + r];
+                    couple16<SPW, 0>(uo, xpr, xpi, ar, ai);
+                } else {
+                    // x_p(k) from LDS: one address per lane group (a broadcast read)
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) {
+                        const zd u = Uo[buf][k * NB + r];
+#pragma unroll
+                        for (int s = 0; s < SPW; ++s) {
+                            const zd x = Bl[cc[s] * kSP + g.p0 + k];
+                            ar[s][k & 1] = fma(u.re, x.re, fma(-u.im, x.im, ar[s][k & 1]));
+                            ai[s][k & 1] = fma(u.re, x.im, fma(u.im, x.re, ai[s][k & 1]));
+                        }
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < SPW; ++s) {
+                    S.br[s] -= ar[s][0] + ar[s][1];
+                    S.bi[s] -= ai[s][0] + ai[s][1];
+                }
+            }
+            const double cn_l = (SAFE && r < g.bs) ? a.safe.cn_in[i0 + r] : 0.0;
+            S.pivots(Ud[buf], r, g.bs, lam, jv, delta);
+            S.run(Us[buf], g.bs, r, base, cn_l, w, omega);
             if (SAFE) {
                 const double asum = a.safe.above_sum[q];
 #pragma unroll
@@ -556,62 +750,87 @@ __global__ __launch_bounds__(kWGB) void k_block(BlockArgs a) {
                             Gl[c] = S.Gs[s];
                             kcl[c] = kc;
                         }
-                        dkl[c] = dk;
+                        dkl[buf][c] = dk;
                         a.safe.kb[(long)q * a.n + col0 + c] = kc;
                     }
                 }
             }
 #pragma unroll
-            for (int s = 0; s < SPW; ++s)
-                if (r < bs) Bl[cc[s] * kSP + lr0 + r] = zd{S.br[s], S.bi[s]};
+            for (int s = 0; s < SPW; ++s) {
+                if (r < g.bs) Bl[cc[s] * kSP + g.lr0 + r] = zd{S.br[s], S.bi[s]};
+                xpr[s] = S.br[s];
+                xpi[s] = S.bi[s];
+            }
         }
-        __syncthreads();
-        if (stp + 1 < nsub) ustage_load(stp + 1);   // next diagonal block, in flight during the update
-
-        // ---- rows of the outer block still to be solved: C -= U_panel * X(block)
-        if (wave < ntile) {
-            const int dsh = SAFE ? dkl[lr] : 0;
-            for (int tile = wave; tile < ntile; tile += NWAVE) {
-                if (PREF) {
-#pragma unroll
-                    for (int ks = 0; ks < KS; ++ks) af[ks] = an[ks];
-                    if (tile + NWAVE < ntile) aload(an, ubeg, uend, i0, bs, tile + NWAVE);
-                } else {
-                    aload(af, ubeg, uend, i0, bs, tile);
-                }
-                const int rb = ubeg + tile * 16;
-                v4d accR, accI;
+        // ---- rows beyond block q: C -= U_panel * x(block p) on the matrix cores.
+        // Tiles 0 .. NUW-1 go to the updating wavefronts (first fragment
+        // prefetched in the round before); the rest are claimed from a counter
+        // by whichever wavefront is free, the solving ones after their solve.
+        {
+            const int ntile = (g.uend - g.ubeg + 15) / 16;
+            const int dsh = (SAFE && g.bsp > 0) ? dkl[buf ^ 1][lr] : 0;
+            auto claim = [&]() __attribute__((always_inline)) {
+                int t = 0;
+                if (lane == 0) t = atomicAdd(&tctr[buf], 1);
+                return __builtin_amdgcn_readfirstlane(t);
+            };
+            auto do_tile = [&](int tile, const zd (&af)[KS]) __attribute__((always_inline)) {
+                const int rb = g.ubeg + tile * 16;
+                // Every LDS read below is in bounds (rows < 256) and needs no
+                // branch: rows past the outer block are zero in Bl, and the
+                // tiles never reach into the block being solved. Unguarded
+                // reads issue together instead of one wait per branch.
+                // Four accumulator chains (real and imaginary parts, each split
+                // in two) keep dependent matrix-core products apart; the halves
+                // are added at the end.
+                v4d accR, accI, accR2, accI2;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = rb + lq + 4 * v;
-                    zd c{0.0, 0.0};
-                    if (row < uend) c = Bl[lr * kSP + row];
+                    zd c = Bl[lr * kSP + row];
                     if (SAFE) {
                         c.re = ldexp(c.re, -dsh);
                         c.im = ldexp(c.im, -dsh);
                     }
                     accR[v] = c.re;
                     accI[v] = c.im;
+                    accR2[v] = 0.0;
+                    accI2[v] = 0.0;
                 }
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
-                    // X(block) fragment from LDS: row k = 4 ks + lane/16, column lane%16
+                    // x(block p) fragment from LDS: row k = 4 ks + lane/16, column lane%16
                     const int k = ks * 4 + lq;
-                    const zd xb = (k < bs) ? Bl[lr * kSP + lr0 + k] : zd{0.0, 0.0};
+                    const zd xb = Bl[lr * kSP + g.p0 + k];
                     const double ar = -af[ks].re, ai = -af[ks].im;
                     accR = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb.re, accR, 0, 0, 0);
                     accI = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb.im, accI, 0, 0, 0);
-                    accR = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, xb.im, accR, 0, 0, 0);
-                    accI = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xb.re, accI, 0, 0, 0);
+                    accR2 = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, xb.im, accR2, 0, 0, 0);
+                    accI2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xb.re, accI2, 0, 0, 0);
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = rb + lq + 4 * v;
-                    if (row < uend) Bl[lr * kSP + row] = zd{accR[v], accI[v]};
+                    if (row < g.uend) Bl[lr * kSP + row] = zd{accR[v] + accR2[v], accI[v] + accI2[v]};
                 }
+            };
+            int cur = (wave >= kAW) ? wave - kAW : claim();
+            if (wave < kAW && cur < ntile) aload(an, g, cur);
+            zd af[KS];
+            while (cur < ntile) {
+                const int nxt = claim();
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) af[ks] = an[ks];
+                if (nxt < ntile) aload(an, g, nxt);
+                do_tile(cur, af);
+                cur = nxt;
             }
+            // first fragment of the next round, in flight across the barrier
+            if (wave >= kAW && stp + 1 < nsub) aload(an, round_of(stp + 1), wave - kAW);
+            // counter of the next round (its last use was before the barrier behind us)
+            if (tid == 0) tctr[buf ^ 1] = NUW;
         }
-        if (stp + 1 < nsub) ustage_store();
+        if (stp + 1 < nsub) stage_store(buf ^ 1);
         __syncthreads();
     }
 
@@ -621,13 +840,13 @@ __global__ __launch_bounds__(kWGB) void k_block(BlockArgs a) {
         a.safe.kcur[col0 + tid] = kcl[tid];
     }
     {
-        constexpr int PER = kCols * kRowsMax / kWGB;
+        constexpr int PER = (kCols * kRowsMax + kWGB - 1) / kWGB;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * kWGB;
             const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
             const int j = col0 + c;
-            if (j < a.n && rr < rows && iS + rr < Ll[c]) {
+            if (idx < kCols * kRowsMax && j < a.n && rr < rows && iS + rr < Ll[c]) {
                 const zd v = Bl[c * kSP + rr];
                 a.B[(long)j * a.ldb + iS + rr] = v;
                 if (MIXED) a.b32[(long)j * a.ldb32 + iS + rr] = zf{(float)v.re, (float)v.im};
@@ -670,19 +889,19 @@ hipError_t launch_blk(const BlockArgs& a, hipStream_t s) {
     const bool varlen = a.col_len != nullptr;
     if (ADJ) {
         if (safe || mixed || varlen) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_block<NB, true, false, false, false>), grid, dim3(kWGB), 0, s, a);
+        hipLaunchKernelGGL((k_block<NB, true, false, false, false>), grid, dim3(block_threads(NB, true, false)), 0, s, a);
     } else if (safe) {
         if (mixed) return hipErrorInvalidValue;
         if (varlen)
-            hipLaunchKernelGGL((k_block<NB, false, true, false, true>), grid, dim3(kWGB), 0, s, a);
+            hipLaunchKernelGGL((k_block<NB, false, true, false, true>), grid, dim3(block_threads(NB, false, true)), 0, s, a);
         else
-            hipLaunchKernelGGL((k_block<NB, false, true, false, false>), grid, dim3(kWGB), 0, s, a);
+            hipLaunchKernelGGL((k_block<NB, false, true, false, false>), grid, dim3(block_threads(NB, false, true)), 0, s, a);
     } else {
         if (varlen) return hipErrorInvalidValue;
         if (mixed)
-            hipLaunchKernelGGL((k_block<NB, false, false, true, false>), grid, dim3(kWGB), 0, s, a);
+            hipLaunchKernelGGL((k_block<NB, false, false, true, false>), grid, dim3(block_threads(NB, false, false)), 0, s, a);
         else
-            hipLaunchKernelGGL((k_block<NB, false, false, false, false>), grid, dim3(kWGB), 0, s, a);
+            hipLaunchKernelGGL((k_block<NB, false, false, false, false>), grid, dim3(block_threads(NB, false, false)), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -701,10 +920,11 @@ hipError_t launch_diag(int nb, bool adjoint, const DiagArgs& a, hipStream_t s) {
 
 int block_rows_max() { return kRowsMax; }
 
+bool block_fusable(int nb) { return nb == 16 || nb == 32; }
+
 hipError_t launch_block(bool adjoint, const BlockArgs& a, hipStream_t s) {
     if (a.rows <= 0 || a.rows > kRowsMax || a.n <= 0 || a.iS % a.nb) return hipErrorInvalidValue;
     switch (a.nb) {
-        case 64: return adjoint ? launch_blk<64, true>(a, s) : launch_blk<64, false>(a, s);
         case 32: return adjoint ? launch_blk<32, true>(a, s) : launch_blk<32, false>(a, s);
         case 16: return adjoint ? launch_blk<16, true>(a, s) : launch_blk<16, false>(a, s);
         default: return hipErrorInvalidValue;
