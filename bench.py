@@ -33,8 +33,8 @@ PEAK_FP64_MFMA_TF = 78.6
 # HBM bytes per launch of the substitution GEMM at this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs scaled by a 512 MiB copy (profiles/k_gemm_direct_solve_m4096_n4096.md).
 # Valid only for the GEMM source it was measured on (sha1 prefix of csrc/kgemm.hip).
-GEMM_TRAFFIC = {"kgemm_sha1": "c7191d12866604e9", "bytes_per_launch": 447.1e6, "m": 4096, "n": 4096,
-                "nb": 32, "outer_nb": 256}
+GEMM_TRAFFIC = {"kgemm_sha1": "602b1a6efd64cc17", "bytes_per_launch": 457.8e6, "m": 4096, "n": 4096,
+                "nb": 16, "outer_nb": 256}
 PEAK_FP32_MFMA_TF = 157.3
 METRIC = "complex128 multi-shift solve GFLOP/s at m=n=4096 and % of MFMA peak vs plain FP64"
 
@@ -131,7 +131,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--m", type=int, default=4096)
     ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--nb", type=int, default=32)
+    ap.add_argument("--nb", type=int, default=16)
     ap.add_argument("--outer-nb", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
@@ -222,7 +222,7 @@ def main() -> int:
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP64_MFMA_TF, 4),
         "traffic": gemm_traffic(m, n, args.nb, args.outer_nb),
-        "kernel": "k_gemm<double> (substitution GEMM, FP64 MFMA 16x16x4)",
+        "kernel": "k_gemm_direct (substitution GEMM, FP64 MFMA 16x16x4)",
         "avg_launch_us": round(g["ms"] * 1e3 / max(1, g["launches"]), 2),
         "flops_per_launch": g["flops"] / max(1, g["launches"]),
         "kernel_ms_per_solve": split,

@@ -42,7 +42,7 @@ typedef enum {
 
 /* Options. A NULL mst_opts* means all defaults; a zero field means its default. */
 typedef struct {
-    int nb;            /* diagonal-block (and scaling-decision) size: 16, 32 or 64; default 32 */
+    int nb;            /* diagonal-block (and scaling-decision) size: 16, 32 or 64; default 16 */
     int outer_nb;      /* rows per deferred substitution step, a multiple of nb; default 256.
                           Equal to nb gives the paper's right-looking order (Alg 3 / Alg 5). */
     int precision;     /* 0: all FP64.
@@ -62,13 +62,14 @@ typedef struct {
     int gemm_staged;   /* 0 (default): substitution GEMM without LDS staging (each wavefront
                           streams its operands from L1/L2); 1: LDS-staged GEMM. Same results
                           up to summation order; kept for testing. */
-    int overlap;       /* 0 (default): with fused outer blocks, the substitution of an outer
-                          block's solution into the rows of the next outer block up runs
-                          ahead on a second stream of the library, together with that
-                          block's diagonal solve, while the GEMM for all rows further up
-                          runs on the caller's stream (ordered by events; the call stays
-                          asynchronous on the caller's stream). -1: everything on the
-                          caller's stream. Results are identical bit for bit. */
+    int overlap;       /* 0 (default): everything on the caller's stream.
+                          1: with fused outer blocks, the substitution of an outer block's
+                          solution into the rows of the next outer block up runs ahead on
+                          a second stream of the library, together with that block's
+                          diagonal solve, while the GEMM for all rows further up runs on
+                          the caller's stream (ordered by events; the call stays
+                          asynchronous on the caller's stream). Results are identical bit
+                          for bit; on MI355X it pays off for nb = 32 only. */
     int reserved[1];
 } mst_opts;
 

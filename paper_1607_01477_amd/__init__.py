@@ -1,7 +1,7 @@
 """Blocked multi-shift triangular solves on AMD MI355X (gfx950).
 
 Python binding of ``libmstrsm.so`` (C-ABI declared in ``include/mstrsm.h``).
-Keyword options left at 0 take the library's defaults (nb = 32, outer_nb = 256).
+Keyword options left at 0 take the library's defaults (nb = 16, outer_nb = 256).
 Every function here only marshals arguments: tensors must be complex128 (int32
 for ``col_len``) on a ROCm device; matrices are passed column-major (a
 Fortran-ordered view, ``t.stride(0) == 1``), copied into that layout if they
@@ -33,9 +33,9 @@ def version() -> str:
 
 
 def _opts(nb=0, outer_nb=0, precision=0, max_sweeps=0, omega_log2=0, force_phase2=0, fuse=True,
-          staged=False, overlap=True):
+          staged=False, overlap=False):
     o = MstOpts()
-    o.overlap = 0 if overlap else -1
+    o.overlap = 1 if overlap else 0
     o.gemm_staged = 1 if staged else 0
     o.nb, o.outer_nb, o.precision = int(nb), int(outer_nb), int(precision)
     o.max_sweeps, o.omega_log2, o.force_phase2 = int(max_sweeps), int(omega_log2), int(force_phase2)
@@ -109,7 +109,7 @@ def _mat(t: torch.Tensor, name: str) -> torch.Tensor:
 
 
 def mstrsm(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2, fuse=True, staged=False,
-           overlap=True):
+           overlap=False):
     """X with (U - shifts[j] I) X[:, j] = B[:, j]; B is overwritten when it is
     already column-major complex128 (the result is returned either way).
     precision=1: FP32 substitution GEMMs + FP64 refinement (max_sweeps)."""
@@ -127,7 +127,7 @@ def mstrsm(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2, fuse=Tr
 
 
 def mstrsm_safe(U, shifts, B, col_len=None, *, nb=0, outer_nb=0, omega_log2=0, fuse=True,
-                staged=False, overlap=True):
+                staged=False, overlap=False):
     """Safe solve: returns (X, scale, scale_log2) with
     (U - shifts[j] I) X[:, j] = scale[j] B[:, j], scale[j] = 2^-scale_log2[j]."""
     U = _mat(U, "U")
@@ -147,7 +147,7 @@ def mstrsm_safe(U, shifts, B, col_len=None, *, nb=0, outer_nb=0, omega_log2=0, f
     return X, scale, klog
 
 
-def mstrsm_adjoint(U, shifts, G, *, nb=0, outer_nb=0, fuse=True, overlap=True):
+def mstrsm_adjoint(U, shifts, G, *, nb=0, outer_nb=0, fuse=True, overlap=False, staged=False):
     """Y with (U - shifts[j] I)^H Y[:, j] = G[:, j] (G overwritten when column-major)."""
     U = _mat(U, "U")
     Y = _mat(G, "G")
@@ -155,7 +155,7 @@ def mstrsm_adjoint(U, shifts, G, *, nb=0, outer_nb=0, fuse=True, overlap=True):
     if U.shape != (m, m):
         raise ValueError("U must be %d x %d" % (m, m))
     s = _vec(shifts, n, "shifts")
-    o = _opts(nb=nb, outer_nb=outer_nb, fuse=fuse, overlap=overlap)
+    o = _opts(nb=nb, outer_nb=outer_nb, fuse=fuse, overlap=overlap, staged=staged)
     rc = _lib.load().mstrsm_adjoint(m, n, _p(U), _ld(U), _p(s), _p(Y), _ld(Y), ctypes.byref(o),
                                     _stream())
     _lib.check("mstrsm_adjoint", rc)

@@ -84,10 +84,10 @@ hipError_t timed(int kind, double flops, hipStream_t s, F&& launch) {
 double gemm_flops(const GemmArgs& g) { return 8.0 * g.M * (double)g.N * g.K; }
 
 struct Opts {
-    int nb = 32, outer = 256, precision = 0, sweeps = 2, omega_log2 = 960;
+    int nb = 16, outer = 256, precision = 0, sweeps = 2, omega_log2 = 960;
     bool fuse = true;
     int staged = 0;
-    bool overlap = true;
+    bool overlap = false;
 };
 
 // position of opt in the caller's argument list, for error reporting
@@ -109,8 +109,8 @@ mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
     r.fuse = o->fuse_blocks == 0;
     if (o->gemm_staged != 0 && o->gemm_staged != 1) return bad(pos);
     r.staged = o->gemm_staged;
-    if (o->overlap != 0 && o->overlap != -1) return bad(pos);
-    r.overlap = o->overlap == 0;
+    if (o->overlap != 0 && o->overlap != 1) return bad(pos);
+    r.overlap = o->overlap == 1;
     return MST_OK;
 }
 
@@ -347,7 +347,7 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
             if (q < qb) {
                 // G(i1:end) -= U(i0:i1, i1:end)^H Y(i0:i1)
                 GemmArgs g{};
-                g.M = end - i1; g.N = n; g.K = bs; g.op = GOP_SUB;
+                g.M = end - i1; g.N = n; g.K = bs; g.op = GOP_SUB; g.staged = o.staged;
                 g.A = U + (long)i1 * ldu + i0; g.lda = ldu; g.a_ct = 1;
                 g.B = G + i0; g.ldb = ldg;
                 g.C = G + i1; g.ldc = ldg;
@@ -358,7 +358,7 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
         if (end < m) {
             const int r0 = qa * nb;
             GemmArgs g{};
-            g.M = m - end; g.N = n; g.K = end - r0; g.op = GOP_SUB;
+            g.M = m - end; g.N = n; g.K = end - r0; g.op = GOP_SUB; g.staged = o.staged;
             g.A = U + (long)end * ldu + r0; g.lda = ldu; g.a_ct = 1;
             g.B = G + r0; g.ldb = ldg;
             g.C = G + end; g.ldc = ldg;

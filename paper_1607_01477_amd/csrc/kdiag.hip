@@ -825,12 +825,13 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
                 do_tile(cur, af);
                 cur = nxt;
             }
-            // first fragment of the next round, in flight across the barrier
-            if (wave >= kAW && stp + 1 < nsub) aload(an, round_of(stp + 1), wave - kAW);
             // counter of the next round (its last use was before the barrier behind us)
             if (tid == 0) tctr[buf ^ 1] = NUW;
         }
         if (stp + 1 < nsub) stage_store(buf ^ 1);
+        // first fragment of the next round, in flight across the barrier; issued
+        // after the staging stores so that their wait does not cover it
+        if (wave >= kAW && stp + 1 < nsub) aload(an, round_of(stp + 1), wave - kAW);
         __syncthreads();
     }
 

@@ -300,15 +300,15 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------- barrier-free substitution GEMM
-// C -= A B for plain (not conjugate-transposed) FP64 operands, the form of the
-// substitution step. Every wavefront owns a 32 x 32 complex tile of C and
+// C -= A B for FP64 operands, A plain (the forward substitution step) or
+// conjugate-transposed (the adjoint's). Every wavefront owns a 32 x 32 complex tile of C and
 // reads its MFMA operands straight from global memory (L1/L2) in the lane
 // layout of the matrix cores: A(row, k) at lane row%16 + 16 k, B(k, col) at
 // lane col%16 + 16 k. Loads run DEPTH k-steps ahead of the matrix cores in a
 // register ring, so no LDS staging and no workgroup barrier are needed and each
 // wavefront keeps its matrix pipe fed on its own. The 4 wavefronts of a
 // workgroup cover a 64 x 64 tile and share A rows / B columns through L1.
-template <int DEPTH, bool SAFE, bool VARLEN>
+template <int DEPTH, bool A_CT, bool SAFE, bool VARLEN>
 __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
     using V = v4d;
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
@@ -400,9 +400,15 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
         auto load = [&](int ks, zd& a0, zd& a1, zd& b0, zd& b1, int& e0, int& e1)
             __attribute__((always_inline)) {
             const int k = MASK ? min(ks * 4 + lq, g.K - 1) : ks * 4 + lq;
-            const zd* ap = A + (long)k * g.lda;
-            a0 = ap[ra0];
-            a1 = ap[ra1];
+            if (!A_CT) {
+                const zd* ap = A + (long)k * g.lda;
+                a0 = ap[ra0];
+                a1 = ap[ra1];
+            } else {
+                // A(r, k) = conj(a[r * lda + k]); conjugated where consumed
+                a0 = A[(long)ra0 * g.lda + k];
+                a1 = A[(long)ra1 * g.lda + k];
+            }
             b0 = B[(long)cb0 * g.ldb + k];
             b1 = B[(long)cb1 * g.ldb + k];
             if (SAFE) {
@@ -426,8 +432,9 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 b0.re = ldexp(b0.re, e0 - kq0); b0.im = ldexp(b0.im, e0 - kq0);
                 b1.re = ldexp(b1.re, e1 - kq1); b1.im = ldexp(b1.im, e1 - kq1);
             }
-            // acc = C - A B: A negated
-            const double a0r = -a0.re, a0i = -a0.im, a1r = -a1.re, a1i = -a1.im;
+            // acc = C - A B: A negated (and conjugated for A_CT)
+            const double a0r = -a0.re, a1r = -a1.re;
+            const double a0i = A_CT ? a0.im : -a0.im, a1i = A_CT ? a1.im : -a1.im;
             accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b0.re, accR[0][0], 0, 0, 0);
             accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b1.re, accR[0][1], 0, 0, 0);
             accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b0.re, accR[1][0], 0, 0, 0);
@@ -502,10 +509,10 @@ hipError_t go(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <bool SAFE, bool VARLEN>
+template <bool A_CT, bool SAFE, bool VARLEN>
 hipError_t go_direct(const GemmArgs& g, hipStream_t s) {
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
-    hipLaunchKernelGGL((k_gemm_direct<4, SAFE, VARLEN>), dim3(TM * TN), dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((k_gemm_direct<4, A_CT, SAFE, VARLEN>), dim3(TM * TN), dim3(NT), 0, s, g);
     return hipGetLastError();
 }
 
@@ -520,7 +527,8 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
             if (g.b_ct) return hipErrorInvalidValue;
             if (g.a_ct) {
                 if (safe || varlen) return hipErrorInvalidValue;
-                return go<double, true, false, GOP_SUB, false, false>(g, s);
+                if (g.staged) return go<double, true, false, GOP_SUB, false, false>(g, s);
+                return go_direct<true, false, false>(g, s);
             }
             if (g.staged) {
                 if (safe && varlen) return go<double, false, false, GOP_SUB, true, true>(g, s);
@@ -528,10 +536,10 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
                 if (varlen) return hipErrorInvalidValue;
                 return go<double, false, false, GOP_SUB, false, false>(g, s);
             }
-            if (safe && varlen) return go_direct<true, true>(g, s);
-            if (safe) return go_direct<true, false>(g, s);
+            if (safe && varlen) return go_direct<false, true, true>(g, s);
+            if (safe) return go_direct<false, true, false>(g, s);
             if (varlen) return hipErrorInvalidValue;
-            return go_direct<false, false>(g, s);
+            return go_direct<false, false, false>(g, s);
         case GOP_RESID:
             if (g.a_ct || g.b_ct || safe || varlen) return hipErrorInvalidValue;
             return go<double, false, false, GOP_RESID, false, false>(g, s);

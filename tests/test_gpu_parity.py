@@ -452,18 +452,31 @@ def test_lookahead_stream_is_bit_identical(P, oracle_mod, nb, outer):
     import torch
     w = W.c1_plain(seed=61, m=1000 + nb // 2, n=150)
     for prec in (0, 1):
-        X1 = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, outer_nb=outer, precision=prec))
-        X0 = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, outer_nb=outer, precision=prec,
-                           overlap=False))
+        X1 = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, outer_nb=outer, precision=prec,
+                           overlap=True))
+        X0 = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, outer_nb=outer, precision=prec))
         assert np.array_equal(X1, X0)
         check_plain(oracle_mod, w.U, w.shifts, w.B, X1)
     U, lam, B = _growth(81, 700, 50)
     L = W.rng(810).integers(0, 701, 50).astype(np.int32)
     r1 = P.mstrsm_safe(dev(U), dev(lam), dev(B), col_len=dev(L, dtype=torch.int32), nb=nb,
-                       outer_nb=outer, omega_log2=40)
+                       outer_nb=outer, omega_log2=40, overlap=True)
     r0 = P.mstrsm_safe(dev(U), dev(lam), dev(B), col_len=dev(L, dtype=torch.int32), nb=nb,
-                       outer_nb=outer, omega_log2=40, overlap=False)
+                       outer_nb=outer, omega_log2=40)
     for a, b in zip(r1, r0):
         assert np.array_equal(host(a), host(b))
     Xo, so, ko = oracle_mod.solve_safe(U, lam, B, col_len=L, nb=nb, omega_log2=40)
     assert np.array_equal(host(r1[2]), ko)
+
+
+@pytest.mark.parametrize("nb,outer,fuse", [(16, 64, True), (32, 96, True), (16, 48, False)])
+def test_adjoint_direct_and_staged_gemm(P, oracle_mod, nb, outer, fuse):
+    """The conjugate-transposed substitution GEMM of the adjoint solve: the
+    barrier-free and the LDS-staged kernels both match the oracle (ragged m,
+    several tiles)."""
+    w = W.c1_plain(seed=63, m=530 + nb // 2, n=140)
+    Yo = oracle_mod.solve_adjoint(w.U, w.shifts, w.B)
+    for staged in (False, True):
+        Y = host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, outer_nb=outer, fuse=fuse,
+                                  staged=staged))
+        assert colerr(Y, Yo).max() <= 1e-10
