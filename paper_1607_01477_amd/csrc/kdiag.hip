@@ -457,16 +457,16 @@ constexpr int block_threads(int nb, bool adj, bool safe) {
 constexpr int kAW = 4;                 // wavefronts that solve diagonal blocks; the others update
 
 // One outer block (rows [iS, iS+rows)) for kCols shifts, with the right-hand
-// sides resident in LDS. Diagonal blocks are solved one per round with a
-// one-block lookahead: in the round that solves block q, the solving
-// wavefronts first apply the solution of the block solved in the round before
+// sides resident in LDS. Diagonal blocks are solved one per pass with a
+// one-block lookahead: in the pass that solves block q, the solving
+// wavefronts first apply the solution of the block solved in the pass before
 // (block p, adjacent to q) to q's own rows (a short product with the coupling
 // block U(q, p), staged in LDS) and then run the back substitution of q, while
 // the other wavefronts apply the same solution of p to all rows of the outer
 // block beyond q with FP64 MFMA products. The two parts touch disjoint rows, so
-// each round needs one barrier, and the matrix-core work runs beside the
+// each pass needs one barrier, and the matrix-core work runs beside the
 // latency-bound substitution instead of after it. Diagonal and coupling blocks
-// of the next round are loaded during the current one (double-buffered LDS).
+// of the next pass are loaded during the current one (double-buffered LDS).
 // Per element the updates keep the order of the blocks.
 template <int NB, bool ADJ, bool SAFE, bool MIXED, bool VARLEN>
 __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArgs a) {
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
     __shared__ zd Ud[2][NB];
     __shared__ double Gl[kCols];
     __shared__ int kcl[kCols], dkl[2][kCols], Ll[kCols];
-    __shared__ int tctr[2];        // next update tile to claim, per round parity
+    __shared__ int tctr[2];        // next update tile to claim, per pass parity
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col0 = blockIdx.x * kCols;
@@ -549,16 +549,16 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
         }
     }
 
-    // ---- geometry of round stp: block ql solved, block qp (solved in the round
+    // ---- geometry of pass stp: block ql solved, block qp (solved in the pass
     // before) applied; rows of the outer block relative to iS
     const int nsub = (rows + NB - 1) / NB;
-    struct Round {
-        int lr0, bs;      // rows of the block solved in this round
-        int p0, bsp;      // rows of the block applied in this round (bsp = 0: none)
-        int ubeg, uend;   // rows updated by the matrix cores in this round
+    struct Pass {
+        int lr0, bs;      // rows of the block solved in this pass
+        int p0, bsp;      // rows of the block applied in this pass (bsp = 0: none)
+        int ubeg, uend;   // rows updated by the matrix cores in this pass
     };
-    auto round_of = [&](int stp) __attribute__((always_inline)) {
-        Round g;
+    auto pass_of = [&](int stp) __attribute__((always_inline)) {
+        Pass g;
         const int ql = ADJ ? stp : nsub - 1 - stp;
         g.lr0 = ql * NB;
         g.bs = min(NB, rows - g.lr0);
@@ -576,11 +576,11 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
         return g;
     };
 
-    // ---- staging of the diagonal and coupling blocks of a round: loads into
-    // registers, stores to LDS later (the latency hides behind a round's work)
+    // ---- staging of the diagonal and coupling blocks of a pass: loads into
+    // registers, stores to LDS later (the latency hides behind a pass's work)
     zd ust[PERS];
     auto stage_load = [&](int stp) __attribute__((always_inline)) {
-        const Round g = round_of(stp);
+        const Pass g = pass_of(stp);
         const int i0 = iS + g.lr0, p0 = iS + g.p0;
 #pragma unroll
         for (int e = 0; e < PERS; ++e) {
@@ -656,7 +656,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
     // U fragments of the matrix-core update: A(row, k) for row = ubeg + tile*16 +
     // lane%16, k = 4 ks + lane/16 (forward: U(iS+row, iS+p0+k); adjoint:
     // conj(U(iS+p0+k, iS+row)))
-    auto aload = [&](zd (&dst)[KS], const Round& g, int tile) __attribute__((always_inline)) {
+    auto aload = [&](zd (&dst)[KS], const Pass& g, int tile) __attribute__((always_inline)) {
         const int arow = g.ubeg + tile * 16 + lr;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
@@ -673,14 +673,14 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
             dst[ks] = v;
         }
     };
-    zd an[KS];   // first fragment of a round, loaded at the end of the round before
-    double xpr[SPW], xpi[SPW];   // solving wavefronts: solution of the block of the round before
+    zd an[KS];   // first fragment of a pass, loaded at the end of the pass before
+    double xpr[SPW], xpi[SPW];   // solving wavefronts: solution of the block of the pass before
 #pragma unroll
     for (int s = 0; s < SPW; ++s) xpr[s] = xpi[s] = 0.0;
 
     for (int stp = 0; stp < nsub; ++stp) {
         const int buf = stp & 1;
-        const Round g = round_of(stp);
+        const Pass g = pass_of(stp);
         const int q = a.qa + (ADJ ? stp : nsub - 1 - stp);
         const int i0 = iS + g.lr0;
         if (stp + 1 < nsub) stage_load(stp + 1);
@@ -710,7 +710,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
 #pragma unroll
                 for (int s = 0; s < SPW; ++s) ar[s][0] = ar[s][1] = ai[s][0] = ai[s][1] = 0.0;
                 if constexpr (NB == 16) {
-                    // x_p(k) is still in lane k of each group from the round before
+                    // x_p(k) is still in lane k of each group from the pass before
                     zd uo[16];
 #pragma unroll
                     for (int k = 0; k < 16; ++k) uo[k] = Uo[buf][k * NB + r];
@@ -764,7 +764,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
         }
         // ---- rows beyond block q: C -= U_panel * x(block p) on the matrix cores.
         // Tiles 0 .. NUW-1 go to the updating wavefronts (first fragment
-        // prefetched in the round before); the rest are claimed from a counter
+        // prefetched in the pass before); the rest are claimed from a counter
         // by whichever wavefront is free, the solving ones after their solve.
         {
             const int ntile = (g.uend - g.ubeg + 15) / 16;
@@ -825,13 +825,13 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
                 do_tile(cur, af);
                 cur = nxt;
             }
-            // counter of the next round (its last use was before the barrier behind us)
+            // counter of the next pass (its last use was before the barrier behind us)
             if (tid == 0) tctr[buf ^ 1] = NUW;
         }
         if (stp + 1 < nsub) stage_store(buf ^ 1);
-        // first fragment of the next round, in flight across the barrier; issued
+        // first fragment of the next pass, in flight across the barrier; issued
         // after the staging stores so that their wait does not cover it
-        if (wave >= kAW && stp + 1 < nsub) aload(an, round_of(stp + 1), wave - kAW);
+        if (wave >= kAW && stp + 1 < nsub) aload(an, pass_of(stp + 1), wave - kAW);
         __syncthreads();
     }
 
