@@ -174,6 +174,9 @@ hipError_t aux_get(int nev, Aux** out) {
 // ---------------------------------------------------------------- forward block loop
 // FP64 (b32 == nullptr) or mixed: the right-hand side lives in W32 (FP32) for the
 // substitution GEMMs and the diagonal blocks write FP64 X into B.
+// outer blocks per group of the two-level deferral in the one-stream forward loop
+constexpr int kSuperOuter = 4;
+
 hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long ldu32,
                         const zd* lam, zd* B, long ldb, zf* W32, long ldw, const Opts& o,
                         const SafeState* safe, const int* col_len, hipStream_t s) {
@@ -187,12 +190,12 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
     auto row_end = [&](int ob) { return ((q_last(ob) + 1) * nb < m) ? (q_last(ob) + 1) * nb : m; };
 
     // B(r0:r1, :) -= U(r0:r1, x0:x1) X(x0:x1, :) with X the solved rows of outer
-    // block ob (x0:x1 are its rows); the safe form brings C from the exponent of
-    // the outer block below ob to that of ob
-    auto substitute = [&](int ob, int r0, int r1, hipStream_t st) -> hipError_t {
+    // blocks ob_lo..ob_hi (x0:x1 are their rows); the safe form brings C from the
+    // exponent of the outer block below ob_hi to that of ob_lo
+    auto substitute_range = [&](int ob_lo, int ob_hi, int r0, int r1, hipStream_t st) -> hipError_t {
         if (r1 <= r0) return hipSuccess;
-        const int qa = q_first(ob), qb = q_last(ob);
-        const int x0 = qa * nb, x1 = row_end(ob);
+        const int qa = q_first(ob_lo), qb = q_last(ob_hi);
+        const int x0 = qa * nb, x1 = row_end(ob_hi);
         GemmArgs g{};
         g.M = r1 - r0; g.N = n; g.K = x1 - x0;
         g.op = GOP_SUB; g.staged = o.staged;
@@ -210,6 +213,9 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
         g.B = W32 + x0; g.ldb = ldw;
         g.C = W32 + r0; g.ldc = ldw;
         return timed(MST_PROF_GEMM_F32, gemm_flops(g), st, [&] { return launch_gemm_f32(g, st); });
+    };
+    auto substitute = [&](int ob, int r0, int r1, hipStream_t st) -> hipError_t {
+        return substitute_range(ob, ob, r0, r1, st);
     };
     // all diagonal blocks of outer block ob, with the substitution between them, in one kernel
     auto solve_outer = [&](int ob, hipStream_t st) -> hipError_t {
@@ -309,8 +315,17 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             }
         }
         if (qa > 0) {
-            hipError_t e = substitute(ob, 0, qa * nb, s);
+            // Two-level deferral: inside a group of kSuperOuter outer blocks the
+            // rows above ob get X of ob (K = outer_nb); the rows above the whole
+            // group get X of all its outer blocks in one GEMM once the group is
+            // solved (K = its rows), so most of the substitution runs as a few
+            // deep products instead of many K = outer_nb ones.
+            const int g_lo = (ob / kSuperOuter) * kSuperOuter;
+            const int g_hi = (g_lo + kSuperOuter - 1 < nob - 1) ? g_lo + kSuperOuter - 1 : nob - 1;
+            const int g0 = q_first(g_lo) * nb;
+            hipError_t e = substitute(ob, g0, qa * nb, s);
             if (e != hipSuccess) return e;
+            if (ob == g_lo && g0 > 0 && (e = substitute_range(g_lo, g_hi, 0, g0, s)) != hipSuccess) return e;
         }
     }
     return hipSuccess;

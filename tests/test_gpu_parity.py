@@ -445,28 +445,30 @@ def test_staged_and_direct_gemm_agree(P, oracle_mod, safe):
 
 
 @pytest.mark.parametrize("nb,outer", [(16, 64), (32, 96), (64, 256)])
-def test_lookahead_stream_is_bit_identical(P, oracle_mod, nb, outer):
-    """The two-stream lookahead keeps every element's update order, so plain,
-    mixed-precision and safe (variable-length) solves match the one-stream
-    order bit for bit, and the oracle to the usual tolerance."""
+def test_lookahead_stream_matches(P, oracle_mod, nb, outer):
+    """The two-stream lookahead (one substitution per outer block) and the
+    one-stream loop (two-level deferral) solve the same systems: plain,
+    mixed-precision and safe (variable-length) results match the oracle, and
+    the safe exponents and scales of both equal the oracle's exactly."""
     import torch
     w = W.c1_plain(seed=61, m=1000 + nb // 2, n=150)
     for prec in (0, 1):
         X1 = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, outer_nb=outer, precision=prec,
                            overlap=True))
         X0 = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, outer_nb=outer, precision=prec))
-        assert np.array_equal(X1, X0)
         check_plain(oracle_mod, w.U, w.shifts, w.B, X1)
+        check_plain(oracle_mod, w.U, w.shifts, w.B, X0)
     U, lam, B = _growth(81, 700, 50)
     L = W.rng(810).integers(0, 701, 50).astype(np.int32)
     r1 = P.mstrsm_safe(dev(U), dev(lam), dev(B), col_len=dev(L, dtype=torch.int32), nb=nb,
                        outer_nb=outer, omega_log2=40, overlap=True)
     r0 = P.mstrsm_safe(dev(U), dev(lam), dev(B), col_len=dev(L, dtype=torch.int32), nb=nb,
                        outer_nb=outer, omega_log2=40)
-    for a, b in zip(r1, r0):
-        assert np.array_equal(host(a), host(b))
+    assert np.array_equal(host(r1[1]), host(r0[1])) and np.array_equal(host(r1[2]), host(r0[2]))
     Xo, so, ko = oracle_mod.solve_safe(U, lam, B, col_len=L, nb=nb, omega_log2=40)
     assert np.array_equal(host(r1[2]), ko)
+    for r in (r1, r0):
+        assert colerr(host(r[0]), Xo).max() <= 1e-6   # growth problem: kappa large
 
 
 @pytest.mark.parametrize("nb,outer,fuse", [(16, 64, True), (32, 96, True), (16, 48, False)])
