@@ -66,6 +66,34 @@ __device__ inline void tile_coords(int TM, int TN, int& tm, int& tn) {
     tn = in / gsz;
 }
 
+// Tile order of -triu(A B^H) on a square grid of TM x TM tiles: the first
+// TM (TM + 1) / 2 workgroups take the tiles on and above the diagonal (row
+// major, dealt out to the XCDs in equal contiguous ranges, since the
+// hardware places workgroup w on XCD w % 8), the rest the tiles below it,
+// which only write zeros.
+__device__ inline void tri_coords(int TM, int& tm, int& tn) {
+    const int T_up = TM * (TM + 1) / 2;
+    int w = blockIdx.x;
+    if (w < T_up) {
+        if ((T_up & 7) == 0) w = (w & 7) * (T_up >> 3) + (w >> 3);
+        int r = 0;
+        while (w >= TM - r) {
+            w -= TM - r;
+            ++r;
+        }
+        tm = r;
+        tn = r + w;
+    } else {
+        int z = w - T_up, r = 1;
+        while (z >= r) {
+            z -= r;
+            ++r;
+        }
+        tm = r;
+        tn = z;
+    }
+}
+
 template <typename CT>
 __device__ inline CT cconj(CT v) {
     v.im = -v.im;
@@ -300,20 +328,28 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------- barrier-free substitution GEMM
-// C -= A B for FP64 operands, A plain (the forward substitution step) or
-// conjugate-transposed (the adjoint's). Every wavefront owns a 32 x 32 complex tile of C and
+// OP = GOP_SUB: C -= A B for FP64 operands, A plain (the forward substitution
+// step) or conjugate-transposed (the adjoint's).
+// OP = GOP_NEG_TRIU: C = -triu(A B^H) (the U gradient): accumulators start at
+// zero, B is read conjugate-transposed, entries below the diagonal are written
+// as zero and wavefront tiles entirely below it skip the product.
+// Every wavefront owns a 32 x 32 complex tile of C and
 // reads its MFMA operands straight from global memory (L1/L2) in the lane
 // layout of the matrix cores: A(row, k) at lane row%16 + 16 k, B(k, col) at
 // lane col%16 + 16 k. Loads run DEPTH k-steps ahead of the matrix cores in a
 // register ring, so no LDS staging and no workgroup barrier are needed and each
 // wavefront keeps its matrix pipe fed on its own. The 4 wavefronts of a
 // workgroup cover a 64 x 64 tile and share A rows / B columns through L1.
-template <int DEPTH, bool A_CT, bool SAFE, bool VARLEN>
+template <int DEPTH, int OP, bool A_CT, bool SAFE, bool VARLEN>
 __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
+    static_assert(OP == GOP_SUB || OP == GOP_NEG_TRIU, "direct GEMM: substitution or -triu(A B^H)");
+    static_assert(OP == GOP_SUB || (!A_CT && !SAFE && !VARLEN), "-triu(A B^H): plain A only");
+    constexpr bool TRI = OP == GOP_NEG_TRIU;
     using V = v4d;
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
     int tm, tn;
-    tile_coords(TM, TN, tm, tn);
+    if (TRI) tri_coords(TM, tm, tn);   // square: M = N
+    else tile_coords(TM, TN, tm, tn);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int lr = lane & 15, lq = lane >> 4;
@@ -328,9 +364,25 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
         const bool act = cc < g.N && g.col_len[cc] > g.b_row0;
         if (!__any(act)) return;
     }
+    if (TRI && rw > cw + 31) {
+        // tile entirely below the diagonal: zeros
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = cw + j * 16 + lr;
+            if (col >= g.N) continue;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rw + i * 16 + lq + 4 * v;
+                    if (row < g.M) C[(long)col * g.ldc + row] = zd{0.0, 0.0};
+                }
+        }
+        return;
+    }
     const bool full = (rw + 32 <= g.M) && (cw + 32 <= g.N);
 
-    // ---- accumulators start from C
+    // ---- accumulators start from C (from zero for -triu(A B^H))
     V accR[2][2], accI[2][2];
     int clim0 = g.M, clim1 = g.M, blim0 = g.K, blim1 = g.K;
 #pragma unroll
@@ -363,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             for (int v = 0; v < 4; ++v) {
                 const int row = rw + i * 16 + lq + 4 * v;
                 zd c{0.0, 0.0};
-                if (col < g.N && row < cl) {
+                if (!TRI && col < g.N && row < cl) {
                     c = C[(long)col * g.ldc + row];
                     if (SAFE) {
                         c.re = ldexp(c.re, -csh);
@@ -409,8 +461,14 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 a0 = A[(long)ra0 * g.lda + k];
                 a1 = A[(long)ra1 * g.lda + k];
             }
-            b0 = B[(long)cb0 * g.ldb + k];
-            b1 = B[(long)cb1 * g.ldb + k];
+            if (!TRI) {
+                b0 = B[(long)cb0 * g.ldb + k];
+                b1 = B[(long)cb1 * g.ldb + k];
+            } else {
+                // B(k, c) = conj(b[k * ldb + c]); conjugated where consumed
+                b0 = B[(long)k * g.ldb + cb0];
+                b1 = B[(long)k * g.ldb + cb1];
+            }
             if (SAFE) {
                 const int q = (g.b_row0 + k) / g.nb;
                 e0 = g.kb[(long)q * g.n_kb + cb0];
@@ -431,6 +489,10 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             if (SAFE) {
                 b0.re = ldexp(b0.re, e0 - kq0); b0.im = ldexp(b0.im, e0 - kq0);
                 b1.re = ldexp(b1.re, e1 - kq1); b1.im = ldexp(b1.im, e1 - kq1);
+            }
+            if (TRI) {
+                b0.im = -b0.im;
+                b1.im = -b1.im;
             }
             // acc = C - A B: A negated (and conjugated for A_CT)
             const double a0r = -a0.re, a1r = -a1.re;
@@ -496,6 +558,10 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 const int row = rw + i * 16 + lq + 4 * v;
                 if (!full && row >= g.M) continue;
                 if (VARLEN && row >= (j == 0 ? clim0 : clim1)) continue;
+                if (TRI && row > col) {
+                    C[(long)col * g.ldc + row] = zd{0.0, 0.0};
+                    continue;
+                }
                 C[(long)col * g.ldc + row] = zd{accR[i][j][v], accI[i][j][v]};
             }
         }
@@ -509,10 +575,10 @@ hipError_t go(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <bool A_CT, bool SAFE, bool VARLEN>
+template <int OP, bool A_CT, bool SAFE, bool VARLEN>
 hipError_t go_direct(const GemmArgs& g, hipStream_t s) {
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
-    hipLaunchKernelGGL((k_gemm_direct<4, A_CT, SAFE, VARLEN>), dim3(TM * TN), dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((k_gemm_direct<4, OP, A_CT, SAFE, VARLEN>), dim3(TM * TN), dim3(NT), 0, s, g);
     return hipGetLastError();
 }
 
@@ -528,7 +594,7 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
             if (g.a_ct) {
                 if (safe || varlen) return hipErrorInvalidValue;
                 if (g.staged) return go<double, true, false, GOP_SUB, false, false>(g, s);
-                return go_direct<true, false, false>(g, s);
+                return go_direct<GOP_SUB, true, false, false>(g, s);
             }
             if (g.staged) {
                 if (safe && varlen) return go<double, false, false, GOP_SUB, true, true>(g, s);
@@ -536,16 +602,18 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
                 if (varlen) return hipErrorInvalidValue;
                 return go<double, false, false, GOP_SUB, false, false>(g, s);
             }
-            if (safe && varlen) return go_direct<false, true, true>(g, s);
-            if (safe) return go_direct<false, true, false>(g, s);
+            if (safe && varlen) return go_direct<GOP_SUB, false, true, true>(g, s);
+            if (safe) return go_direct<GOP_SUB, false, true, false>(g, s);
             if (varlen) return hipErrorInvalidValue;
-            return go_direct<false, false, false>(g, s);
+            return go_direct<GOP_SUB, false, false, false>(g, s);
         case GOP_RESID:
             if (g.a_ct || g.b_ct || safe || varlen) return hipErrorInvalidValue;
             return go<double, false, false, GOP_RESID, false, false>(g, s);
         case GOP_NEG_TRIU:
             if (g.a_ct || !g.b_ct || safe || varlen) return hipErrorInvalidValue;
-            return go<double, false, true, GOP_NEG_TRIU, false, false>(g, s);
+            if (g.staged) return go<double, false, true, GOP_NEG_TRIU, false, false>(g, s);
+            if (g.M != g.N) return hipErrorInvalidValue;
+            return go_direct<GOP_NEG_TRIU, false, false, false>(g, s);
         default:
             return hipErrorInvalidValue;
     }

@@ -482,3 +482,16 @@ def test_adjoint_direct_and_staged_gemm(P, oracle_mod, nb, outer, fuse):
         Y = host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, outer_nb=outer, fuse=fuse,
                                   staged=staged))
         assert colerr(Y, Yo).max() <= 1e-10
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (7, 3), (65, 70), (130, 5), (257, 33), (600, 130)])
+def test_grad_u_shapes(P, oracle_mod, m, n):
+    """-triu(Y X^H) on the barrier-free MFMA GEMM (zero tiles below the
+    diagonal, ragged edges in M and K) against the oracle's gradient."""
+    g = W.rng(900 + m)
+    Y = W.cnormal(g, (m, n))
+    X = W.cnormal(g, (m, n))
+    gU, _, _ = oracle_mod.gradient(np.zeros((m, m), complex), np.zeros(n, complex), X, Y)
+    gUd = host(P.grad_u(dev(Y), dev(X)))
+    np.testing.assert_allclose(gUd, gU, rtol=0, atol=1e-13 * max(1.0, np.abs(gU).max()) * n)
+    assert np.all(np.tril(gUd, -1) == 0)
