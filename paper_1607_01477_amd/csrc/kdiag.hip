@@ -448,11 +448,12 @@ constexpr int kRowsMax = 256;          // rows of one outer block
 constexpr int kCols = 16;              // shifts per workgroup
 constexpr int kSP = kRowsMax + 1;      // padded LDS column stride (bank spread)
 // threads of the fused kernel: 4 solving wavefronts plus 8 updating ones for
-// the plain forward solve with nb = 16 (three wavefronts per SIMD, two of them
-// on the matrix cores); 4 plus 4 where the register use leaves room for two
-// wavefronts per SIMD only (nb = 32, safe, adjoint)
+// the plain solves with nb = 16 (three wavefronts per SIMD, two of them on the
+// matrix cores); 4 plus 4 where the register use leaves room for two
+// wavefronts per SIMD only (nb = 32, safe). The adjoint variant at 768 threads
+// keeps four addresses of its final store loop in scratch (reloaded once).
 constexpr int block_threads(int nb, bool adj, bool safe) {
-    return (nb == 16 && !adj && !safe) ? 768 : 512;
+    return (nb == 16 && !safe) ? 768 : 512;
 }
 constexpr int kAW = 4;                 // wavefronts that solve diagonal blocks; the others update
 
