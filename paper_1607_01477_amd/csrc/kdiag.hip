@@ -578,42 +578,51 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
     };
 
     // ---- staging of the diagonal and coupling blocks of a pass: loads into
-    // registers, stores to LDS later (the latency hides behind a pass's work)
+    // registers, stores to LDS later (the latency hides behind a pass's work).
+    // Every thread issues exactly one unconditional load per element, from a
+    // clamped address inside U's upper triangle; elements outside the blocks
+    // are zeroed at the store. Conditional loads into shared registers make
+    // the compiler wait for each load before the next (write-after-write).
     zd ust[PERS];
+    bool usv[PERS];
     auto stage_load = [&](int stp) __attribute__((always_inline)) {
         const Pass g = pass_of(stp);
         const int i0 = iS + g.lr0, p0 = iS + g.p0;
 #pragma unroll
         for (int e = 0; e < PERS; ++e) {
             const int t = tid + e * kWGB;
-            ust[e] = zd{0.0, 0.0};
+            long off = (long)i0 * a.ldu + i0;   // the block's first pivot: always valid
+            bool v = false;
             if (t < NBB) {
                 const int c = t / NB, rr = t - c * NB;
-                if (rr <= c && c < g.bs) ust[e] = a.U[(long)(i0 + c) * a.ldu + i0 + rr];
+                v = rr <= c && c < g.bs;
+                off = v ? (long)(i0 + c) * a.ldu + i0 + rr : off;
             } else if (t < 2 * NBB) {
                 const int t2 = t - NBB;
                 if (!ADJ) {
                     // coefficient of x_p(k) in row r: U(i0 + r, p0 + k)
                     const int k = t2 / NB, r = t2 - k * NB;
-                    if (r < g.bs && k < g.bsp) ust[e] = a.U[(long)(p0 + k) * a.ldu + i0 + r];
+                    v = r < g.bs && k < g.bsp;
+                    off = v ? (long)(p0 + k) * a.ldu + i0 + r : off;
                 } else {
-                    // adjoint: conj(U(p0 + k, i0 + r))
+                    // adjoint: conj(U(p0 + k, i0 + r)), conjugated at the store
                     const int r = t2 / NB, k = t2 - r * NB;
-                    if (r < g.bs && k < g.bsp) {
-                        const zd v = a.U[(long)(i0 + r) * a.ldu + p0 + k];
-                        ust[e] = zd{v.re, -v.im};
-                    }
+                    v = r < g.bs && k < g.bsp;
+                    off = v ? (long)(i0 + r) * a.ldu + p0 + k : off;
                 }
             }
+            usv[e] = v;
+            ust[e] = a.U[off];
         }
     };
     auto stage_store = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
         for (int e = 0; e < PERS; ++e) {
             const int t = tid + e * kWGB;
+            zd v = usv[e] ? ust[e] : zd{0.0, 0.0};
+            if (ADJ) v.im = -v.im;
             if (t < NBB) {
                 const int c = t / NB, rr = t - c * NB;
-                const zd v = ADJ ? zd{ust[e].re, -ust[e].im} : ust[e];
                 if (rr == c) {
                     Ud[buf][rr] = v;
                     Us[buf][c * NB + rr] = zd{0.0, 0.0};
@@ -632,7 +641,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
                     r = t2 / NB;
                     k = t2 - r * NB;
                 }
-                Uo[buf][k * NB + r] = ust[e];
+                Uo[buf][k * NB + r] = v;
             }
         }
     };
@@ -652,26 +661,25 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
         cc[s] = c;
         jv[s] = col0 + c < a.n;
         lam[s] = (wave < kAW && jv[s]) ? a.lam[col0 + c] : zd{0.0, 0.0};
+        // wait for the shifts here, once: the first use is inside the pass loop,
+        // where the compiler cannot count the loads in flight and would wait for
+        // all of them (the next pass's staging loads included) in every pass
+        asm volatile("" : "+v"(lam[s].re), "+v"(lam[s].im));
     }
 
     // U fragments of the matrix-core update: A(row, k) for row = ubeg + tile*16 +
     // lane%16, k = 4 ks + lane/16 (forward: U(iS+row, iS+p0+k); adjoint:
-    // conj(U(iS+p0+k, iS+row)))
+    // conj(U(iS+p0+k, iS+row)), conjugated where consumed). Loads are
+    // unconditional from clamped positions inside U's upper triangle (needs
+    // uend > ubeg and bsp > 0); positions outside the tile are zeroed where
+    // consumed.
     auto aload = [&](zd (&dst)[KS], const Pass& g, int tile) __attribute__((always_inline)) {
-        const int arow = g.ubeg + tile * 16 + lr;
+        const int arow = max(g.ubeg, min(g.ubeg + tile * 16 + lr, g.uend - 1));
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const int k = ks * 4 + lq;
-            zd v{0.0, 0.0};
-            if (k < g.bsp && arow < g.uend) {
-                if (!ADJ) {
-                    v = a.U[(long)(iS + g.p0 + k) * a.ldu + iS + arow];
-                } else {
-                    v = a.U[(long)(iS + arow) * a.ldu + iS + g.p0 + k];
-                    v.im = -v.im;
-                }
-            }
-            dst[ks] = v;
+            const int k = min(ks * 4 + lq, g.bsp - 1);
+            if (!ADJ) dst[ks] = a.U[(long)(iS + g.p0 + k) * a.ldu + iS + arow];
+            else dst[ks] = a.U[(long)(iS + arow) * a.ldu + iS + g.p0 + k];
         }
     };
     zd an[KS];   // first fragment of a pass, loaded at the end of the pass before
@@ -684,6 +692,13 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
         const Pass g = pass_of(stp);
         const int q = a.qa + (ADJ ? stp : nsub - 1 - stp);
         const int i0 = iS + g.lr0;
+        // updating wavefronts: settle the first fragment of this pass (loaded in
+        // the pass before) before the staging loads are issued, so that the
+        // wait for it does not also cover them
+        if (wave >= kAW) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) asm volatile("" : "+v"(an[ks].re), "+v"(an[ks].im));
+        }
         if (stp + 1 < nsub) stage_load(stp + 1);
 
         if (wave < kAW) {
@@ -777,6 +792,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
             };
             auto do_tile = [&](int tile, const zd (&af)[KS]) __attribute__((always_inline)) {
                 const int rb = g.ubeg + tile * 16;
+                const bool rowok = rb + lr < g.uend;   // this lane's A row inside the tile
                 // Every LDS read below is in bounds (rows < 256) and needs no
                 // branch: rows past the outer block are zero in Bl, and the
                 // tiles never reach into the block being solved. Unguarded
@@ -803,7 +819,9 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
                     // x(block p) fragment from LDS: row k = 4 ks + lane/16, column lane%16
                     const int k = ks * 4 + lq;
                     const zd xb = Bl[lr * kSP + g.p0 + k];
-                    const double ar = -af[ks].re, ai = -af[ks].im;
+                    const bool ok = rowok && k < g.bsp;
+                    const double ar = ok ? -af[ks].re : 0.0;
+                    const double ai = ok ? (ADJ ? af[ks].im : -af[ks].im) : 0.0;
                     accR = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb.re, accR, 0, 0, 0);
                     accI = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb.im, accI, 0, 0, 0);
                     accR2 = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, xb.im, accR2, 0, 0, 0);
@@ -832,7 +850,10 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
         if (stp + 1 < nsub) stage_store(buf ^ 1);
         // first fragment of the next pass, in flight across the barrier; issued
         // after the staging stores so that their wait does not cover it
-        if (wave >= kAW && stp + 1 < nsub) aload(an, pass_of(stp + 1), wave - kAW);
+        if (wave >= kAW && stp + 1 < nsub) {
+            const Pass gn = pass_of(stp + 1);
+            if (gn.uend > gn.ubeg) aload(an, gn, wave - kAW);
+        }
         __syncthreads();
     }
 
