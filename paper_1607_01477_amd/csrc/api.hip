@@ -385,9 +385,9 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
 }
 
 hipError_t residual(int m, int n, const zd* U, long ldu, const zd* lam, const zd* X, long ldx,
-                    const zd* B0, long ldb0, zd* R, long ldr, hipStream_t s) {
+                    const zd* B0, long ldb0, zd* R, long ldr, hipStream_t s, int staged = 0) {
     GemmArgs g{};
-    g.M = m; g.N = n; g.K = m; g.op = GOP_RESID;
+    g.M = m; g.N = n; g.K = m; g.op = GOP_RESID; g.staged = staged;
     g.A = U; g.lda = ldu;
     g.B = X; g.ldb = ldx;
     g.C = R; g.ldc = ldr;
@@ -445,7 +445,7 @@ mst_status plain_solve(int m, int n, const zd* U, long ldu, const zd* lam, zd* B
     HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_to_f32(m, n, B, ldb, W32, m, false, s); }));
     HIPCHK(forward_loop(m, n, U, ldu, U32, m, lam, B, ldb, W32, m, o, nullptr, nullptr, s));
     for (int sw = 0; sw < o.sweeps; ++sw) {
-        HIPCHK(residual(m, n, U, ldu, lam, B, ldb, B0, m, R, m, s));
+        HIPCHK(residual(m, n, U, ldu, lam, B, ldb, B0, m, R, m, s, o.staged));
         HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_to_f32(m, n, R, m, W32, m, false, s); }));
         HIPCHK(forward_loop(m, n, U, ldu, U32, m, lam, R, m, W32, m, o, nullptr, nullptr, s));
         HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_axpy_inplace(m, n, R, m, B, ldb, s); }));

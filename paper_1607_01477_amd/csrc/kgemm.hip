@@ -327,36 +327,54 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(GemmArgs g) {
     }
 }
 
-// ---------------------------------------------------------------- barrier-free substitution GEMM
-// OP = GOP_SUB: C -= A B for FP64 operands, A plain (the forward substitution
-// step) or conjugate-transposed (the adjoint's).
+// ---------------------------------------------------------------- barrier-free GEMM
+// OP = GOP_SUB: C -= A B, A plain (the forward substitution step) or
+// conjugate-transposed (the adjoint's); FP64, or FP32 for the mixed-precision
+// substitution (plain operands only).
 // OP = GOP_NEG_TRIU: C = -triu(A B^H) (the U gradient): accumulators start at
 // zero, B is read conjugate-transposed, entries below the diagonal are written
 // as zero and wavefront tiles entirely below it skip the product.
-// Every wavefront owns a 32 x 32 complex tile of C and
-// reads its MFMA operands straight from global memory (L1/L2) in the lane
-// layout of the matrix cores: A(row, k) at lane row%16 + 16 k, B(k, col) at
-// lane col%16 + 16 k. Loads run DEPTH k-steps ahead of the matrix cores in a
-// register ring, so no LDS staging and no workgroup barrier are needed and each
-// wavefront keeps its matrix pipe fed on its own. The 4 wavefronts of a
-// workgroup cover a 64 x 64 tile and share A rows / B columns through L1.
-template <int DEPTH, int OP, bool A_CT, bool SAFE, bool VARLEN>
+// OP = GOP_RESID: C = B0 - A B + B diag(lam), A upper triangular (U): each
+// wavefront's K range starts at its first row and U's strict lower triangle
+// is never read.
+// Every wavefront owns a 32 x 32 complex tile of C and reads its MFMA operands
+// straight from global memory (L1/L2) in the lane layout of the matrix cores:
+// A(row, k) at lane row%16 + 16 k, B(k, col) at lane col%16 + 16 k. Loads run
+// DEPTH k-steps ahead of the matrix cores in a register ring, so no LDS staging
+// and no workgroup barrier are needed and each wavefront keeps its matrix pipe
+// fed on its own. The 4 wavefronts of a workgroup cover a 64 x 64 tile and
+// share A rows / B columns through L1.
+template <typename T, int DEPTH, int OP, bool A_CT, bool SAFE, bool VARLEN>
 __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
-    static_assert(OP == GOP_SUB || OP == GOP_NEG_TRIU, "direct GEMM: substitution or -triu(A B^H)");
-    static_assert(OP == GOP_SUB || (!A_CT && !SAFE && !VARLEN), "-triu(A B^H): plain A only");
+    static_assert(OP == GOP_SUB || OP == GOP_NEG_TRIU || OP == GOP_RESID, "direct GEMM op");
+    static_assert(OP == GOP_SUB || (!A_CT && !SAFE && !VARLEN), "triangular products: plain A only");
+    static_assert(sizeof(T) == 8 || (OP == GOP_SUB && !A_CT && !SAFE && !VARLEN),
+                  "FP32: plain substitution only");
     constexpr bool TRI = OP == GOP_NEG_TRIU;
-    using V = v4d;
+    constexpr bool RES = OP == GOP_RESID;
+    using Tr = Traits<T>;
+    using CT = typename Tr::C;
+    using V = typename Tr::V;
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
     int tm, tn;
-    if (TRI) tri_coords(TM, tm, tn);   // square: M = N
-    else tile_coords(TM, TN, tm, tn);
+    if (TRI) {
+        tri_coords(TM, tm, tn);   // square: M = N
+    } else if (RES) {
+        // work falls with the tile row (K runs from the row to the end): row
+        // major, heaviest rows first, each row spread over all XCDs (the
+        // hardware deals workgroup w to XCD w % 8)
+        tm = blockIdx.x / TN;
+        tn = blockIdx.x - tm * TN;
+    } else {
+        tile_coords(TM, TN, tm, tn);
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int lr = lane & 15, lq = lane >> 4;
     const int rw = tm * BM + wr * 32, cw = tn * BN + wc * 32;
-    const zd* __restrict__ A = (const zd*)g.A;
-    const zd* __restrict__ B = (const zd*)g.B;
-    zd* __restrict__ C = (zd*)g.C;
+    const CT* __restrict__ A = (const CT*)g.A;
+    const CT* __restrict__ B = (const CT*)g.B;
+    CT* __restrict__ C = (CT*)g.C;
 
     if (VARLEN) {
         // a wavefront whose columns all end above the B operand's rows has nothing to do
@@ -374,21 +392,22 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int row = rw + i * 16 + lq + 4 * v;
-                    if (row < g.M) C[(long)col * g.ldc + row] = zd{0.0, 0.0};
+                    const int row = rw + i * 16 + Tr::out_row(lq, v);
+                    if (row < g.M) C[(long)col * g.ldc + row] = CT{0, 0};
                 }
         }
         return;
     }
     const bool full = (rw + 32 <= g.M) && (cw + 32 <= g.N);
 
-    // ---- accumulators start from C (from zero for -triu(A B^H))
+    // ---- accumulators start from C (SUB), from B0 + lam B (RESID), from zero (TRI)
     V accR[2][2], accI[2][2];
     int clim0 = g.M, clim1 = g.M, blim0 = g.K, blim1 = g.K;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int col = cw + j * 16 + lr;
         int csh = 0, cl = g.M, bl = g.K;
+        zd lamc{0.0, 0.0};
         if (col < g.N) {
             if (VARLEN) {
                 cl = min(g.M, g.col_len[col] - g.c_row0);
@@ -399,6 +418,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 const int kq = (g.q_c >= 0) ? g.kb[(long)g.q_c * g.n_kb + col] : 0;
                 csh = kc - kq;
             }
+            if (RES) lamc = g.lam[col];
         } else {
             bl = 0;
         }
@@ -413,13 +433,20 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
         for (int i = 0; i < 2; ++i) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = rw + i * 16 + lq + 4 * v;
-                zd c{0.0, 0.0};
+                const int row = rw + i * 16 + Tr::out_row(lq, v);
+                CT c{0, 0};
                 if (!TRI && col < g.N && row < cl) {
-                    c = C[(long)col * g.ldc + row];
-                    if (SAFE) {
-                        c.re = ldexp(c.re, -csh);
-                        c.im = ldexp(c.im, -csh);
+                    if (RES) {
+                        const zd b0 = g.B0[(long)col * g.ldb0 + row];
+                        const CT x = B[(long)col * g.ldb + row];
+                        c = CT{T(b0.re + (lamc.re * x.re - lamc.im * x.im)),
+                               T(b0.im + (lamc.re * x.im + lamc.im * x.re))};
+                    } else {
+                        c = C[(long)col * g.ldc + row];
+                        if (SAFE) {
+                            c.re = ldexp(c.re, -csh);
+                            c.im = ldexp(c.im, -csh);
+                        }
                     }
                 }
                 accR[i][j][v] = c.re;
@@ -434,6 +461,8 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
     // flight for later steps. Elements outside the product are zeroed where
     // they are consumed (the clamped load may return anything, even NaN).
     const int nks = (g.K + 3) / 4;
+    const int kfirst = RES ? (rw >> 2) : 0;   // U(row, k) = 0 for k < row
+    const int nloc = nks - kfirst;
     const int ra0 = min(rw + lr, g.M - 1), ra1 = min(rw + 16 + lr, g.M - 1);
     const int cb0 = min(cw + lr, g.N - 1), cb1 = min(cw + 16 + lr, g.N - 1);
     const bool oka0 = rw + lr < g.M, oka1 = rw + 16 + lr < g.M;
@@ -447,13 +476,17 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
 
     auto kloop = [&](auto mask_tag) __attribute__((always_inline)) {
         constexpr bool MASK = decltype(mask_tag)::value;
-        zd pa0[DEPTH], pa1[DEPTH], pb0[DEPTH], pb1[DEPTH];
+        CT pa0[DEPTH], pa1[DEPTH], pb0[DEPTH], pb1[DEPTH];
         int qe0[DEPTH] = {}, qe1[DEPTH] = {};
-        auto load = [&](int ks, zd& a0, zd& a1, zd& b0, zd& b1, int& e0, int& e1)
+        auto load = [&](int ks, CT& a0, CT& a1, CT& b0, CT& b1, int& e0, int& e1)
             __attribute__((always_inline)) {
             const int k = MASK ? min(ks * 4 + lq, g.K - 1) : ks * 4 + lq;
-            if (!A_CT) {
-                const zd* ap = A + (long)k * g.lda;
+            if (RES) {
+                // stay inside U's upper triangle: below it the element is never used
+                a0 = A[(long)max(k, ra0) * g.lda + ra0];
+                a1 = A[(long)max(k, ra1) * g.lda + ra1];
+            } else if (!A_CT) {
+                const CT* ap = A + (long)k * g.lda;
                 a0 = ap[ra0];
                 a1 = ap[ra1];
             } else {
@@ -475,16 +508,21 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 e1 = g.kb[(long)q * g.n_kb + cb1];
             }
         };
-        auto mma = [&](int ks, zd a0, zd a1, zd b0, zd b1, int e0, int e1)
+        auto mma = [&](int ks, CT a0, CT a1, CT b0, CT b1, int e0, int e1)
             __attribute__((always_inline)) {
             if (MASK) {
                 const int k = ks * 4 + lq;
                 const bool kin = k < g.K;
-                const bool u0 = kin && oka0, u1 = kin && oka1, v0 = k < blim0, v1 = k < blim1;
-                a0.re = u0 ? a0.re : 0.0; a0.im = u0 ? a0.im : 0.0;
-                a1.re = u1 ? a1.re : 0.0; a1.im = u1 ? a1.im : 0.0;
-                b0.re = v0 ? b0.re : 0.0; b0.im = v0 ? b0.im : 0.0;
-                b1.re = v1 ? b1.re : 0.0; b1.im = v1 ? b1.im : 0.0;
+                bool u0 = kin && oka0, u1 = kin && oka1;
+                if (RES) {
+                    u0 = u0 && k >= rw + lr;
+                    u1 = u1 && k >= rw + 16 + lr;
+                }
+                const bool v0 = k < blim0, v1 = k < blim1;
+                a0.re = u0 ? a0.re : T(0); a0.im = u0 ? a0.im : T(0);
+                a1.re = u1 ? a1.re : T(0); a1.im = u1 ? a1.im : T(0);
+                b0.re = v0 ? b0.re : T(0); b0.im = v0 ? b0.im : T(0);
+                b1.re = v1 ? b1.re : T(0); b1.im = v1 ? b1.im : T(0);
             }
             if (SAFE) {
                 b0.re = ldexp(b0.re, e0 - kq0); b0.im = ldexp(b0.im, e0 - kq0);
@@ -495,34 +533,34 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 b1.im = -b1.im;
             }
             // acc = C - A B: A negated (and conjugated for A_CT)
-            const double a0r = -a0.re, a1r = -a1.re;
-            const double a0i = A_CT ? a0.im : -a0.im, a1i = A_CT ? a1.im : -a1.im;
-            accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b0.re, accR[0][0], 0, 0, 0);
-            accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b1.re, accR[0][1], 0, 0, 0);
-            accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b0.re, accR[1][0], 0, 0, 0);
-            accR[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b1.re, accR[1][1], 0, 0, 0);
-            accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b0.im, accI[0][0], 0, 0, 0);
-            accI[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0r, b1.im, accI[0][1], 0, 0, 0);
-            accI[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b0.im, accI[1][0], 0, 0, 0);
-            accI[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1r, b1.im, accI[1][1], 0, 0, 0);
-            accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0i, b0.im, accR[0][0], 0, 0, 0);
-            accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0i, b1.im, accR[0][1], 0, 0, 0);
-            accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1i, b0.im, accR[1][0], 0, 0, 0);
-            accR[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1i, b1.im, accR[1][1], 0, 0, 0);
-            accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0i, b0.re, accI[0][0], 0, 0, 0);
-            accI[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0i, b1.re, accI[0][1], 0, 0, 0);
-            accI[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1i, b0.re, accI[1][0], 0, 0, 0);
-            accI[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1i, b1.re, accI[1][1], 0, 0, 0);
+            const T a0r = -a0.re, a1r = -a1.re;
+            const T a0i = A_CT ? a0.im : -a0.im, a1i = A_CT ? a1.im : -a1.im;
+            accR[0][0] = Tr::mfma(a0r, b0.re, accR[0][0]);
+            accR[0][1] = Tr::mfma(a0r, b1.re, accR[0][1]);
+            accR[1][0] = Tr::mfma(a1r, b0.re, accR[1][0]);
+            accR[1][1] = Tr::mfma(a1r, b1.re, accR[1][1]);
+            accI[0][0] = Tr::mfma(a0r, b0.im, accI[0][0]);
+            accI[0][1] = Tr::mfma(a0r, b1.im, accI[0][1]);
+            accI[1][0] = Tr::mfma(a1r, b0.im, accI[1][0]);
+            accI[1][1] = Tr::mfma(a1r, b1.im, accI[1][1]);
+            accR[0][0] = Tr::mfma(-a0i, b0.im, accR[0][0]);
+            accR[0][1] = Tr::mfma(-a0i, b1.im, accR[0][1]);
+            accR[1][0] = Tr::mfma(-a1i, b0.im, accR[1][0]);
+            accR[1][1] = Tr::mfma(-a1i, b1.im, accR[1][1]);
+            accI[0][0] = Tr::mfma(a0i, b0.re, accI[0][0]);
+            accI[0][1] = Tr::mfma(a0i, b1.re, accI[0][1]);
+            accI[1][0] = Tr::mfma(a1i, b0.re, accI[1][0]);
+            accI[1][1] = Tr::mfma(a1i, b1.re, accI[1][1]);
         };
-        if (nks == 0) return;
+        if (nloc <= 0) return;
         // The ring is refilled without a condition (past the end the last
         // k-step is loaded again, in bounds and unused), so the main loop is
-        // straight-line code; only the last nks % DEPTH steps are guarded.
+        // straight-line code; only the last nloc % DEPTH steps are guarded.
 #pragma unroll
         for (int d = 0; d < DEPTH; ++d)
-            load(min(d, nks - 1), pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
-        int ks0 = 0;
-        for (; ks0 + DEPTH <= nks; ks0 += DEPTH) {
+            load(kfirst + min(d, nloc - 1), pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
+        int l0 = 0;
+        for (; l0 + DEPTH <= nloc; l0 += DEPTH) {
 #pragma unroll
             for (int d = 0; d < DEPTH; ++d) {
                 // Step d consumes ring slot d, then refills it. The scheduling
@@ -530,23 +568,23 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 // gives it other registers, and the copy back into the ring at
                 // the loop's end then waits for every load in flight; left free,
                 // the scheduler also gathers all refills at the end of the body.
-                mma(ks0 + d, pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
+                mma(kfirst + l0 + d, pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
                 __builtin_amdgcn_sched_barrier(0);
-                load(min(ks0 + d + DEPTH, nks - 1), pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
+                load(kfirst + min(l0 + d + DEPTH, nloc - 1), pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
 #pragma unroll
         for (int d = 0; d < DEPTH; ++d)
-            if (ks0 + d < nks) mma(ks0 + d, pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
+            if (l0 + d < nloc) mma(kfirst + l0 + d, pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
     };
-    // interior tiles of the plain form need no masking at all
-    if (full && (g.K & 3) == 0 && !VARLEN && !SAFE)
+    // interior tiles of the plain forms need no masking at all
+    if (full && (g.K & 3) == 0 && !VARLEN && !SAFE && !RES)
         kloop(std::false_type{});
     else
         kloop(std::true_type{});
 
-    // ---- epilogue: lane holds column lane%16, rows lane/16 + 4 v of each 16 x 16 block
+    // ---- epilogue
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int col = cw + j * 16 + lr;
@@ -555,14 +593,14 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
         for (int i = 0; i < 2; ++i) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = rw + i * 16 + lq + 4 * v;
+                const int row = rw + i * 16 + Tr::out_row(lq, v);
                 if (!full && row >= g.M) continue;
                 if (VARLEN && row >= (j == 0 ? clim0 : clim1)) continue;
                 if (TRI && row > col) {
-                    C[(long)col * g.ldc + row] = zd{0.0, 0.0};
+                    C[(long)col * g.ldc + row] = CT{0, 0};
                     continue;
                 }
-                C[(long)col * g.ldc + row] = zd{accR[i][j][v], accI[i][j][v]};
+                C[(long)col * g.ldc + row] = CT{accR[i][j][v], accI[i][j][v]};
             }
         }
     }
@@ -575,10 +613,10 @@ hipError_t go(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int OP, bool A_CT, bool SAFE, bool VARLEN>
+template <typename T, int OP, bool A_CT, bool SAFE, bool VARLEN>
 hipError_t go_direct(const GemmArgs& g, hipStream_t s) {
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
-    hipLaunchKernelGGL((k_gemm_direct<4, OP, A_CT, SAFE, VARLEN>), dim3(TM * TN), dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((k_gemm_direct<T, 4, OP, A_CT, SAFE, VARLEN>), dim3(TM * TN), dim3(NT), 0, s, g);
     return hipGetLastError();
 }
 
@@ -594,7 +632,7 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
             if (g.a_ct) {
                 if (safe || varlen) return hipErrorInvalidValue;
                 if (g.staged) return go<double, true, false, GOP_SUB, false, false>(g, s);
-                return go_direct<GOP_SUB, true, false, false>(g, s);
+                return go_direct<double, GOP_SUB, true, false, false>(g, s);
             }
             if (g.staged) {
                 if (safe && varlen) return go<double, false, false, GOP_SUB, true, true>(g, s);
@@ -602,18 +640,19 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
                 if (varlen) return hipErrorInvalidValue;
                 return go<double, false, false, GOP_SUB, false, false>(g, s);
             }
-            if (safe && varlen) return go_direct<GOP_SUB, false, true, true>(g, s);
-            if (safe) return go_direct<GOP_SUB, false, true, false>(g, s);
+            if (safe && varlen) return go_direct<double, GOP_SUB, false, true, true>(g, s);
+            if (safe) return go_direct<double, GOP_SUB, false, true, false>(g, s);
             if (varlen) return hipErrorInvalidValue;
-            return go_direct<GOP_SUB, false, false, false>(g, s);
+            return go_direct<double, GOP_SUB, false, false, false>(g, s);
         case GOP_RESID:
             if (g.a_ct || g.b_ct || safe || varlen) return hipErrorInvalidValue;
-            return go<double, false, false, GOP_RESID, false, false>(g, s);
+            if (g.staged) return go<double, false, false, GOP_RESID, false, false>(g, s);
+            return go_direct<double, GOP_RESID, false, false, false>(g, s);
         case GOP_NEG_TRIU:
             if (g.a_ct || !g.b_ct || safe || varlen) return hipErrorInvalidValue;
             if (g.staged) return go<double, false, true, GOP_NEG_TRIU, false, false>(g, s);
             if (g.M != g.N) return hipErrorInvalidValue;
-            return go_direct<GOP_NEG_TRIU, false, false, false>(g, s);
+            return go_direct<double, GOP_NEG_TRIU, false, false, false>(g, s);
         default:
             return hipErrorInvalidValue;
     }
@@ -623,7 +662,8 @@ hipError_t launch_gemm_f32(const GemmArgs& g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (g.op != GOP_SUB || g.a_ct || g.b_ct || g.kb != nullptr || g.col_len != nullptr)
         return hipErrorInvalidValue;
-    return go<float, false, false, GOP_SUB, false, false>(g, s);
+    if (g.staged) return go<float, false, false, GOP_SUB, false, false>(g, s);
+    return go_direct<float, GOP_SUB, false, false, false>(g, s);
 }
 
 }  // namespace mst

@@ -321,12 +321,19 @@ def test_autograd_finite_differences(P):
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
 
 
-def test_residual_kernel(P):
-    w = W.c1_plain(seed=12, m=333, n=77)
-    X = np.asfortranarray(W.cnormal(W.rng(1), (333, 77)))
-    R = host(P.residual(dev(w.U), dev(w.shifts), dev(X), dev(w.B)))
+@pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (64, 130), (333, 77), (600, 33)])
+def test_residual_kernel(P, m, n):
+    """B0 - (U X - X diag(lam)) on the barrier-free MFMA GEMM (triangular K
+    range per wavefront); U's strict lower triangle holds NaN and must never
+    be read."""
+    w = W.c1_plain(seed=12 + m, m=m, n=n)
+    X = np.asfortranarray(W.cnormal(W.rng(1 + m), (m, n)))
+    Un = w.U.copy()
+    Un[np.tril_indices(m, -1)] = np.nan
+    R = host(P.residual(dev(Un), dev(w.shifts), dev(X), dev(w.B)))
     ref = w.B - (np.triu(w.U) @ X - X * w.shifts[None, :])
-    np.testing.assert_allclose(R, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+    assert np.all(np.isfinite(R))
+    np.testing.assert_allclose(R, ref, rtol=0, atol=1e-13 * max(1.0, np.abs(ref).max()) * max(1, m) ** 0.5)
 
 
 # ------------------------------------------------------------------ mixed precision
@@ -430,6 +437,10 @@ def test_staged_and_direct_gemm_agree(P, oracle_mod, safe):
                 X = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=32, outer_nb=128,
                                   staged=staged, fuse=fuse))
                 check_plain(oracle_mod, w.U, w.shifts, w.B, X)
+            # mixed precision: FP32 substitution GEMM and FP64 residual on either kernel
+            X = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=64, precision=1,
+                              max_sweeps=2, staged=staged))
+            check_plain(oracle_mod, w.U, w.shifts, w.B, X)
     else:
         U, lam, B = _growth(79, 450, 60)
         L = W.rng(790).integers(0, 451, 60).astype(np.int32)
