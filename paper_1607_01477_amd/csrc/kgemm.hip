@@ -528,29 +528,51 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 b0.re = ldexp(b0.re, e0 - kq0); b0.im = ldexp(b0.im, e0 - kq0);
                 b1.re = ldexp(b1.re, e1 - kq1); b1.im = ldexp(b1.im, e1 - kq1);
             }
-            if (TRI) {
-                b0.im = -b0.im;
-                b1.im = -b1.im;
+            if constexpr (sizeof(T) == 8) {
+                // acc -= A' B' with A' = conj(A) for A_CT, B' = conj(B) for TRI.
+                // FP64: every sign is an MFMA source modifier (the last operand's
+                // bit 0 negates A), so the loop spends no VALU on negation:
+                //   Re -= ar br - a'i b'i,  Im -= ar b'i + a'i br
+                constexpr int NRR = 1;
+                constexpr int NII = (A_CT != TRI) ? 1 : 0;   // + sa sb ai bi
+                constexpr int NRI = TRI ? 0 : 1;             // - sb ar bi
+                constexpr int NIR = A_CT ? 0 : 1;            // - sa ai br
+                accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.re, b0.re, accR[0][0], 0, 0, NRR);
+                accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.re, b1.re, accR[0][1], 0, 0, NRR);
+                accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.re, b0.re, accR[1][0], 0, 0, NRR);
+                accR[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.re, b1.re, accR[1][1], 0, 0, NRR);
+                accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.re, b0.im, accI[0][0], 0, 0, NRI);
+                accI[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.re, b1.im, accI[0][1], 0, 0, NRI);
+                accI[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.re, b0.im, accI[1][0], 0, 0, NRI);
+                accI[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.re, b1.im, accI[1][1], 0, 0, NRI);
+                accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.im, b0.im, accR[0][0], 0, 0, NII);
+                accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.im, b1.im, accR[0][1], 0, 0, NII);
+                accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.im, b0.im, accR[1][0], 0, 0, NII);
+                accR[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.im, b1.im, accR[1][1], 0, 0, NII);
+                accI[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.im, b0.re, accI[0][0], 0, 0, NIR);
+                accI[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.im, b1.re, accI[0][1], 0, 0, NIR);
+                accI[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.im, b0.re, accI[1][0], 0, 0, NIR);
+                accI[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.im, b1.re, accI[1][1], 0, 0, NIR);
+            } else {
+                // FP32 (plain operands): acc = C - A B with A negated
+                const T a0r = -a0.re, a1r = -a1.re, a0i = -a0.im, a1i = -a1.im;
+                accR[0][0] = Tr::mfma(a0r, b0.re, accR[0][0]);
+                accR[0][1] = Tr::mfma(a0r, b1.re, accR[0][1]);
+                accR[1][0] = Tr::mfma(a1r, b0.re, accR[1][0]);
+                accR[1][1] = Tr::mfma(a1r, b1.re, accR[1][1]);
+                accI[0][0] = Tr::mfma(a0r, b0.im, accI[0][0]);
+                accI[0][1] = Tr::mfma(a0r, b1.im, accI[0][1]);
+                accI[1][0] = Tr::mfma(a1r, b0.im, accI[1][0]);
+                accI[1][1] = Tr::mfma(a1r, b1.im, accI[1][1]);
+                accR[0][0] = Tr::mfma(-a0i, b0.im, accR[0][0]);
+                accR[0][1] = Tr::mfma(-a0i, b1.im, accR[0][1]);
+                accR[1][0] = Tr::mfma(-a1i, b0.im, accR[1][0]);
+                accR[1][1] = Tr::mfma(-a1i, b1.im, accR[1][1]);
+                accI[0][0] = Tr::mfma(a0i, b0.re, accI[0][0]);
+                accI[0][1] = Tr::mfma(a0i, b1.re, accI[0][1]);
+                accI[1][0] = Tr::mfma(a1i, b0.re, accI[1][0]);
+                accI[1][1] = Tr::mfma(a1i, b1.re, accI[1][1]);
             }
-            // acc = C - A B: A negated (and conjugated for A_CT)
-            const T a0r = -a0.re, a1r = -a1.re;
-            const T a0i = A_CT ? a0.im : -a0.im, a1i = A_CT ? a1.im : -a1.im;
-            accR[0][0] = Tr::mfma(a0r, b0.re, accR[0][0]);
-            accR[0][1] = Tr::mfma(a0r, b1.re, accR[0][1]);
-            accR[1][0] = Tr::mfma(a1r, b0.re, accR[1][0]);
-            accR[1][1] = Tr::mfma(a1r, b1.re, accR[1][1]);
-            accI[0][0] = Tr::mfma(a0r, b0.im, accI[0][0]);
-            accI[0][1] = Tr::mfma(a0r, b1.im, accI[0][1]);
-            accI[1][0] = Tr::mfma(a1r, b0.im, accI[1][0]);
-            accI[1][1] = Tr::mfma(a1r, b1.im, accI[1][1]);
-            accR[0][0] = Tr::mfma(-a0i, b0.im, accR[0][0]);
-            accR[0][1] = Tr::mfma(-a0i, b1.im, accR[0][1]);
-            accR[1][0] = Tr::mfma(-a1i, b0.im, accR[1][0]);
-            accR[1][1] = Tr::mfma(-a1i, b1.im, accR[1][1]);
-            accI[0][0] = Tr::mfma(a0i, b0.re, accI[0][0]);
-            accI[0][1] = Tr::mfma(a0i, b1.re, accI[0][1]);
-            accI[1][0] = Tr::mfma(a1i, b0.re, accI[1][0]);
-            accI[1][1] = Tr::mfma(a1i, b1.re, accI[1][1]);
         };
         if (nloc <= 0) return;
         // The ring is refilled without a condition (past the end the last
