@@ -575,6 +575,43 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             }
         };
         if (nloc <= 0) return;
+        if constexpr (!MASK) {
+            // Interior tiles (plain, full, K a multiple of 4, at least DEPTH
+            // k-steps): one running pointer per operand, advanced by a k-step
+            // per refill, so the loop spends one address add per operand
+            // instead of recomputing products; the main loop runs while every
+            // refill lies inside K, a short guarded tail drains the ring.
+            const long sA = A_CT ? 4 : 4L * g.lda, sB = TRI ? 4L * g.ldb : 4;
+            const CT* qa0 = A_CT ? A + (long)ra0 * g.lda + lq : A + (long)lq * g.lda + ra0;
+            const CT* qa1 = A_CT ? A + (long)ra1 * g.lda + lq : qa0 + 16;
+            const CT* qb0 = TRI ? B + (long)lq * g.ldb + cb0 : B + (long)cb0 * g.ldb + lq;
+            const CT* qb1 = TRI ? qb0 + 16 : B + (long)cb1 * g.ldb + lq;
+            auto next = [&](CT& a0, CT& a1, CT& b0, CT& b1) __attribute__((always_inline)) {
+                a0 = *qa0; a1 = *qa1; b0 = *qb0; b1 = *qb1;
+                qa0 += sA; qa1 += sA; qb0 += sB; qb1 += sB;
+            };
+#pragma unroll
+            for (int d = 0; d < DEPTH; ++d) next(pa0[d], pa1[d], pb0[d], pb1[d]);
+            int l0 = 0;
+            for (; l0 + 2 * DEPTH <= nloc; l0 += DEPTH) {
+#pragma unroll
+                for (int d = 0; d < DEPTH; ++d) {
+                    mma(l0 + d, pa0[d], pa1[d], pb0[d], pb1[d], 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    next(pa0[d], pa1[d], pb0[d], pb1[d]);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < DEPTH; ++d) {
+                mma(l0 + d, pa0[d], pa1[d], pb0[d], pb1[d], 0, 0);
+                if (l0 + d + DEPTH < nloc) next(pa0[d], pa1[d], pb0[d], pb1[d]);
+            }
+#pragma unroll
+            for (int d = 0; d < DEPTH; ++d)
+                if (l0 + DEPTH + d < nloc) mma(l0 + DEPTH + d, pa0[d], pa1[d], pb0[d], pb1[d], 0, 0);
+            return;
+        }
         // The ring is refilled without a condition (past the end the last
         // k-step is loaded again, in bounds and unused), so the main loop is
         // straight-line code; only the last nloc % DEPTH steps are guarded.
@@ -601,7 +638,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             if (l0 + d < nloc) mma(kfirst + l0 + d, pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
     };
     // interior tiles of the plain forms need no masking at all
-    if (full && (g.K & 3) == 0 && !VARLEN && !SAFE && !RES)
+    if (full && (g.K & 3) == 0 && nloc >= DEPTH && !VARLEN && !SAFE && !RES)
         kloop(std::false_type{});
     else
         kloop(std::true_type{});
