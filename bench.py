@@ -33,7 +33,7 @@ PEAK_FP64_MFMA_TF = 78.6
 # HBM bytes per launch of the substitution GEMM at this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs scaled by a 512 MiB copy (profiles/k_gemm_direct_solve_m4096_n4096.md).
 # Valid only for the GEMM source it was measured on (sha1 prefix of csrc/kgemm.hip).
-GEMM_TRAFFIC = {"kgemm_sha1": "bf7c2d2a32b17d44", "bytes_per_launch": 298.8e6, "m": 4096, "n": 4096,
+GEMM_TRAFFIC = {"kgemm_sha1": "2140b2487aa40a20", "bytes_per_launch": 291.7e6, "m": 4096, "n": 4096,
                 "nb": 16, "outer_nb": 256}
 PEAK_FP32_MFMA_TF = 157.3
 METRIC = "complex128 multi-shift solve GFLOP/s at m=n=4096 and % of MFMA peak vs plain FP64"
