@@ -174,8 +174,8 @@ hipError_t aux_get(int nev, Aux** out) {
 // ---------------------------------------------------------------- forward block loop
 // FP64 (b32 == nullptr) or mixed: the right-hand side lives in W32 (FP32) for the
 // substitution GEMMs and the diagonal blocks write FP64 X into B.
-// outer blocks per group of the two-level deferral in the one-stream forward loop
-constexpr int kSuperOuter = 4;
+// rows per group of the two-level deferral in the one-stream forward loop
+constexpr int kSuperRows = 1024;
 
 hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long ldu32,
                         const zd* lam, zd* B, long ldb, zf* W32, long ldw, const Opts& o,
@@ -315,13 +315,14 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             }
         }
         if (qa > 0) {
-            // Two-level deferral: inside a group of kSuperOuter outer blocks the
+            // Two-level deferral: inside a group of outer blocks (kSuperRows rows) the
             // rows above ob get X of ob (K = outer_nb); the rows above the whole
             // group get X of all its outer blocks in one GEMM once the group is
             // solved (K = its rows), so most of the substitution runs as a few
             // deep products instead of many K = outer_nb ones.
-            const int g_lo = (ob / kSuperOuter) * kSuperOuter;
-            const int g_hi = (g_lo + kSuperOuter - 1 < nob - 1) ? g_lo + kSuperOuter - 1 : nob - 1;
+            const int G = (o.outer < kSuperRows) ? kSuperRows / o.outer : 1;   // outer blocks per group
+            const int g_lo = (ob / G) * G;
+            const int g_hi = (g_lo + G - 1 < nob - 1) ? g_lo + G - 1 : nob - 1;
             const int g0 = q_first(g_lo) * nb;
             hipError_t e = substitute(ob, g0, qa * nb, s);
             if (e != hipSuccess) return e;
