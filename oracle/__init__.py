@@ -11,11 +11,16 @@ What each function follows (T. Moon, J. Poulson, arXiv 1607.01477):
   for each shift, the per-column content of Alg 3.
 * :func:`solve_safe` — Alg 4 (Sec. 3) per column (``nb=0``), or Alg 5 (Sec. 3)
   with decision block size ``nb``; scale factors ``s_j = 2^-k_j``.
+* :func:`solve_gen` — the generalized solve ``(U - lambda_j V) x_j = b_j``
+  of the appendix (Alg 8), unblocked: back substitution on the shifted pencil.
+* :func:`solve_safe_gen` — its safe form, Alg 9: Alg 4 on each shifted
+  diagonal block U(I1,I1) - lambda_j V(I1,I1), column bound with both norms.
 * :func:`solve_adjoint` — forward substitution with ``(U - lambda_j I)^H``, the
   lower-triangular variant noted in the footnote to Sec. 2.
 * :func:`gradient` — gradients of a real loss through the solve (not in the
   paper): ``gB = Y``, ``gU = -triu(Y X^H)``, ``glambda_j = x_j^H y_j``.
 * :func:`triang_eig` — TriangEig, Alg 6 (Sec. 4).
+* :func:`gen_triang_eig` — GeneralizedTriangEig (appendix, Alg 10).
 * :func:`lanczos_sigma_min` — second stage of the Van Loan/Lui method, Alg 7
   (Sec. 5): Lanczos on ``(U - zI)^{-H}(U - zI)^{-1}``.
 
@@ -69,7 +74,10 @@ def _load():
             lib.oracle_mstrsm.argtypes = [I, I, P, I, P, P, I]
             lib.oracle_mstrsm_adjoint.argtypes = [I, I, P, I, P, P, I]
             lib.oracle_mstrsm_safe.argtypes = [I, I, P, I, P, P, I, P, P, P, I, I, I, P]
-            for f in (lib.oracle_mstrsm, lib.oracle_mstrsm_adjoint, lib.oracle_mstrsm_safe):
+            lib.oracle_mstrsm_gen.argtypes = [I, I, P, I, P, I, P, P, I]
+            lib.oracle_mstrsm_safe_gen.argtypes = [I, I, P, I, P, I, P, P, I, P, P, P, I, I, I]
+            for f in (lib.oracle_mstrsm, lib.oracle_mstrsm_adjoint, lib.oracle_mstrsm_safe,
+                      lib.oracle_mstrsm_gen, lib.oracle_mstrsm_safe_gen):
                 f.restype = I
             lib.oracle_num_threads.restype = I
             lib.oracle_set_num_threads.argtypes = [I]
@@ -104,6 +112,23 @@ def solve(U, lam, B) -> np.ndarray:
     rc = _load().oracle_mstrsm(m, n, _ptr(U), max(1, m), _ptr(lam), _ptr(X), max(1, m))
     if rc != 0:
         raise RuntimeError("oracle_mstrsm failed: %d" % rc)
+    return X
+
+
+def solve_gen(U, V, lam, B) -> np.ndarray:
+    """X with (U - lam[j] V) X[:, j] = B[:, j], U and V upper triangular
+    (appendix, Alg 8; plain, singular systems give inf/NaN)."""
+    U = _cm(U)
+    V = _cm(V)
+    lam = np.ascontiguousarray(lam, dtype=np.complex128)
+    X = _cm(B).copy(order="F")
+    m, n = X.shape
+    if U.shape != (m, m) or V.shape != (m, m) or lam.shape != (n,):
+        raise ValueError("shape mismatch")
+    rc = _load().oracle_mstrsm_gen(m, n, _ptr(U), max(1, m), _ptr(V), max(1, m), _ptr(lam), _ptr(X),
+                                   max(1, m))
+    if rc != 0:
+        raise RuntimeError("oracle_mstrsm_gen failed: %d" % rc)
     return X
 
 
@@ -157,6 +182,33 @@ def solve_safe(U, lam, B, col_len=None, nb: int = 64, omega_log2: int = OMEGA_LO
     return X, scale, k
 
 
+def solve_safe_gen(U, V, lam, B, col_len=None, nb: int = 64, omega_log2: int = OMEGA_LOG2,
+                   force_phase2: bool = False):
+    """Safe generalized solve (appendix, Alg 9): returns (X, scale, k) with
+    (U - lam_j V) X_j = 2^-k_j B_j. nb and col_len as in :func:`solve_safe`."""
+    U = _cm(U)
+    V = _cm(V)
+    lam = np.ascontiguousarray(lam, dtype=np.complex128)
+    X = _cm(B).copy(order="F")
+    m, n = X.shape
+    if U.shape != (m, m) or V.shape != (m, m) or lam.shape != (n,):
+        raise ValueError("shape mismatch")
+    cl = None
+    if col_len is not None:
+        cl = np.ascontiguousarray(col_len, dtype=np.int32)
+        if cl.shape != (n,):
+            raise ValueError("col_len shape")
+    scale = np.zeros(n, dtype=np.float64)
+    k = np.zeros(n, dtype=np.int32)
+    rc = _load().oracle_mstrsm_safe_gen(m, n, _ptr(U), max(1, m), _ptr(V), max(1, m), _ptr(lam),
+                                        _ptr(X), max(1, m), _ptr(cl) if cl is not None else None,
+                                        _ptr(scale), _ptr(k), int(nb), int(omega_log2),
+                                        int(bool(force_phase2)))
+    if rc != 0:
+        raise RuntimeError("oracle_mstrsm_safe_gen failed: %d" % rc)
+    return X, scale, k
+
+
 def gradient(U, lam, X, Y):
     """Gradients of a real loss L through X = solve(U, lam, B), given
     Y = solve_adjoint(U, lam, dL/dX) (PyTorch convention: the gradient of a
@@ -182,6 +234,23 @@ def triang_eig(T, nb: int = 64, omega_log2: int = OMEGA_LOG2, force_phase2: bool
     col_len = np.arange(m, dtype=np.int32)
     Z, s, k = solve_safe(T, lam, Z, col_len=col_len, nb=nb, omega_log2=omega_log2,
                          force_phase2=force_phase2)
+    Z[np.arange(m), np.arange(m)] = s
+    return lam, Z, k
+
+
+def gen_triang_eig(T, S, nb: int = 64, omega_log2: int = OMEGA_LOG2):
+    """GeneralizedTriangEig (appendix, Alg 10): lam = diag(T) / diag(S);
+    Z = -T + S diag(lam) with zero diagonal (upper triangular, so column j
+    has rows [0, j) only); safe generalized solve; diag(Z) = s.
+    Returns (lam, Z, k) with T Z[:, j] = lam_j S Z[:, j] and Z(j, j) = 2^-k_j.
+    The diagonal of S must be nonzero (finite eigenvalues)."""
+    T = _cm(T)
+    S = _cm(S)
+    m = T.shape[0]
+    lam = np.array(np.diag(T) / np.diag(S), dtype=np.complex128)
+    Z = np.asfortranarray(np.triu(-T + S * lam[None, :], 1))
+    col_len = np.arange(m, dtype=np.int32)
+    Z, s, k = solve_safe_gen(T, S, lam, Z, col_len=col_len, nb=nb, omega_log2=omega_log2)
     Z[np.arange(m), np.arange(m)] = s
     return lam, Z, k
 

@@ -99,6 +99,38 @@ int oracle_mstrsm(int m, int n, const double* Up, int ldu, const double* lamp,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Generalized plain solve (appendix, Alg 8): (U - lambda_j V) x_j = b_j     */
+/* with V upper triangular. Back substitution on the shifted matrix, whose   */
+/* entries are formed as U(r,c) - lambda_j * V(r,c) (the xAXPY of Alg 8).   */
+/* Alg 8 blocks the same arithmetic (its second GEMM adds V * (lambda x),    */
+/* i.e. subtracts the -lambda V part of the shifted entries), so the         */
+/* unblocked form is the definition. V's strict lower triangle is never read.*/
+/* ------------------------------------------------------------------------ */
+static void trsv_gen(int m, const zc* U, int ldu, const zc* V, int ldv, zc lam, zc* b) {
+    for (int i = m - 1; i >= 0; --i) {
+        zc d = zsub(AT(U, ldu, i, i), zmul(lam, AT(V, ldv, i, i)));
+        zc x = zdiv(b[i], d);
+        b[i] = x;
+        const zc* ucol = &AT(U, ldu, 0, i);
+        const zc* vcol = &AT(V, ldv, 0, i);
+        for (int r = 0; r < i; ++r) b[r] = zaxpy_neg(b[r], zsub(ucol[r], zmul(lam, vcol[r])), x);
+    }
+}
+
+int oracle_mstrsm_gen(int m, int n, const double* Up, int ldu, const double* Vp, int ldv,
+                      const double* lamp, double* Bp, int ldb) {
+    if (m < 0 || n < 0 || ldu < (m > 1 ? m : 1) || ldv < (m > 1 ? m : 1) || ldb < (m > 1 ? m : 1))
+        return -1;
+    const zc* U = (const zc*)Up;
+    const zc* V = (const zc*)Vp;
+    const zc* lam = (const zc*)lamp;
+    zc* B = (zc*)Bp;
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) trsv_gen(m, U, ldu, V, ldv, lam[j], &AT(B, ldb, 0, j));
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Adjoint solve: (U - lambda_j I)^H y_j = g_j. U^H is lower triangular, so */
 /* this is forward substitution (the lower-triangular variant the paper     */
 /* notes in its footnote to Sec. 2):                                        */
@@ -384,6 +416,151 @@ int oracle_mstrsm_safe(int m, int n, const double* Up, int ldu, const double* la
     free(cn_in);
     free(above);
     free(above_sum);
+    return 0;
+}
+
+/*
+ * Safe generalized solve (appendix, Alg 9): (U - lambda_j V) x_j = s_j b_j,
+ * s_j = 2^-k_j, U and V upper triangular.
+ *
+ * Per column and decision block (blocks as in the safe solve above):
+ *   - the shifted diagonal block U' = U(I1,I1) - lambda_j V(I1,I1) is formed
+ *     entry by entry (the xAXPY of Alg 9) and Alg 4 runs on it: its pivots
+ *     are the diagonal of U', its column norms those of U' above the diagonal
+ *     inside the block;
+ *   - a rescale t < 1 from the block scales B(I0,j), B(I2,j), s_j and G(j);
+ *   - the column bound adds sum_{k in I1} (||U(I0,k)||_inf +
+ *     |lambda_j| ||V(I0,k)||_inf) * ||B(I1,j)||_inf, evaluated as
+ *     above_sum_U + cabs1(lambda_j) * above_sum_V, then rescales B(:,j) when
+ *     it reaches Omega;
+ *   - substitution: C = lambda_j X(I1,j), B(I0,j) -= U(I0,I1) X(I1,j), then
+ *     B(I0,j) += V(I0,I1) C (the two xGEMM steps of Alg 9, columns of the
+ *     block from last to first).
+ * nb <= 0 or nb >= m: one block, i.e. Alg 4 on the whole shifted matrix.
+ * A pivot of U' that is exactly zero is replaced by
+ * delta = 2^-52 * max(max cabs1(U), max cabs1(V)) (2^-1022 if both are zero).
+ * col_len (nullable): as in the safe solve above.
+ */
+int oracle_mstrsm_safe_gen(int m, int n, const double* Up, int ldu, const double* Vp, int ldv,
+                           const double* lamp, double* Bp, int ldb, const int* col_len,
+                           double* scale, int* klog, int nb, int omega_log2, int force_phase2) {
+    if (m < 0 || n < 0 || ldu < (m > 1 ? m : 1) || ldv < (m > 1 ? m : 1) || ldb < (m > 1 ? m : 1))
+        return -1;
+    if (omega_log2 <= 0) omega_log2 = 960;
+    if (omega_log2 < 2 || omega_log2 > 1000) return -2;
+    const zc* U = (const zc*)Up;
+    const zc* V = (const zc*)Vp;
+    const zc* lam = (const zc*)lamp;
+    zc* B = (zc*)Bp;
+    int unblocked = (nb <= 0 || nb >= m);
+    int nbe = unblocked ? (m > 0 ? m : 1) : nb;
+    int nblk = (m + nbe - 1) / nbe;
+    size_t mm = (size_t)(m > 0 ? m : 1);
+
+    double* scratch = (double*)malloc(sizeof(double) * (4 * mm + 2 * (size_t)(nblk > 0 ? nblk : 1)));
+    double *cnU = scratch, *aboveU = scratch + mm, *cnV = scratch + 2 * mm, *aboveV = scratch + 3 * mm;
+    double *asumU = scratch + 4 * mm, *asumV = asumU + (nblk > 0 ? nblk : 1);
+    double umax = 0.0, vmax = 0.0;
+    column_norms(m, U, ldu, nbe, cnU, aboveU, &umax);
+    column_norms(m, V, ldv, nbe, cnV, aboveV, &vmax);
+    for (int bi = 0; bi < nblk; ++bi) {
+        double su = 0.0, sv = 0.0;
+        int c1 = (bi + 1) * nbe < m ? (bi + 1) * nbe : m;
+        for (int c = bi * nbe; c < c1; ++c) { su = su + aboveU[c]; sv = sv + aboveV[c]; }
+        asumU[bi] = su;
+        asumV[bi] = sv;
+    }
+
+    safe_cfg cfg;
+    cfg.omega_log2 = omega_log2;
+    cfg.omega = ldexp(1.0, omega_log2);
+    cfg.force_phase2 = force_phase2;
+    double mx = fmax(umax, vmax);
+    cfg.delta = (mx > 0.0) ? ldexp(mx, -52) : ldexp(1.0, -1022);
+    const int w = omega_log2;
+    const double omega = cfg.omega;
+    const zc zero = {0.0, 0.0};
+
+    #pragma omp parallel
+    {
+        zc* Ub = (zc*)malloc(sizeof(zc) * (size_t)nbe * (size_t)nbe);
+        zc* buf = (zc*)malloc(sizeof(zc) * (size_t)nbe);
+        zc* Cb = (zc*)malloc(sizeof(zc) * (size_t)nbe);
+        double* cnb = (double*)malloc(sizeof(double) * (size_t)nbe);
+        #pragma omp for schedule(static)
+        for (int j = 0; j < n; ++j) {
+            zc* b = &AT(B, ldb, 0, j);
+            const zc lj = lam[j];
+            const double labs = cabs1(lj);
+            int L = col_len ? col_len[j] : m;
+            if (L > m) L = m;
+            if (L < 0) L = 0;
+            int kj = 0;
+            double G = 0.0;
+            for (int r = 0; r < L; ++r) G = fmax(G, cabs1(b[r]));
+            for (int bi = nblk - 1; bi >= 0; --bi) {
+                int i0 = bi * nbe;
+                int i1 = (i0 + nbe < m) ? i0 + nbe : m;
+                int bs = i1 - i0;
+                if (i0 >= L) continue;
+                /* U' = U(I1,I1) - lambda_j V(I1,I1) and its column norms */
+                for (int c = 0; c < bs; ++c) {
+                    double cm = 0.0;
+                    for (int r = 0; r <= c; ++r) {
+                        zc e = zsub(AT(U, ldu, i0 + r, i0 + c), zmul(lj, AT(V, ldv, i0 + r, i0 + c)));
+                        AT(Ub, nbe, r, c) = e;
+                        if (r < c) cm = fmax(cm, cabs1(e));
+                    }
+                    cnb[c] = cm;
+                }
+                /* diagonal block step: Alg 4 on U' (its shift is already applied) */
+                for (int r = 0; r < bs; ++r) buf[r] = (i0 + r < L) ? b[i0 + r] : zero;
+                int kb = safe_trsv(bs, Ub, nbe, 0, zero, buf, cnb, &cfg);
+                for (int r = 0; r < bs; ++r) if (i0 + r < L) b[i0 + r] = buf[r];
+                if (kb > 0) {
+                    for (int r = 0; r < i0; ++r) b[r] = zscale2(b[r], kb);
+                    for (int r = i1; r < L; ++r) b[r] = zscale2(b[r], kb);
+                    G = ldexp(G, -kb);
+                    kj += kb;
+                }
+                /* column bound with the pencil's two norms */
+                double xn = 0.0;
+                for (int r = 0; r < bs; ++r) xn = fmax(xn, cabs1(buf[r]));
+                double a = asumU[bi] + labs * asumV[bi];
+                double Gn;
+                int k2 = bound_add(G, a, xn, w, omega, &Gn);
+                if (k2 > 0) {
+                    for (int r = 0; r < L; ++r) b[r] = zscale2(b[r], k2);
+                    kj += k2;
+                }
+                G = Gn;
+                /* substitution: C = lambda X(I1), B(I0) -= U(I0,I1) X(I1), B(I0) += V(I0,I1) C */
+                int cend = (i1 < L) ? i1 : L;   /* zero entries of x contribute nothing */
+                for (int c = i0; c < cend; ++c) Cb[c - i0] = zmul(lj, b[c]);
+                for (int c = cend - 1; c >= i0; --c) {
+                    zc x = b[c];
+                    const zc* col = &AT(U, ldu, 0, c);
+                    for (int r = 0; r < i0; ++r) b[r] = zaxpy_neg(b[r], col[r], x);
+                }
+                for (int c = cend - 1; c >= i0; --c) {
+                    zc cc = Cb[c - i0];
+                    const zc* col = &AT(V, ldv, 0, c);
+                    for (int r = 0; r < i0; ++r) {
+                        zc p = zmul(col[r], cc);
+                        b[r].re = b[r].re + p.re;
+                        b[r].im = b[r].im + p.im;
+                    }
+                }
+            }
+            klog[j] = kj;
+            scale[j] = ldexp(1.0, -kj);
+        }
+        free(Ub);
+        free(buf);
+        free(Cb);
+        free(cnb);
+    }
+    free(scratch);
     return 0;
 }
 

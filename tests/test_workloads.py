@@ -60,3 +60,20 @@ def test_c4_grid():
     assert len(np.unique(np.round(z.real, 12))) == 100
     np.testing.assert_allclose(np.linalg.norm(w.B, axis=0), 1.0, rtol=1e-14)
     assert abs(W.nominal_flops(2000, 10000) * 30 / 1e12 - 4.8) < 0.01
+
+
+def test_c6_c7_generalized_pencils():
+    w = W.c6_generalized(m=256, n=64)
+    V = w.extra["V"]
+    assert V.shape == (256, 256) and V.flags.f_contiguous
+    assert np.all(np.tril(V, -1) == 0) and np.all(np.tril(w.U, -1) == 0)
+    dv = np.diag(V)
+    assert np.all(dv.imag == 0) and dv.real.min() >= 0.5 and dv.real.max() <= 1.5
+    assert np.all(np.abs(w.shifts) <= 0.2)
+    # pivots of U - lambda V stay away from zero: |u| >= 0.5, |lambda v| <= 0.3
+    piv = np.diag(w.U)[:, None] - w.shifts[None, :] * dv[:, None]
+    assert np.abs(piv).min() >= 0.2
+    w7 = W.c7_gen_triang_eig(m=128)
+    S = w7.extra["S"]
+    assert np.all(np.tril(S, -1) == 0) and np.all(np.diag(S).real >= 0.5)
+    assert np.array_equal(w7.col_len, np.arange(128)) and w7.B is None

@@ -14,7 +14,7 @@ Conventions
   interfaces take. U is upper triangular; its strict lower triangle is zero
   here (the solvers never read it).
 
-The five workloads stand in for the paper's own test matrices (random
+The workloads stand in for the paper's own test matrices (random
 triangular factors with shifts near the spectrum, triangular eigenvectors,
 a 100x100 grid of pseudospectra shifts), which are not available as data:
 see the experimental-results section of the paper.
@@ -29,7 +29,7 @@ import numpy as np
 __all__ = [
     "rng", "cnormal", "disk_uniform", "random_upper",
     "Workload", "c1_plain", "c2_triang_eig", "c3_mixed", "c4_pseudospectra",
-    "c5_adjoint", "WORKLOADS", "nominal_flops",
+    "c5_adjoint", "c6_generalized", "c7_gen_triang_eig", "WORKLOADS", "nominal_flops",
 ]
 
 
@@ -164,12 +164,43 @@ def c5_adjoint(seed: int = 5, m: int = 4096, n: int = 2048) -> Workload:
     return Workload("c5_adjoint", U, lam, B, extra={"W": W})
 
 
+def c6_generalized(seed: int = 6, m: int = 4096, n: int = 4096) -> Workload:
+    """Generalized solve (U - lambda_j V) x_j = b_j on a triangular pencil:
+    U as the mixed-precision workload (off-diagonal CN(0,1)/sqrt(m), diagonal
+    area-uniform on the annulus 0.5 <= |d| <= 2); V off-diagonal
+    CN(0,1)/sqrt(m), diagonal real uniform in [0.5, 1.5] (the real
+    non-negative diagonal a complex QZ factorisation gives); shifts uniform in
+    the disk of radius 0.2; B iid CN(0,1). V is in extra["V"]."""
+    g = rng(seed)
+    d = annulus_uniform(g, m, 0.5, 2.0)
+    U = random_upper(g, m, 1.0 / math.sqrt(m), d)
+    V = random_upper(g, m, 1.0 / math.sqrt(m), (0.5 + g.random(m)).astype(np.complex128))
+    lam = disk_uniform(g, n, 0.2)
+    B = np.asfortranarray(cnormal(g, (m, n)))
+    return Workload("c6_generalized", U, lam, B, extra={"V": V})
+
+
+def c7_gen_triang_eig(seed: int = 7, m: int = 2048) -> Workload:
+    """Generalized triangular eigenvectors of the pencil (T, S): T as the
+    triangular-eigenvector workload without repeats (off-diagonal CN(0,1),
+    diagonal CN(0,1)), S off-diagonal CN(0,1)/sqrt(m), diagonal real uniform in
+    [0.5, 1.5]. Shifts and right-hand sides are formed by the solver from
+    (T, S); S is in extra["S"]."""
+    g = rng(seed)
+    T = random_upper(g, m, 1.0, cnormal(g, m))
+    S = random_upper(g, m, 1.0 / math.sqrt(m), (0.5 + g.random(m)).astype(np.complex128))
+    return Workload("c7_gen_triang_eig", T, np.zeros(m, dtype=np.complex128), None,
+                    np.arange(m, dtype=np.int32), extra={"S": S})
+
+
 WORKLOADS = {
     "c1_plain": c1_plain,
     "c2_triang_eig": c2_triang_eig,
     "c3_mixed": c3_mixed,
     "c4_pseudospectra": c4_pseudospectra,
     "c5_adjoint": c5_adjoint,
+    "c6_generalized": c6_generalized,
+    "c7_gen_triang_eig": c7_gen_triang_eig,
 }
 
 
