@@ -76,7 +76,8 @@ def _time(fn, torch, reps):
 
 def other_workloads(P, W, torch, np) -> dict:
     """Triangular eigenvectors (safe solve, variable-length columns), inverse
-    Lanczos on a 100x100 shift grid, and forward + backward through the solve."""
+    Lanczos on a 100x100 shift grid, forward + backward through the solve, the
+    generalized (pencil) solve and generalized triangular eigenvectors."""
     out = {}
     # triangular eigenvectors, m = 2048: sum_j 4 j^2 flops
     w = W.c2_triang_eig()
@@ -121,6 +122,30 @@ def other_workloads(P, W, torch, np) -> dict:
     out["c5_fwd_bwd_m4096_n2048"] = {"fwd_ms": round(ms_f, 3), "fwd_bwd_ms": round(ms_fb, 3),
                                      "fwd_bwd_gflops": round(3 * ffl / (ms_fb * 1e-3) / 1e9, 2)}
     log("forward %.3f ms, forward+backward %.3f ms" % (ms_f, ms_fb))
+    del U, s, B, Wt
+    # generalized (pencil) solve, m = n = 4096: 8 m^2 n flops (U X and V (lambda X))
+    w = W.c6_generalized()
+    Ug, Vg = dev(w.U, torch), dev(w.extra["V"], torch)
+    sg = torch.from_numpy(w.shifts).cuda()
+    Bg = dev(w.B, torch)
+    ms_g = _time(lambda: P.mstrsm_gen(Ug, Vg, sg, Bg), torch, 3)
+    Bg.copy_(dev(w.B, torch))
+    ms_gs = _time(lambda: P.mstrsm_safe_gen(Ug, Vg, sg, Bg), torch, 3)
+    gfl = 2 * W.nominal_flops(w.m, w.n)
+    out["c6_generalized_m4096_n4096"] = {
+        "ms": round(ms_g, 3), "gflops": round(gfl / (ms_g * 1e-3) / 1e9, 2),
+        "safe_ms": round(ms_gs, 3), "safe_gflops": round(gfl / (ms_gs * 1e-3) / 1e9, 2)}
+    log("generalized solve 4096 x 4096: %.3f ms plain, %.3f ms safe" % (ms_g, ms_gs))
+    del Ug, Vg, Bg
+    # generalized triangular eigenvectors, m = 2048: sum_j 8 j^2 flops
+    w = W.c7_gen_triang_eig()
+    T, S = dev(w.U, torch), dev(w.extra["S"], torch)
+    ms = _time(lambda: P.gen_triang_eig(T, S), torch, 3)
+    ev, Z, k = P.gen_triang_eig(T, S)
+    fl = 2 * W.nominal_flops(w.m, w.m, w.col_len)
+    out["c7_gen_triang_eig_m2048"] = {"ms": round(ms, 3), "gflops": round(fl / (ms * 1e-3) / 1e9, 2),
+                                      "rescaled_columns": int((k > 0).sum().item())}
+    log("generalized triangular eigenvectors m=2048: %.3f ms" % ms)
     return out
 
 

@@ -155,6 +155,54 @@ mst_status mst_triang_eig(int m, const void* T, int ldt, void* Z, int ldz, void*
                           int* scale_log2, const mst_opts* opt, void* stream);
 
 /*
+ * mstrsm_gen — generalized multi-shift solve, appendix (Alg 8):
+ *     (U - shifts[j] V) X(:,j) = B(:,j),   j = 0..n-1,
+ * with U and V upper triangular (e.g. the triangular pair of a generalized
+ * Schur form). The diagonal blocks are solved with U' = U - shifts[j] V
+ * formed per shift; the rows above receive U X and V (shifts * X) as two
+ * matrix products.
+ *   V, ldv    m x m upper triangular, read only (strict lower triangle not read)
+ *   other arguments as for mstrsm
+ * Supported: nb = 16 (the default), precision 0; otherwise MST_EUNSUPPORTED.
+ * Singular systems give Inf/NaN like mstrsm.
+ */
+mst_status mstrsm_gen(int m, int n, const void* U, int ldu, const void* V, int ldv,
+                      const void* shifts, void* B, int ldb, const mst_opts* opt, void* stream);
+
+/*
+ * mstrsm_safe_gen — safe generalized multi-shift solve, appendix (Alg 9):
+ *     (U - shifts[j] V) X(:,j) = s_j B(:,j),  s_j = 2^-k_j,
+ * as mstrsm_safe, with: the checked back substitution (Alg 4) run on each
+ * shifted diagonal block U' = U - shifts[j] V (its pivots, and its column norms
+ * above the diagonal inside the block, per shift); the column growth bound
+ * adding sum_k (||U(I0,k)||_inf + |shifts[j]|_1 ||V(I0,k)||_inf) ||X(I1,j)||_inf
+ * over the columns k of the block; exactly zero pivots replaced by
+ * delta = 2^-52 max(max|U|_1, max|V|_1).
+ *   arguments as for mstrsm_safe, plus V, ldv as for mstrsm_gen
+ * Supported: nb = 16 (the default); otherwise MST_EUNSUPPORTED.
+ */
+mst_status mstrsm_safe_gen(int m, int n, const void* U, int ldu, const void* V, int ldv,
+                           const void* shifts, void* B, int ldb, const int* col_len,
+                           double* scale, int* scale_log2, const mst_opts* opt, void* stream);
+
+/*
+ * mst_gen_triang_eig — GeneralizedTriangEig, appendix (Alg 10): eigenvectors
+ * of the upper triangular pencil (T, S) through one safe generalized solve:
+ * eigvals[j] = T(j,j) / S(j,j); Z(:,j) = [z; s_j; 0] with
+ *   (T - eigvals[j] S)(0:j,0:j) z = -s_j (T - eigvals[j] S)(0:j, j),
+ * so that T Z(:,j) = eigvals[j] S Z(:,j) and Z(j,j) = s_j = 2^-k_j.
+ *   T, ldt; S, lds   m x m upper triangular, read only; S(j,j) must be nonzero
+ *                    (finite eigenvalues), otherwise the column is Inf/NaN
+ *   Z, ldz           m x m output (the strict lower triangle is set to 0)
+ *   eigvals          m complex output
+ *   scale_log2       nullable, m int32 output (k_j)
+ * Supported: nb = 16 (the default); otherwise MST_EUNSUPPORTED.
+ */
+mst_status mst_gen_triang_eig(int m, const void* T, int ldt, const void* S, int lds, void* Z,
+                              int ldz, void* eigvals, int* scale_log2, const mst_opts* opt,
+                              void* stream);
+
+/*
  * mst_lanczos_sigma_min — second stage of the Van Loan/Lui method (Alg 7,
  * Sec. 5): for every shift z_j, `iters` steps of plain Lanczos (no
  * reorthogonalisation) on (U - z_j I)^{-H} (U - z_j I)^{-1}, each product

@@ -22,7 +22,8 @@ from . import _lib
 from ._lib import MstError, MstOpts
 
 __all__ = ["mstrsm", "mstrsm_safe", "mstrsm_adjoint", "grad_u", "grad_shift", "residual",
-           "triang_eig", "lanczos_sigma_min", "solve", "MultiShiftSolve", "colmajor",
+           "triang_eig", "lanczos_sigma_min", "mstrsm_gen", "mstrsm_safe_gen", "gen_triang_eig",
+           "solve", "MultiShiftSolve", "colmajor",
            "MstError", "version", "lib_path"]
 
 lib_path = _lib.LIB_PATH
@@ -216,6 +217,63 @@ def triang_eig(T, *, nb=0, outer_nb=0, omega_log2=0):
     rc = _lib.load().mst_triang_eig(m, _p(T), _ld(T), _p(Z), max(1, m), _p(ev), _p(klog),
                                     ctypes.byref(o), _stream())
     _lib.check("mst_triang_eig", rc)
+    return ev, Z, klog
+
+
+def mstrsm_gen(U, V, shifts, B, *, outer_nb=0, fuse=True, overlap=False):
+    """Generalized solve (appendix, Alg 8): X with
+    (U - shifts[j] V) X[:, j] = B[:, j] (nb = 16; B overwritten when column-major)."""
+    U = _mat(U, "U")
+    V = _mat(V, "V")
+    X = _mat(B, "B")
+    m, n = X.shape
+    if U.shape != (m, m) or V.shape != (m, m):
+        raise ValueError("U and V must be %d x %d" % (m, m))
+    s = _vec(shifts, n, "shifts")
+    o = _opts(outer_nb=outer_nb, fuse=fuse, overlap=overlap)
+    rc = _lib.load().mstrsm_gen(m, n, _p(U), _ld(U), _p(V), _ld(V), _p(s), _p(X), _ld(X),
+                                ctypes.byref(o), _stream())
+    _lib.check("mstrsm_gen", rc)
+    return X
+
+
+def mstrsm_safe_gen(U, V, shifts, B, col_len=None, *, outer_nb=0, omega_log2=0, fuse=True,
+                    overlap=False):
+    """Safe generalized solve (appendix, Alg 9): returns (X, scale, scale_log2) with
+    (U - shifts[j] V) X[:, j] = scale[j] B[:, j], scale[j] = 2^-scale_log2[j]."""
+    U = _mat(U, "U")
+    V = _mat(V, "V")
+    X = _mat(B, "B")
+    m, n = X.shape
+    if U.shape != (m, m) or V.shape != (m, m):
+        raise ValueError("U and V must be %d x %d" % (m, m))
+    s = _vec(shifts, n, "shifts")
+    cl = _vec(col_len, n, "col_len", torch.int32) if col_len is not None else None
+    scale = torch.empty(n, dtype=torch.float64, device=X.device)
+    klog = torch.empty(n, dtype=torch.int32, device=X.device)
+    o = _opts(outer_nb=outer_nb, omega_log2=omega_log2, fuse=fuse, overlap=overlap)
+    rc = _lib.load().mstrsm_safe_gen(m, n, _p(U), _ld(U), _p(V), _ld(V), _p(s), _p(X), _ld(X),
+                                     _p(cl), _p(scale), _p(klog), ctypes.byref(o), _stream())
+    _lib.check("mstrsm_safe_gen", rc)
+    return X, scale, klog
+
+
+def gen_triang_eig(T, S, *, outer_nb=0, omega_log2=0, fuse=True):
+    """GeneralizedTriangEig (appendix, Alg 10): returns (eigvals, Z, scale_log2)
+    with T Z[:, j] = eigvals[j] S Z[:, j], eigvals[j] = T[j, j] / S[j, j],
+    Z upper triangular, Z[j, j] = 2^-scale_log2[j]."""
+    T = _mat(T, "T")
+    S = _mat(S, "S")
+    m = T.shape[0]
+    if T.shape != (m, m) or S.shape != (m, m):
+        raise ValueError("T and S must be square and of one size")
+    Z = torch.empty_strided((m, m), (1, max(1, m)), dtype=torch.complex128, device=T.device)
+    ev = torch.empty(m, dtype=torch.complex128, device=T.device)
+    klog = torch.empty(m, dtype=torch.int32, device=T.device)
+    o = _opts(outer_nb=outer_nb, omega_log2=omega_log2, fuse=fuse)
+    rc = _lib.load().mst_gen_triang_eig(m, _p(T), _ld(T), _p(S), _ld(S), _p(Z), max(1, m), _p(ev),
+                                        _p(klog), ctypes.byref(o), _stream())
+    _lib.check("mst_gen_triang_eig", rc)
     return ev, Z, klog
 
 

@@ -81,7 +81,9 @@ hipError_t timed(int kind, double flops, hipStream_t s, F&& launch) {
     return e;
 }
 
-double gemm_flops(const GemmArgs& g) { return 8.0 * g.M * (double)g.N * g.K; }
+double gemm_flops(const GemmArgs& g) {
+    return (g.op == GOP_GEN_SUB ? 16.0 : 8.0) * g.M * (double)g.N * g.K;
+}
 
 struct Opts {
     int nb = 16, outer = 256, precision = 0, sweeps = 2, omega_log2 = 960;
@@ -174,12 +176,15 @@ hipError_t aux_get(int nev, Aux** out) {
 // ---------------------------------------------------------------- forward block loop
 // FP64 (b32 == nullptr) or mixed: the right-hand side lives in W32 (FP32) for the
 // substitution GEMMs and the diagonal blocks write FP64 X into B.
+// V != nullptr: the pencil U - lambda_j V (FP64, nb = 16): diagonal blocks of
+// U - lambda_j V, substitution C -= U X - V (lambda X) (Alg 8 / Alg 9).
 // rows per group of the two-level deferral in the one-stream forward loop
 constexpr int kSuperRows = 1024;
 
 hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long ldu32,
                         const zd* lam, zd* B, long ldb, zf* W32, long ldw, const Opts& o,
-                        const SafeState* safe, const int* col_len, hipStream_t s) {
+                        const SafeState* safe, const int* col_len, hipStream_t s,
+                        const zd* V = nullptr, long ldv = 0) {
     const int nb = o.nb, P = o.outer / o.nb;
     const int nblk = (m + nb - 1) / nb;
     const int nob = (nblk + P - 1) / P;
@@ -207,6 +212,10 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             g.A = U + (long)x0 * ldu + r0; g.lda = ldu;
             g.B = B + x0; g.ldb = ldb;
             g.C = B + r0; g.ldc = ldb;
+            if (V) {
+                g.op = GOP_GEN_SUB;
+                g.A2 = V + (long)x0 * ldv + r0; g.lda2 = ldv; g.glam = lam;
+            }
             return timed(MST_PROF_GEMM_F64, gemm_flops(g), st, [&] { return launch_gemm_f64(g, st); });
         }
         g.A = U32 + (long)x0 * ldu32 + r0; g.lda = ldu32;
@@ -224,6 +233,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
         b.m = m; b.n = n; b.nb = nb; b.qa = qa; b.iS = qa * nb;
         b.rows = row_end(ob) - qa * nb;
         b.U = U; b.ldu = ldu; b.lam = lam; b.B = B; b.ldb = ldb;
+        b.V = V; b.ldv = ldv;
         b.b32 = mixed ? W32 : nullptr; b.ldb32 = ldw;
         b.col_len = col_len;
         if (safe) {
@@ -232,7 +242,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
         } else {
             b.safe.omega_log2 = o.omega_log2;
         }
-        const double fl = 4.0 * b.rows * (double)b.rows * n;
+        const double fl = (V ? 8.0 : 4.0) * b.rows * (double)b.rows * n;
         return timed(MST_PROF_DIAG, fl, st, [&] { return launch_block(false, b, st); });
     };
 
@@ -282,6 +292,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             DiagArgs d{};
             d.m = m; d.n = n; d.i0 = i0; d.bs = bs; d.q = q;
             d.U = U; d.ldu = ldu; d.lam = lam; d.B = B; d.ldb = ldb;
+            d.V = V; d.ldv = ldv;
             d.b32 = mixed ? W32 : nullptr; d.ldb32 = ldw;
             d.col_len = col_len;
             if (safe) {
@@ -290,7 +301,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             } else {
                 d.safe.omega_log2 = o.omega_log2;
             }
-            hipError_t e = timed(MST_PROF_DIAG, 4.0 * bs * bs * (double)n, s, [&] { return launch_diag(nb, false, d, s); });
+            hipError_t e = timed(MST_PROF_DIAG, (V ? 8.0 : 4.0) * bs * bs * (double)n, s, [&] { return launch_diag(nb, false, d, s); });
             if (e != hipSuccess) return e;
             if (q > qa) {
                 GemmArgs g{};
@@ -304,6 +315,10 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
                     g.A = U + (long)i0 * ldu + qa * nb; g.lda = ldu;
                     g.B = B + i0; g.ldb = ldb;
                     g.C = B + qa * nb; g.ldc = ldb;
+                    if (V) {
+                        g.op = GOP_GEN_SUB;
+                        g.A2 = V + (long)i0 * ldv + qa * nb; g.lda2 = ldv; g.glam = lam;
+                    }
                     e = timed(MST_PROF_GEMM_F64, gemm_flops(g), s, [&] { return launch_gemm_f64(g, s); });
                 } else {
                     g.A = U32 + (long)i0 * ldu32 + qa * nb; g.lda = ldu32;
@@ -405,7 +420,7 @@ mst_status check_mat(const void* p, int ld, int rows, int cols, int ppos, int ld
 // safe solve into an existing workspace scope
 mst_status safe_solve(int m, int n, const zd* U, long ldu, const zd* lam, zd* B, long ldb,
                       const int* col_len, double* scale, int* klog, const Opts& o, hipStream_t s,
-                      Workspace& ws) {
+                      Workspace& ws, const zd* V = nullptr, long ldv = 0) {
     const int nb = o.nb;
     const int nblk = (m + nb - 1) / nb;
     double *G, *cn_in, *above, *colmax, *above_sum, *delta;
@@ -423,7 +438,19 @@ mst_status safe_solve(int m, int n, const zd* U, long ldu, const zd* lam, zd* B,
     SafeState st{};
     st.G = G; st.kcur = kcur; st.kb = kb; st.cn_in = cn_in; st.above_sum = above_sum;
     st.delta = delta; st.omega_log2 = o.omega_log2;
-    HIPCHK(forward_loop(m, n, U, ldu, nullptr, 0, lam, B, ldb, nullptr, 0, o, &st, col_len, s));
+    if (V) {
+        // the same sums and zero-pivot replacement for V (pencil bound of Alg 9)
+        double *cn_v, *above_v, *colmax_v, *above_sum_v, *delta_v;
+        HIPCHK(ws_get(ws, (size_t)m, &cn_v));
+        HIPCHK(ws_get(ws, (size_t)m, &above_v));
+        HIPCHK(ws_get(ws, (size_t)m, &colmax_v));
+        HIPCHK(ws_get(ws, (size_t)nblk, &above_sum_v));
+        HIPCHK(ws_get(ws, (size_t)1, &delta_v));
+        HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_norms(m, V, ldv, nb, cn_v, above_v, colmax_v, above_sum_v, delta_v, s); }));
+        st.above_sum_v = above_sum_v;
+        st.delta_v = delta_v;
+    }
+    HIPCHK(forward_loop(m, n, U, ldu, nullptr, 0, lam, B, ldb, nullptr, 0, o, &st, col_len, s, V, ldv));
     HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_finalize(m, n, nb, B, ldb, col_len, kcur, kb, scale, klog, s); }));
     return MST_OK;
 }
@@ -596,6 +623,83 @@ mst_status mst_triang_eig(int m, const void* T, int ldt, void* Z, int ldz, void*
     HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_triang_setup(m, (const zd*)T, ldt, (zd*)Z, ldz, (zd*)eigvals, col_len, s); }));
     st = safe_solve(m, m, (const zd*)T, ldt, (const zd*)eigvals, (zd*)Z, ldz, col_len, scale, scale_log2,
                     o, s, ws);
+    if (st != MST_OK) return st;
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_triang_diag(m, (zd*)Z, ldz, scale, s); }));
+    return MST_OK;
+}
+
+mst_status mstrsm_gen(int m, int n, const void* U, int ldu, const void* V, int ldv, const void* shifts,
+                      void* B, int ldb, const mst_opts* opt, void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    if (n < 0) return bad(2);
+    mst_status st;
+    if ((st = check_mat(U, ldu, m, n > 0 ? m : 0, 3, 4)) != MST_OK) return st;
+    if ((st = check_mat(V, ldv, m, n > 0 ? m : 0, 5, 6)) != MST_OK) return st;
+    if (n > 0 && m > 0 && !shifts) return bad(7);
+    if ((st = check_mat(B, ldb, m, n, 8, 9)) != MST_OK) return st;
+    Opts o;
+    if ((st = read_opts(opt, o, 10)) != MST_OK) return st;
+    if (o.nb != 16 || o.precision != 0) return MST_EUNSUPPORTED;
+    if (m == 0 || n == 0) return MST_OK;
+    HIPCHK(forward_loop(m, n, (const zd*)U, ldu, nullptr, 0, (const zd*)shifts, (zd*)B, ldb, nullptr, 0, o,
+                        nullptr, nullptr, (hipStream_t)stream, (const zd*)V, ldv));
+    return MST_OK;
+}
+
+mst_status mstrsm_safe_gen(int m, int n, const void* U, int ldu, const void* V, int ldv,
+                           const void* shifts, void* B, int ldb, const int* col_len, double* scale,
+                           int* scale_log2, const mst_opts* opt, void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    if (n < 0) return bad(2);
+    mst_status st;
+    if ((st = check_mat(U, ldu, m, n > 0 ? m : 0, 3, 4)) != MST_OK) return st;
+    if ((st = check_mat(V, ldv, m, n > 0 ? m : 0, 5, 6)) != MST_OK) return st;
+    if (n > 0 && m > 0 && !shifts) return bad(7);
+    if ((st = check_mat(B, ldb, m, n, 8, 9)) != MST_OK) return st;
+    if (n > 0 && !scale) return bad(11);
+    Opts o;
+    if ((st = read_opts(opt, o, 13)) != MST_OK) return st;
+    if (o.nb != 16 || o.precision != 0) return MST_EUNSUPPORTED;
+    if (n == 0) return MST_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace ws(s);
+    if (m == 0) {
+        int* kcur;
+        int* kb;
+        HIPCHK(ws_get(ws, (size_t)n, &kcur));
+        HIPCHK(ws_get(ws, (size_t)n, &kb));
+        HIPCHK(launch_fill_int(n, 0, kcur, s));
+        HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_finalize(0, n, o.nb, (zd*)B, 1, nullptr, kcur, kb, scale, scale_log2, s); }));
+        return MST_OK;
+    }
+    return safe_solve(m, n, (const zd*)U, ldu, (const zd*)shifts, (zd*)B, ldb, col_len, scale,
+                      scale_log2, o, s, ws, (const zd*)V, ldv);
+}
+
+mst_status mst_gen_triang_eig(int m, const void* T, int ldt, const void* S, int lds, void* Z, int ldz,
+                              void* eigvals, int* scale_log2, const mst_opts* opt, void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    mst_status st;
+    if ((st = check_mat(T, ldt, m, m, 2, 3)) != MST_OK) return st;
+    if ((st = check_mat(S, lds, m, m, 4, 5)) != MST_OK) return st;
+    if ((st = check_mat(Z, ldz, m, m, 6, 7)) != MST_OK) return st;
+    if (m > 0 && !eigvals) return bad(8);
+    Opts o;
+    if ((st = read_opts(opt, o, 10)) != MST_OK) return st;
+    if (o.nb != 16 || o.precision != 0) return MST_EUNSUPPORTED;
+    if (m == 0) return MST_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace ws(s);
+    int* col_len;
+    double* scale;
+    HIPCHK(ws_get(ws, (size_t)m, &col_len));
+    HIPCHK(ws_get(ws, (size_t)m, &scale));
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_gen_triang_setup(m, (const zd*)T, ldt, (const zd*)S, lds, (zd*)Z, ldz, (zd*)eigvals, col_len, s); }));
+    st = safe_solve(m, m, (const zd*)T, ldt, (const zd*)eigvals, (zd*)Z, ldz, col_len, scale, scale_log2,
+                    o, s, ws, (const zd*)S, lds);
     if (st != MST_OK) return st;
     HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_triang_diag(m, (zd*)Z, ldz, scale, s); }));
     return MST_OK;

@@ -18,6 +18,10 @@ struct SafeState {
     const double* above_sum;  // nblk: sum over the block's columns of max cabs1 above the block
     const double* delta;      // 1: replacement for a zero pivot
     int omega_log2;
+    // pencil (U - lambda V): the same sums and replacement for V; the bound adds
+    // cabs1(lambda_j) * above_sum_v and the zero-pivot replacement is max(delta, delta_v)
+    const double* above_sum_v;
+    const double* delta_v;
 };
 
 // ---------------------------------------------------------------- diagonal blocks
@@ -27,9 +31,11 @@ struct SafeState {
 // safe != nullptr: Alg 4 phase 2 with Alg 5's column bound and decisions, block index q.
 // b32 != nullptr (mixed precision): the right-hand side is read from b32 (FP32),
 // solved in FP64, and written both to B (FP64) and back to b32 (rounded).
+// V != nullptr: the pencil U - lambda_j V (nb = 16, forward, FP64 only).
 struct DiagArgs {
     int m, n, i0, bs, q;
     const zd* U; long ldu;
+    const zd* V; long ldv;
     const zd* lam;
     zd* B; long ldb;
     zf* b32; long ldb32;
@@ -41,10 +47,12 @@ hipError_t launch_diag(int nb, bool adjoint, const DiagArgs& a, hipStream_t s);
 
 // Whole outer block [iS, iS+rows) (rows <= block_rows_max(), iS a multiple of nb,
 // first diagonal block index qa) for all n shifts: the diagonal blocks in
-// order and the substitution between them, in one launch.
+// order and the substitution between them, in one launch. V != nullptr: the
+// pencil U - lambda_j V (nb = 16, forward, FP64 only).
 struct BlockArgs {
     int m, n, nb, qa, iS, rows;
     const zd* U; long ldu;
+    const zd* V; long ldv;
     const zd* lam;
     zd* B; long ldb;
     zf* b32; long ldb32;
@@ -62,6 +70,7 @@ enum GemmOp : int {
     GOP_SUB = 0,      // C = 2^-dk_c * C - acc   (dk from the safe state, else 0)
     GOP_RESID = 1,    // C = B0 - acc + lam_c * Bop(row, c)   (A upper triangular, global indices)
     GOP_NEG_TRIU = 2, // C = -acc on and above the diagonal, 0 below
+    GOP_GEN_SUB = 3,  // C = 2^-dk_c * C - A B + lam_c * (A2 B)   (pencil substitution)
 };
 struct GemmArgs {
     int M, N, K;
@@ -79,6 +88,8 @@ struct GemmArgs {
     const int* col_len; int c_row0;
     // substitution (GOP_SUB, plain operands): 1 = LDS-staged kernel, 0 = barrier-free kernel
     int staged;
+    // GOP_GEN_SUB: second A operand (plain, same shape as A) and the shift of each column
+    const void* A2; long lda2; const zd* glam;
 };
 hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s);
 hipError_t launch_gemm_f32(const GemmArgs& g, hipStream_t s);
@@ -101,6 +112,8 @@ hipError_t launch_axpy_inplace(int rows, int cols, const zd* D, long ldd, zd* X,
                                hipStream_t s);
 hipError_t launch_triang_setup(int m, const zd* T, long ldt, zd* Z, long ldz, zd* eig,
                                int* col_len, hipStream_t s);
+hipError_t launch_gen_triang_setup(int m, const zd* T, long ldt, const zd* S, long lds, zd* Z, long ldz,
+                                   zd* eig, int* col_len, hipStream_t s);
 hipError_t launch_triang_diag(int m, zd* Z, long ldz, const double* scale, hipStream_t s);
 hipError_t launch_normalize_cols(int m, int n, zd* V, long ldv, hipStream_t s);
 hipError_t launch_lanczos_step(int m, int n, int it, int iters, const zd* V, long ldv,

@@ -190,6 +190,35 @@ __global__ __launch_bounds__(256) void k_triang_setup(int m, const zd* T, long l
     }
 }
 
+// GeneralizedTriangEig set-up (appendix, Alg 10): lambda_j = T(j,j) / S(j,j)
+// (scaled complex division: S(j,j) = 2^e d', T/S = 2^-e T conj(d') / |d'|^2);
+// Z(r, j) = -T(r, j) + lambda_j S(r, j) for r < j, zero elsewhere.
+__global__ __launch_bounds__(256) void k_gen_triang_setup(int m, const zd* T, long ldt, const zd* S,
+                                                          long lds, zd* Z, long ldz, zd* eig,
+                                                          int* col_len) {
+#pragma clang fp contract(off)
+    const int nrb = (m + 255) / 256;
+    const int j = blockIdx.x / nrb;
+    const int r = (blockIdx.x - j * nrb) * 256 + threadIdx.x;
+    if (r >= m) return;
+    const zd t = T[(long)j * ldt + j], d = S[(long)j * lds + j];
+    const double am = fmax(fabs(d.re), fabs(d.im));
+    const int e = (am > 0.0) ? ilogb(am) : 0;
+    const double sr = ldexp(d.re, -e), si = ldexp(d.im, -e);
+    const double den = sr * sr + si * si;
+    const zd lam{ldexp((t.re * sr + t.im * si) / den, -e), ldexp((t.im * sr - t.re * si) / den, -e)};
+    zd v{0.0, 0.0};
+    if (r < j) {
+        const zd tr = T[(long)j * ldt + r], sv = S[(long)j * lds + r];
+        v = zd{(lam.re * sv.re - lam.im * sv.im) - tr.re, (lam.re * sv.im + lam.im * sv.re) - tr.im};
+    }
+    Z[(long)j * ldz + r] = v;
+    if (r == j) {
+        eig[j] = lam;
+        col_len[j] = j;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_triang_diag(int m, zd* Z, long ldz, const double* scale) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j < m) Z[(long)j * ldz + j] = zd{scale[j], 0.0};
@@ -360,6 +389,13 @@ hipError_t launch_triang_setup(int m, const zd* T, long ldt, zd* Z, long ldz, zd
                                hipStream_t s) {
     const dim3 grid(((m + 255) / 256) * m);
     hipLaunchKernelGGL(k_triang_setup, grid, dim3(256), 0, s, m, T, ldt, Z, ldz, eig, col_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_triang_setup(int m, const zd* T, long ldt, const zd* S, long lds, zd* Z, long ldz,
+                                   zd* eig, int* col_len, hipStream_t s) {
+    const dim3 grid(((m + 255) / 256) * m);
+    hipLaunchKernelGGL(k_gen_triang_setup, grid, dim3(256), 0, s, m, T, ldt, S, lds, Z, ldz, eig, col_len);
     return hipGetLastError();
 }
 

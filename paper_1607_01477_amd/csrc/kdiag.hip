@@ -71,6 +71,20 @@ __device__ inline double quotient(double a, double b) {
     return a / b;
 }
 
+// Entry u - lambda v of the shifted pencil, every operation rounded on its own
+// (the xAXPY that forms U' in Alg 8 / Alg 9).
+__device__ inline zd pencil(zd u, zd v, zd l) {
+#pragma clang fp contract(off)
+    return zd{u.re - (l.re * v.re - l.im * v.im), u.im - (l.re * v.im + l.im * v.re)};
+}
+
+// Column-bound increment of Alg 9 for one shift: sum_k ||U(I0,k)||_inf +
+// |lambda| sum_k ||V(I0,k)||_inf, with |lambda| taken as cabs1.
+__device__ inline double pencil_asum(double au, double av, zd l) {
+#pragma clang fp contract(off)
+    return au + (fabs(l.re) + fabs(l.im)) * av;
+}
+
 // Value of lane i of each group of NB lanes, to every lane of that group.
 //   NB = 64: v_readlane into scalar registers (measured faster than a pair of
 //            readlanes plus a select for NB = 32, which uses ds_bpermute);
@@ -144,22 +158,33 @@ __device__ inline void stage_diag(zd* Us, zd* Ud, const zd* U, long ldu, int i0,
 // Per-wavefront solve of SPW interleaved shifts (per group of NB lanes) against
 // the staged block. b holds the right-hand side rows (lane r = row r) and
 // receives the solution; kblk the block's scale exponent (safe variant).
-template <int NB, int SPW, bool ADJ, bool SAFE>
+// GEN: the block of a pencil, U' = U - lambda V per shift (nb = 16, one shift
+// per lane group): pivots and coefficients are formed from both staged blocks.
+template <int NB, int SPW, bool ADJ, bool SAFE, bool GEN = false>
 struct BlockSolve {
+    static_assert(!GEN || (NB == 16 && SPW == 1 && !ADJ), "pencil blocks: nb 16, forward");
     double br[SPW], bi[SPW], pr[SPW], pi[SPW], cdl[SPW], Gs[SPW], Ms[SPW];
     int pe[SPW], kblk[SPW];
 
     // pivot d = U(r,r) - lambda (forward) or its conjugate (adjoint); exact
     // zeros replaced by delta in the safe variant
+    // (GEN: d = U(r,r) - lambda V(r,r), V's diagonal in Vd)
     __device__ __forceinline__ void pivots(const zd* Ud, int r, int bs, const zd (&lam)[SPW],
-                                           const bool (&jv)[SPW], double delta) {
+                                           const bool (&jv)[SPW], double delta,
+                                           const zd* Vd = nullptr) {
 #pragma unroll
         for (int s = 0; s < SPW; ++s) {
             double dr = 1.0, di = 0.0;
             if (r < bs && jv[s]) {
                 const zd u = Ud[r];
-                dr = u.re - lam[s].re;
-                di = ADJ ? (u.im + lam[s].im) : (u.im - lam[s].im);
+                if constexpr (GEN) {
+                    const zd d = pencil(u, Vd[r], lam[s]);
+                    dr = d.re;
+                    di = d.im;
+                } else {
+                    dr = u.re - lam[s].re;
+                    di = ADJ ? (u.im + lam[s].im) : (u.im - lam[s].im);
+                }
                 if (SAFE && dr == 0.0 && di == 0.0) dr = delta;
             }
             cdl[s] = cabs1(dr, di);
@@ -275,13 +300,20 @@ struct BlockSolve {
     }
 
     // The coefficients come from LDS ahead of the dependent chain of steps:
-    // all nb of them for nb = 16, one step ahead otherwise.
+    // all nb of them for nb = 16, one step ahead otherwise. GEN: coefficient
+    // U(r,i) - lambda V(r,i) from the two staged blocks (Vs, shift lg), and in
+    // the safe form the column norms of the shifted block (Alg 4 on U') are
+    // formed here per shift instead of taken from cn_l.
     __device__ __forceinline__ void run(const zd* Us, int bs, int r, int base, double cn_l, int w,
-                                        double omega) {
+                                        double omega, const zd* Vs = nullptr, zd lg = zd{0.0, 0.0}) {
+        auto coef = [&](int i) __attribute__((always_inline)) {
+            if constexpr (GEN) return pencil(Us[i * NB + r], Vs[i * NB + r], lg);
+            else return Us[i * NB + r];
+        };
         if constexpr (NB == 16 && !SAFE && SPW == 1) {
             zd uu[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) uu[i] = Us[i * NB + r];
+            for (int i = 0; i < 16; ++i) uu[i] = coef(i);
             // b' = b / d, u' = u / d (pr, pi: 1 / d of this lane's row)
             const double b_r = br[0], b_i = bi[0];
             br[0] = fma(b_r, pr[0], -b_i * pi[0]);
@@ -294,9 +326,20 @@ struct BlockSolve {
             }
             run16s<0>(uu);
         } else if constexpr (NB == 16) {
+            if constexpr (GEN && SAFE) {
+                // lane r: max cabs1 of column r of U' above the diagonal (the
+                // staged blocks are zero on and below it)
+                double cn = 0.0;
+#pragma unroll
+                for (int i = 0; i < 15; ++i) {
+                    const zd e = pencil(Us[r * NB + i], Vs[r * NB + i], lg);
+                    cn = fmax(cn, cabs1(e.re, e.im));
+                }
+                cn_l = cn;
+            }
             zd uu[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) uu[i] = Us[i * NB + r];
+            for (int i = 0; i < 16; ++i) uu[i] = coef(i);
             // keep the loads here: left alone the compiler sinks each into its
             // step's branch and every step then waits for LDS
 #pragma unroll
@@ -337,12 +380,16 @@ struct BlockSolve {
     }
 };
 
-template <int NB, int SPW, bool ADJ, bool SAFE, bool MIXED, bool VARLEN>
+template <int NB, int SPW, bool ADJ, bool SAFE, bool MIXED, bool VARLEN, bool GEN = false>
 __global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
+    static_assert(!GEN || (NB == 16 && !ADJ && !MIXED), "pencil: nb 16, forward, FP64");
     __shared__ zd Us[NB * NB];
     __shared__ zd Ud[NB];
+    __shared__ zd Vs[GEN ? NB * NB : 1];
+    __shared__ zd Vd[GEN ? NB : 1];
     const int bs = a.bs, i0 = a.i0;
     stage_diag<NB, ADJ>(Us, Ud, a.U, a.ldu, i0, bs);
+    if (GEN) stage_diag<NB, false>(Vs, Vd, a.V, a.ldv, i0, bs);
     __syncthreads();
 
     constexpr int G = 64 / NB;
@@ -353,10 +400,10 @@ __global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
 
     const int w = a.safe.omega_log2;
     const double omega = ldexp(1.0, w);
-    const double delta = SAFE ? *a.safe.delta : 0.0;
-    const double cn_l = (SAFE && r < bs) ? a.safe.cn_in[i0 + r] : 0.0;
+    const double delta = SAFE ? (GEN ? fmax(*a.safe.delta, *a.safe.delta_v) : *a.safe.delta) : 0.0;
+    const double cn_l = (SAFE && !GEN && r < bs) ? a.safe.cn_in[i0 + r] : 0.0;
 
-    BlockSolve<NB, SPW, ADJ, SAFE> S;
+    BlockSolve<NB, SPW, ADJ, SAFE, GEN> S;
     int jj[SPW], Lr[SPW];
     zd lam[SPW];
     bool jv[SPW];
@@ -397,16 +444,18 @@ __global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
             if (r == 0 && jv[s]) a.safe.kb[(long)a.q * a.n + jj[s]] = a.safe.kcur[jj[s]];
         return;
     }
-    S.pivots(Ud, r, bs, lam, jv, delta);
-    S.run(Us, bs, r, base, cn_l, w, omega);
+    S.pivots(Ud, r, bs, lam, jv, delta, Vd);
+    S.run(Us, bs, r, base, cn_l, w, omega, Vs, lam[0]);
 
     if (SAFE) {
-        const double asum = a.safe.above_sum[a.q];
+        const double asum0 = a.safe.above_sum[a.q];
+        const double asumv = GEN ? a.safe.above_sum_v[a.q] : 0.0;
 #pragma unroll
         for (int s = 0; s < SPW; ++s) {
             const int j = jj[s];
             const bool active = jv[s] && (i0 < Lr[s]);
             double Gj = jv[s] ? a.safe.G[j] : 0.0;
+            const double asum = GEN ? pencil_asum(asum0, asumv, lam[s]) : asum0;
             const int dk = S.column_bound(s, active, asum, &Gj, w, omega);
             if (r == 0 && jv[s]) {
                 const int kc = a.safe.kcur[j] + dk;
@@ -452,8 +501,8 @@ constexpr int kSP = kRowsMax + 1;      // padded LDS column stride (bank spread)
 // matrix cores); 4 plus 4 where the register use leaves room for two
 // wavefronts per SIMD only (nb = 32, safe). The adjoint variant at 768 threads
 // keeps four addresses of its final store loop in scratch (reloaded once).
-constexpr int block_threads(int nb, bool adj, bool safe) {
-    return (nb == 16 && !safe) ? 768 : 512;
+constexpr int block_threads(int nb, bool adj, bool safe, bool gen = false) {
+    return (nb == 16 && !safe && !gen) ? 768 : 512;
 }
 constexpr int kAW = 4;                 // wavefronts that solve diagonal blocks; the others update
 
@@ -469,22 +518,30 @@ constexpr int kAW = 4;                 // wavefronts that solve diagonal blocks;
 // latency-bound substitution instead of after it. Diagonal and coupling blocks
 // of the next pass are loaded during the current one (double-buffered LDS).
 // Per element the updates keep the order of the blocks.
-template <int NB, bool ADJ, bool SAFE, bool MIXED, bool VARLEN>
-__global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArgs a) {
+// GEN: the pencil U - lambda_j V (Alg 8 / Alg 9): the V blocks are staged
+// beside U's, the solving wavefronts form U - lambda V per shift, and the
+// matrix-core update adds V times lambda x to the subtraction of U x.
+template <int NB, bool ADJ, bool SAFE, bool MIXED, bool VARLEN, bool GEN = false>
+__global__ __launch_bounds__(block_threads(NB, ADJ, SAFE, GEN)) void k_block(BlockArgs a) {
     static_assert(NB == 16 || NB == 32, "fused outer block: nb 16 or 32");
+    static_assert(!GEN || (NB == 16 && !ADJ && !MIXED), "pencil: nb 16, forward, FP64");
     constexpr int G = 64 / NB;
-    constexpr int kWGB = block_threads(NB, ADJ, SAFE);
+    constexpr int kWGB = block_threads(NB, ADJ, SAFE, GEN);
     constexpr int NWAVE = kWGB / 64;
     constexpr int NUW = NWAVE - kAW;                     // updating wavefronts
     constexpr int SPW = kCols / (kAW * G);               // interleaved shifts per lane group
     constexpr int NBB = NB * NB;
-    constexpr int PERS = (2 * NBB + kWGB - 1) / kWGB;    // staged elements per thread
+    constexpr int NST = GEN ? 4 : 2;                     // staged blocks per pass
+    constexpr int PERS = (NST * NBB + kWGB - 1) / kWGB;  // staged elements per thread
     constexpr int KS = NB / 4;
     static_assert(SPW * G * kAW == kCols, "column split");
     __shared__ zd Bl[kCols * kSP];
     __shared__ zd Us[2][NBB];      // diagonal block, strict triangle (see stage_diag)
     __shared__ zd Uo[2][NBB];      // coupling block: Uo[k*NB + r] = coefficient of x_p(k) in row r of q
     __shared__ zd Ud[2][NB];
+    __shared__ zd Vs[GEN ? 2 : 1][GEN ? NBB : 1];   // the same three blocks of V (pencil)
+    __shared__ zd Vo[GEN ? 2 : 1][GEN ? NBB : 1];
+    __shared__ zd Vd[GEN ? 2 : 1][GEN ? NB : 1];
     __shared__ double Gl[kCols];
     __shared__ int kcl[kCols], dkl[2][kCols], Ll[kCols];
     __shared__ int tctr[2];        // next update tile to claim, per pass parity
@@ -494,7 +551,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
     const int iS = a.iS, rows = a.rows;
     const int w = a.safe.omega_log2;
     const double omega = ldexp(1.0, w);
-    const double delta = SAFE ? *a.safe.delta : 0.0;
+    const double delta = SAFE ? (GEN ? fmax(*a.safe.delta, *a.safe.delta_v) : *a.safe.delta) : 0.0;
 
     if (tid == 0) tctr[0] = NUW;
     if (tid < kCols) {
@@ -590,37 +647,59 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
         const int i0 = iS + g.lr0, p0 = iS + g.p0;
 #pragma unroll
         for (int e = 0; e < PERS; ++e) {
-            const int t = tid + e * kWGB;
-            long off = (long)i0 * a.ldu + i0;   // the block's first pivot: always valid
+            const int t0 = tid + e * kWGB;
+            // pencil: elements 2 NBB .. 4 NBB stage the same blocks of V
+            const bool fv = GEN && t0 >= 2 * NBB;
+            const int t = fv ? t0 - 2 * NBB : t0;
+            const long ld = fv ? a.ldv : a.ldu;
+            long off = (long)i0 * ld + i0;   // the block's first pivot: always valid
             bool v = false;
             if (t < NBB) {
                 const int c = t / NB, rr = t - c * NB;
                 v = rr <= c && c < g.bs;
-                off = v ? (long)(i0 + c) * a.ldu + i0 + rr : off;
+                off = v ? (long)(i0 + c) * ld + i0 + rr : off;
             } else if (t < 2 * NBB) {
                 const int t2 = t - NBB;
                 if (!ADJ) {
                     // coefficient of x_p(k) in row r: U(i0 + r, p0 + k)
                     const int k = t2 / NB, r = t2 - k * NB;
                     v = r < g.bs && k < g.bsp;
-                    off = v ? (long)(p0 + k) * a.ldu + i0 + r : off;
+                    off = v ? (long)(p0 + k) * ld + i0 + r : off;
                 } else {
                     // adjoint: conj(U(p0 + k, i0 + r)), conjugated at the store
                     const int r = t2 / NB, k = t2 - r * NB;
                     v = r < g.bs && k < g.bsp;
-                    off = v ? (long)(i0 + r) * a.ldu + p0 + k : off;
+                    off = v ? (long)(i0 + r) * ld + p0 + k : off;
                 }
             }
             usv[e] = v;
-            ust[e] = a.U[off];
+            ust[e] = (fv ? a.V : a.U)[off];
         }
     };
     auto stage_store = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
         for (int e = 0; e < PERS; ++e) {
-            const int t = tid + e * kWGB;
+            const int t0 = tid + e * kWGB;
             zd v = usv[e] ? ust[e] : zd{0.0, 0.0};
             if (ADJ) v.im = -v.im;
+            if (GEN && t0 >= 2 * NBB) {
+                const int t = t0 - 2 * NBB;
+                if (t < NBB) {
+                    const int c = t / NB, rr = t - c * NB;
+                    if (rr == c) {
+                        Vd[buf][rr] = v;
+                        Vs[buf][c * NB + rr] = zd{0.0, 0.0};
+                    } else {
+                        Vs[buf][c * NB + rr] = v;
+                    }
+                } else if (t < 2 * NBB) {
+                    const int t2 = t - NBB;
+                    const int k = t2 / NB, r = t2 - k * NB;
+                    Vo[buf][k * NB + r] = v;
+                }
+                continue;
+            }
+            const int t = t0;
             if (t < NBB) {
                 const int c = t / NB, rr = t - c * NB;
                 if (rr == c) {
@@ -666,6 +745,12 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
         // all of them (the next pass's staging loads included) in every pass
         asm volatile("" : "+v"(lam[s].re), "+v"(lam[s].im));
     }
+    // pencil: shift of this lane's column in the matrix-core tiles (column lane % 16)
+    zd lamt{0.0, 0.0};
+    if (GEN) {
+        if (col0 + lr < a.n) lamt = a.lam[col0 + lr];
+        asm volatile("" : "+v"(lamt.re), "+v"(lamt.im));
+    }
 
     // U fragments of the matrix-core update: A(row, k) for row = ubeg + tile*16 +
     // lane%16, k = 4 ks + lane/16 (forward: U(iS+row, iS+p0+k); adjoint:
@@ -673,16 +758,20 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
     // unconditional from clamped positions inside U's upper triangle (needs
     // uend > ubeg and bsp > 0); positions outside the tile are zeroed where
     // consumed.
-    auto aload = [&](zd (&dst)[KS], const Pass& g, int tile) __attribute__((always_inline)) {
+    // (pencil: the same positions of V into dstv)
+    auto aload = [&](zd (&dst)[KS], zd (&dstv)[GEN ? KS : 1], const Pass& g, int tile)
+        __attribute__((always_inline)) {
         const int arow = max(g.ubeg, min(g.ubeg + tile * 16 + lr, g.uend - 1));
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int k = min(ks * 4 + lq, g.bsp - 1);
             if (!ADJ) dst[ks] = a.U[(long)(iS + g.p0 + k) * a.ldu + iS + arow];
             else dst[ks] = a.U[(long)(iS + arow) * a.ldu + iS + g.p0 + k];
+            if constexpr (GEN) dstv[ks] = a.V[(long)(iS + g.p0 + k) * a.ldv + iS + arow];
         }
     };
     zd an[KS];   // first fragment of a pass, loaded at the end of the pass before
+    zd vn[GEN ? KS : 1];
     double xpr[SPW], xpi[SPW];   // solving wavefronts: solution of the block of the pass before
 #pragma unroll
     for (int s = 0; s < SPW; ++s) xpr[s] = xpi[s] = 0.0;
@@ -698,12 +787,16 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
         if (wave >= kAW) {
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) asm volatile("" : "+v"(an[ks].re), "+v"(an[ks].im));
+            if constexpr (GEN) {
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) asm volatile("" : "+v"(vn[ks].re), "+v"(vn[ks].im));
+            }
         }
         if (stp + 1 < nsub) stage_load(stp + 1);
 
         if (wave < kAW) {
             // ---- rows of block q: apply x of block p, then back substitution
-            BlockSolve<NB, SPW, ADJ, SAFE> S;
+            BlockSolve<NB, SPW, ADJ, SAFE, GEN> S;
             bool act[SPW];
 #pragma unroll
             for (int s = 0; s < SPW; ++s) {
@@ -729,7 +822,10 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
                     // x_p(k) is still in lane k of each group from the pass before
                     zd uo[16];
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) uo[k] = Uo[buf][k * NB + r];
+                    for (int k = 0; k < 16; ++k) {
+                        if constexpr (GEN) uo[k] = pencil(Uo[buf][k * NB + r], Vo[buf][k * NB + r], lam[0]);
+                        else uo[k] = Uo[buf][k * NB + r];
+                    }
                     couple16<SPW, 0>(uo, xpr, xpi, ar, ai);
                 } else {
                     // x_p(k) from LDS: one address per lane group (a broadcast read)
@@ -750,14 +846,16 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
                     S.bi[s] -= ai[s][0] + ai[s][1];
                 }
             }
-            const double cn_l = (SAFE && r < g.bs) ? a.safe.cn_in[i0 + r] : 0.0;
-            S.pivots(Ud[buf], r, g.bs, lam, jv, delta);
-            S.run(Us[buf], g.bs, r, base, cn_l, w, omega);
+            const double cn_l = (SAFE && !GEN && r < g.bs) ? a.safe.cn_in[i0 + r] : 0.0;
+            S.pivots(Ud[buf], r, g.bs, lam, jv, delta, Vd[buf]);
+            S.run(Us[buf], g.bs, r, base, cn_l, w, omega, Vs[buf], lam[0]);
             if (SAFE) {
-                const double asum = a.safe.above_sum[q];
+                const double asum0 = a.safe.above_sum[q];
+                const double asumv = GEN ? a.safe.above_sum_v[q] : 0.0;
 #pragma unroll
                 for (int s = 0; s < SPW; ++s) {
                     const int c = cc[s];
+                    const double asum = GEN ? pencil_asum(asum0, asumv, lam[s]) : asum0;
                     double Gj = Gl[c];
                     const int dk = S.column_bound(s, act[s], asum, &Gj, w, omega);
                     if (r == 0 && jv[s]) {
@@ -790,7 +888,8 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
                 if (lane == 0) t = atomicAdd(&tctr[buf], 1);
                 return __builtin_amdgcn_readfirstlane(t);
             };
-            auto do_tile = [&](int tile, const zd (&af)[KS]) __attribute__((always_inline)) {
+            auto do_tile = [&](int tile, const zd (&af)[KS], const zd (&vf)[GEN ? KS : 1])
+                __attribute__((always_inline)) {
                 const int rb = g.ubeg + tile * 16;
                 const bool rowok = rb + lr < g.uend;   // this lane's A row inside the tile
                 // Every LDS read below is in bounds (rows < 256) and needs no
@@ -826,6 +925,17 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
                     accI = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb.im, accI, 0, 0, 0);
                     accR2 = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, xb.im, accR2, 0, 0, 0);
                     accI2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xb.re, accI2, 0, 0, 0);
+                    if constexpr (GEN) {
+                        // + V(row, k) * (lambda_col x(k, col))
+                        const double wr = lamt.re * xb.re - lamt.im * xb.im;
+                        const double wi = lamt.re * xb.im + lamt.im * xb.re;
+                        const double vr = ok ? vf[ks].re : 0.0;
+                        const double vi = ok ? vf[ks].im : 0.0;
+                        accR = __builtin_amdgcn_mfma_f64_16x16x4f64(vr, wr, accR, 0, 0, 0);
+                        accI = __builtin_amdgcn_mfma_f64_16x16x4f64(vr, wi, accI, 0, 0, 0);
+                        accR2 = __builtin_amdgcn_mfma_f64_16x16x4f64(-vi, wi, accR2, 0, 0, 0);
+                        accI2 = __builtin_amdgcn_mfma_f64_16x16x4f64(vi, wr, accI2, 0, 0, 0);
+                    }
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -834,14 +944,19 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
                 }
             };
             int cur = (wave >= kAW) ? wave - kAW : claim();
-            if (wave < kAW && cur < ntile) aload(an, g, cur);
+            if (wave < kAW && cur < ntile) aload(an, vn, g, cur);
             zd af[KS];
+            zd vf[GEN ? KS : 1];
             while (cur < ntile) {
                 const int nxt = claim();
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) af[ks] = an[ks];
-                if (nxt < ntile) aload(an, g, nxt);
-                do_tile(cur, af);
+                if constexpr (GEN) {
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) vf[ks] = vn[ks];
+                }
+                if (nxt < ntile) aload(an, vn, g, nxt);
+                do_tile(cur, af, vf);
                 cur = nxt;
             }
             // counter of the next pass (its last use was before the barrier behind us)
@@ -852,7 +967,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE)) void k_block(BlockArg
         // after the staging stores so that their wait does not cover it
         if (wave >= kAW && stp + 1 < nsub) {
             const Pass gn = pass_of(stp + 1);
-            if (gn.uend > gn.ubeg) aload(an, gn, wave - kAW);
+            if (gn.uend > gn.ubeg) aload(an, vn, gn, wave - kAW);
         }
         __syncthreads();
     }
@@ -885,6 +1000,20 @@ hipError_t launch_nb(const DiagArgs& a, hipStream_t s) {
     const bool safe = a.use_safe != 0;
     const bool mixed = a.b32 != nullptr;
     const bool varlen = a.col_len != nullptr;
+    if (a.V != nullptr) {
+        if constexpr (NB == 16 && !ADJ) {
+            if (mixed || (varlen && !safe)) return hipErrorInvalidValue;
+            if (safe && varlen)
+                hipLaunchKernelGGL((k_diag<16, SPW, false, true, false, true, true>), grid, dim3(kWG), 0, s, a);
+            else if (safe)
+                hipLaunchKernelGGL((k_diag<16, SPW, false, true, false, false, true>), grid, dim3(kWG), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_diag<16, SPW, false, false, false, false, true>), grid, dim3(kWG), 0, s, a);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (ADJ) {
         if (safe || mixed || varlen) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_diag<NB, SPW, true, false, false, false>), grid, dim3(kWG), 0, s, a);
@@ -910,6 +1039,21 @@ hipError_t launch_blk(const BlockArgs& a, hipStream_t s) {
     const bool safe = a.use_safe != 0;
     const bool mixed = a.b32 != nullptr;
     const bool varlen = a.col_len != nullptr;
+    if (a.V != nullptr) {
+        if constexpr (NB == 16 && !ADJ) {
+            if (mixed || (varlen && !safe)) return hipErrorInvalidValue;
+            const dim3 blk(block_threads(16, false, safe, true));
+            if (safe && varlen)
+                hipLaunchKernelGGL((k_block<16, false, true, false, true, true>), grid, blk, 0, s, a);
+            else if (safe)
+                hipLaunchKernelGGL((k_block<16, false, true, false, false, true>), grid, blk, 0, s, a);
+            else
+                hipLaunchKernelGGL((k_block<16, false, false, false, false, true>), grid, blk, 0, s, a);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (ADJ) {
         if (safe || mixed || varlen) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_block<NB, true, false, false, false>), grid, dim3(block_threads(NB, true, false)), 0, s, a);

@@ -346,12 +346,16 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(GemmArgs g) {
 // share A rows / B columns through L1.
 template <typename T, int DEPTH, int OP, bool A_CT, bool SAFE, bool VARLEN>
 __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
-    static_assert(OP == GOP_SUB || OP == GOP_NEG_TRIU || OP == GOP_RESID, "direct GEMM op");
-    static_assert(OP == GOP_SUB || (!A_CT && !SAFE && !VARLEN), "triangular products: plain A only");
+    static_assert(OP == GOP_SUB || OP == GOP_NEG_TRIU || OP == GOP_RESID || OP == GOP_GEN_SUB,
+                  "direct GEMM op");
+    static_assert(OP == GOP_SUB || OP == GOP_GEN_SUB || (!A_CT && !SAFE && !VARLEN),
+                  "triangular products: plain A only");
+    static_assert(OP != GOP_GEN_SUB || (sizeof(T) == 8 && !A_CT), "pencil substitution: FP64, plain A");
     static_assert(sizeof(T) == 8 || (OP == GOP_SUB && !A_CT && !SAFE && !VARLEN),
                   "FP32: plain substitution only");
     constexpr bool TRI = OP == GOP_NEG_TRIU;
     constexpr bool RES = OP == GOP_RESID;
+    constexpr bool GEN = OP == GOP_GEN_SUB;
     using Tr = Traits<T>;
     using CT = typename Tr::C;
     using V = typename Tr::V;
@@ -400,9 +404,12 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
     }
     const bool full = (rw + 32 <= g.M) && (cw + 32 <= g.N);
 
-    // ---- accumulators start from C (SUB), from B0 + lam B (RESID), from zero (TRI)
+    // ---- accumulators start from C (SUB), from B0 + lam B (RESID), from zero
+    // (TRI; GEN, whose C is added at the end)
     V accR[2][2], accI[2][2];
     int clim0 = g.M, clim1 = g.M, blim0 = g.K, blim1 = g.K;
+    int cshv[2] = {0, 0};
+    zd lamv[2] = {{0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int col = cw + j * 16 + lr;
@@ -419,6 +426,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 csh = kc - kq;
             }
             if (RES) lamc = g.lam[col];
+            if (GEN) lamv[j] = g.glam[col];
         } else {
             bl = 0;
         }
@@ -429,13 +437,14 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             clim1 = cl;
             blim1 = bl;
         }
+        cshv[j] = csh;
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = rw + i * 16 + Tr::out_row(lq, v);
                 CT c{0, 0};
-                if (!TRI && col < g.N && row < cl) {
+                if (!TRI && !GEN && col < g.N && row < cl) {
                     if (RES) {
                         const zd b0 = g.B0[(long)col * g.ldb0 + row];
                         const CT x = B[(long)col * g.ldb + row];
@@ -474,7 +483,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
         kq1 = g.kb[(long)g.q_cur * g.n_kb + cb1];
     }
 
-    auto kloop = [&](auto mask_tag) __attribute__((always_inline)) {
+    auto kloop = [&](auto mask_tag, const CT* __restrict__ A, long lda) __attribute__((always_inline)) {
         constexpr bool MASK = decltype(mask_tag)::value;
         CT pa0[DEPTH], pa1[DEPTH], pb0[DEPTH], pb1[DEPTH];
         int qe0[DEPTH] = {}, qe1[DEPTH] = {};
@@ -483,16 +492,16 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             const int k = MASK ? min(ks * 4 + lq, g.K - 1) : ks * 4 + lq;
             if (RES) {
                 // stay inside U's upper triangle: below it the element is never used
-                a0 = A[(long)max(k, ra0) * g.lda + ra0];
-                a1 = A[(long)max(k, ra1) * g.lda + ra1];
+                a0 = A[(long)max(k, ra0) * lda + ra0];
+                a1 = A[(long)max(k, ra1) * lda + ra1];
             } else if (!A_CT) {
-                const CT* ap = A + (long)k * g.lda;
+                const CT* ap = A + (long)k * lda;
                 a0 = ap[ra0];
                 a1 = ap[ra1];
             } else {
                 // A(r, k) = conj(a[r * lda + k]); conjugated where consumed
-                a0 = A[(long)ra0 * g.lda + k];
-                a1 = A[(long)ra1 * g.lda + k];
+                a0 = A[(long)ra0 * lda + k];
+                a1 = A[(long)ra1 * lda + k];
             }
             if (!TRI) {
                 b0 = B[(long)cb0 * g.ldb + k];
@@ -581,9 +590,9 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             // per refill, so the loop spends one address add per operand
             // instead of recomputing products; the main loop runs while every
             // refill lies inside K, a short guarded tail drains the ring.
-            const long sA = A_CT ? 4 : 4L * g.lda, sB = TRI ? 4L * g.ldb : 4;
-            const CT* qa0 = A_CT ? A + (long)ra0 * g.lda + lq : A + (long)lq * g.lda + ra0;
-            const CT* qa1 = A_CT ? A + (long)ra1 * g.lda + lq : qa0 + 16;
+            const long sA = A_CT ? 4 : 4L * lda, sB = TRI ? 4L * g.ldb : 4;
+            const CT* qa0 = A_CT ? A + (long)ra0 * lda + lq : A + (long)lq * lda + ra0;
+            const CT* qa1 = A_CT ? A + (long)ra1 * lda + lq : qa0 + 16;
             const CT* qb0 = TRI ? B + (long)lq * g.ldb + cb0 : B + (long)cb0 * g.ldb + lq;
             const CT* qb1 = TRI ? qb0 + 16 : B + (long)cb1 * g.ldb + lq;
             auto next = [&](CT& a0, CT& a1, CT& b0, CT& b1) __attribute__((always_inline)) {
@@ -638,10 +647,29 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             if (l0 + d < nloc) mma(kfirst + l0 + d, pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
     };
     // interior tiles of the plain forms need no masking at all
-    if (full && (g.K & 3) == 0 && nloc >= DEPTH && !VARLEN && !SAFE && !RES)
-        kloop(std::false_type{});
+    const bool unmasked = full && (g.K & 3) == 0 && nloc >= DEPTH && !VARLEN && !SAFE && !RES;
+    if (GEN) {
+        // pencil: acc = -A2 B, then acc = lam_c * (A2 B) per column (once per
+        // tile, not per k-step), then acc -= A B; C is added in the epilogue
+        if (unmasked)
+            kloop(std::false_type{}, (const CT*)g.A2, g.lda2);
+        else
+            kloop(std::true_type{}, (const CT*)g.A2, g.lda2);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double r = accR[i][j][v], im = accI[i][j][v];
+                    accR[i][j][v] = lamv[j].im * im - lamv[j].re * r;
+                    accI[i][j][v] = -(lamv[j].re * im + lamv[j].im * r);
+                }
+    }
+    if (unmasked)
+        kloop(std::false_type{}, A, g.lda);
     else
-        kloop(std::true_type{});
+        kloop(std::true_type{}, A, g.lda);
 
     // ---- epilogue
 #pragma unroll
@@ -657,6 +685,15 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 if (VARLEN && row >= (j == 0 ? clim0 : clim1)) continue;
                 if (TRI && row > col) {
                     C[(long)col * g.ldc + row] = CT{0, 0};
+                    continue;
+                }
+                if (GEN) {
+                    CT c = C[(long)col * g.ldc + row];
+                    if (SAFE) {
+                        c.re = ldexp(c.re, -cshv[j]);
+                        c.im = ldexp(c.im, -cshv[j]);
+                    }
+                    C[(long)col * g.ldc + row] = CT{c.re + accR[i][j][v], c.im + accI[i][j][v]};
                     continue;
                 }
                 C[(long)col * g.ldc + row] = CT{accR[i][j][v], accI[i][j][v]};
@@ -707,6 +744,12 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
             if (g.a_ct || g.b_ct || safe || varlen) return hipErrorInvalidValue;
             if (g.staged) return go<double, false, false, GOP_RESID, false, false>(g, s);
             return go_direct<double, GOP_RESID, false, false, false>(g, s);
+        case GOP_GEN_SUB:
+            if (g.a_ct || g.b_ct || !g.A2 || !g.glam || g.staged) return hipErrorInvalidValue;
+            if (safe && varlen) return go_direct<double, GOP_GEN_SUB, false, true, true>(g, s);
+            if (safe) return go_direct<double, GOP_GEN_SUB, false, true, false>(g, s);
+            if (varlen) return hipErrorInvalidValue;
+            return go_direct<double, GOP_GEN_SUB, false, false, false>(g, s);
         case GOP_NEG_TRIU:
             if (g.a_ct || !g.b_ct || safe || varlen) return hipErrorInvalidValue;
             if (g.staged) return go<double, false, true, GOP_NEG_TRIU, false, false>(g, s);

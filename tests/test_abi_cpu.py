@@ -46,3 +46,25 @@ def test_argument_errors_without_gpu():
     assert lib.mst_last_bad_arg() == 4
     assert lib.mstrsm(0, 7, None, 1, None, None, 1, None, None) == _lib.MST_OK
     assert lib.mst_status_string(_lib.MST_EARG).decode().startswith("MST_EARG")
+
+
+def test_generalized_argument_errors_without_gpu():
+    from paper_1607_01477_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(4096)   # never dereferenced: the calls return before any HIP call
+    # V missing / its leading dimension too small
+    assert lib.mstrsm_gen(3, 2, fake, 3, None, 3, fake, fake, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 5
+    assert lib.mstrsm_gen(3, 2, fake, 3, fake, 2, fake, fake, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 6
+    assert lib.mstrsm_safe_gen(3, 2, fake, 3, fake, 3, fake, fake, 3, None, None, None, None,
+                               None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 11
+    assert lib.mst_gen_triang_eig(3, fake, 3, None, 3, fake, 3, fake, None, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 4
+    # only nb = 16 is supported for the pencil
+    o = _lib.MstOpts()
+    o.nb = 32
+    assert lib.mstrsm_gen(3, 2, fake, 3, fake, 3, fake, fake, 3, ctypes.byref(o), None) == \
+        _lib.MST_EUNSUPPORTED
+    assert lib.mstrsm_gen(0, 5, None, 1, None, 1, None, None, 1, None, None) == _lib.MST_OK

@@ -205,11 +205,13 @@ def _exact_solve(A, b):
     return x
 
 
-@pytest.mark.parametrize("nb", [0, 1, 3, 4])
+@pytest.mark.parametrize("nb", [0, 1, 3, 4, 16])
 @pytest.mark.parametrize("omega_log2", [8, 14, 960])
-def test_safe_gen_dyadic_exact(oracle_mod, nb, omega_log2):
-    m, n = 10, 4
-    U, V, lam, B = _dyadic_pencil(40 + omega_log2 + nb, m, n)
+@pytest.mark.parametrize("m", [10, 20])
+def test_safe_gen_dyadic_exact(oracle_mod, nb, omega_log2, m):
+    # (for larger m the exact solutions need more than 53 significant bits)
+    n = 4
+    U, V, lam, B = _dyadic_pencil(40 + omega_log2 + nb + m, m, n)
     X, s, k = oracle_mod.solve_safe_gen(U, V, lam, B, nb=nb, omega_log2=omega_log2)
     events = 0
     for j in range(n):
