@@ -66,6 +66,12 @@ __device__ inline int bound_add(double g, double a, double b, int w, double omeg
     return k;
 }
 
+// g + a*b without contraction (the growth bound when it stays below Omega)
+__device__ inline double bound_sum(double g, double a, double b) {
+#pragma clang fp contract(off)
+    return g + a * b;
+}
+
 __device__ inline double quotient(double a, double b) {
 #pragma clang fp contract(off)
     return a / b;
@@ -271,6 +277,45 @@ struct BlockSolve {
         }
     }
 
+    // Safe step without its rescaling branches: the quotient M = |b_i|/|d_i|
+    // and the bound G + M c_i of Alg 4 are evaluated beside the substitution
+    // chain instead of gating it, and a step that would rescale (or meet a
+    // non-finite value) raises flag. Where nothing rescales, every value equals
+    // the checked step's; the caller redoes the block with the checked steps
+    // when any flag is up.
+    template <typename BC>
+    __device__ __forceinline__ void step_spec(const zd u, int i, int r, double cn_l, double omega,
+                                              BC bc, bool& flag) {
+        const double cni = bc(cn_l);
+#pragma unroll
+        for (int s = 0; s < SPW; ++s) {
+            const double cb = bc(cabs1(br[s], bi[s]));
+            const double cd = bc(cdl[s]);
+            double xl_r = fma(br[s], pr[s], -bi[s] * pi[s]);
+            double xl_i = fma(br[s], pi[s], bi[s] * pr[s]);
+            xl_r = ldexp(xl_r, -pe[s]);
+            xl_i = ldexp(xl_i, -pe[s]);
+            const double xr = bc(xl_r), xi = bc(xl_i);
+            const double M = quotient(cb, cd);
+            const double Gn = bound_sum(Gs[s], M, cni);
+            flag = flag || !(M < omega) || !(Gn < omega);
+            Gs[s] = Gn;
+            const double nr = fma(-u.re, xr, fma(u.im, xi, br[s]));
+            const double ni = fma(-u.re, xi, fma(-u.im, xr, bi[s]));
+            br[s] = (r == i) ? xl_r : nr;
+            bi[s] = (r == i) ? xl_i : ni;
+        }
+    }
+
+    template <int I>
+    __device__ __forceinline__ void run16spec(const zd (&uu)[16], int bs, int r, double cn_l,
+                                              double omega, bool& flag) {
+        constexpr int STEP = ADJ ? I : 15 - I;
+        if (STEP < bs)
+            step_spec(uu[STEP], STEP, r, cn_l, omega, [](double v) { return bcast16<STEP>(v); }, flag);
+        if constexpr (I < 15) run16spec<I + 1>(uu, bs, r, cn_l, omega, flag);
+    }
+
     template <int I>
     __device__ __forceinline__ void run16(const zd (&uu)[16], int bs, int r, double cn_l, int w,
                                           double omega) {
@@ -344,13 +389,65 @@ struct BlockSolve {
             // step's branch and every step then waits for LDS
 #pragma unroll
             for (int i = 0; i < 16; ++i) asm volatile("" : "+v"(uu[i].re), "+v"(uu[i].im));
-            run16<0>(uu, bs, r, cn_l, w, omega);
+            if constexpr (SAFE) {
+                // speculative pass first; the checked steps only when some
+                // step of some shift in the wavefront would rescale
+                double b0r[SPW], b0i[SPW], G0[SPW];
+#pragma unroll
+                for (int s = 0; s < SPW; ++s) {
+                    b0r[s] = br[s];
+                    b0i[s] = bi[s];
+                    G0[s] = Gs[s];
+                }
+                bool flag = false;
+                run16spec<0>(uu, bs, r, cn_l, omega, flag);
+                if (__any(flag)) {
+#pragma unroll
+                    for (int s = 0; s < SPW; ++s) {
+                        br[s] = b0r[s];
+                        bi[s] = b0i[s];
+                        Gs[s] = G0[s];
+                    }
+                    run16<0>(uu, bs, r, cn_l, w, omega);
+                }
+            } else {
+                run16<0>(uu, bs, r, cn_l, w, omega);
+            }
         } else if (!ADJ) {
-            zd un = Us[(bs - 1) * NB + r];
-            for (int i = bs - 1; i >= 0; --i) {
-                const zd u = un;
-                un = Us[(i > 0 ? i - 1 : 0) * NB + r];
-                step(u, i, r, cn_l, w, omega, [&](double v) { return bcast<NB>(v, i, base); });
+            bool redo = true;
+            double b0r[SPW], b0i[SPW], G0[SPW];
+            if constexpr (SAFE) {
+                // speculative pass, as for nb = 16
+#pragma unroll
+                for (int s = 0; s < SPW; ++s) {
+                    b0r[s] = br[s];
+                    b0i[s] = bi[s];
+                    G0[s] = Gs[s];
+                }
+                bool flag = false;
+                zd un = Us[(bs - 1) * NB + r];
+                for (int i = bs - 1; i >= 0; --i) {
+                    const zd u = un;
+                    un = Us[(i > 0 ? i - 1 : 0) * NB + r];
+                    step_spec(u, i, r, cn_l, omega, [&](double v) { return bcast<NB>(v, i, base); }, flag);
+                }
+                redo = __any(flag);
+                if (redo) {
+#pragma unroll
+                    for (int s = 0; s < SPW; ++s) {
+                        br[s] = b0r[s];
+                        bi[s] = b0i[s];
+                        Gs[s] = G0[s];
+                    }
+                }
+            }
+            if (redo) {
+                zd un = Us[(bs - 1) * NB + r];
+                for (int i = bs - 1; i >= 0; --i) {
+                    const zd u = un;
+                    un = Us[(i > 0 ? i - 1 : 0) * NB + r];
+                    step(u, i, r, cn_l, w, omega, [&](double v) { return bcast<NB>(v, i, base); });
+                }
             }
         } else {
             zd un = Us[r];

@@ -478,9 +478,23 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
     // safe form: exponent of the current outer block per column; the B rows of
     // diagonal block q carry exponent kb[q] and are brought to it exactly
     int kq0 = 0, kq1 = 0;
+    // The plain loop also serves the safe and variable-length forms of a
+    // wavefront whose columns all cover the B rows (col_len >= b_row0 + K, so
+    // no element is masked) and for which every diagonal block under the K
+    // range kept the current exponent (rescaling is rare): then the masks and
+    // the operand scaling are identities.
+    bool plain_ok = true;
+    if (VARLEN) plain_ok = __all(g.col_len[cb0] >= g.b_row0 + g.K && g.col_len[cb1] >= g.b_row0 + g.K);
     if (SAFE) {
         kq0 = g.kb[(long)g.q_cur * g.n_kb + cb0];
         kq1 = g.kb[(long)g.q_cur * g.n_kb + cb1];
+        if (plain_ok) {
+            // exponents only grow as blocks are solved (bottom to top), so the
+            // block solved first under the K range (the lowest) carries the
+            // smallest: equal to the current one means all are equal
+            const int qhi = (g.b_row0 + g.K - 1) / g.nb;
+            plain_ok = __all(g.kb[(long)qhi * g.n_kb + cb0] == kq0 && g.kb[(long)qhi * g.n_kb + cb1] == kq1);
+        }
     }
 
     auto kloop = [&](auto mask_tag, const CT* __restrict__ A, long lda) __attribute__((always_inline)) {
@@ -533,7 +547,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 b0.re = v0 ? b0.re : T(0); b0.im = v0 ? b0.im : T(0);
                 b1.re = v1 ? b1.re : T(0); b1.im = v1 ? b1.im : T(0);
             }
-            if (SAFE) {
+            if (SAFE && MASK) {
                 b0.re = ldexp(b0.re, e0 - kq0); b0.im = ldexp(b0.im, e0 - kq0);
                 b1.re = ldexp(b1.re, e1 - kq1); b1.im = ldexp(b1.im, e1 - kq1);
             }
@@ -647,7 +661,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             if (l0 + d < nloc) mma(kfirst + l0 + d, pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
     };
     // interior tiles of the plain forms need no masking at all
-    const bool unmasked = full && (g.K & 3) == 0 && nloc >= DEPTH && !VARLEN && !SAFE && !RES;
+    const bool unmasked = full && (g.K & 3) == 0 && nloc >= DEPTH && !RES && plain_ok;
     if (GEN) {
         // pencil: acc = -A2 B, then acc = lam_c * (A2 B) per column (once per
         // tile, not per k-step), then acc -= A B; C is added in the epilogue
