@@ -16,7 +16,11 @@ Also reported on the same line:
   secondary     the FP32-GEMM + FP64-refinement form of the same solve, its
                 time to FP64 accuracy and its error against the FP64 result.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload solve|pencil]
+
+--workload pencil times the generalized solve (U - l_j V) X = B (appendix,
+Alg 8) at the same size instead (8 m^2 n flops per solve), with its own
+roofline and CPU-oracle lines and no secondary measurements.
 """
 from __future__ import annotations
 
@@ -33,10 +37,13 @@ PEAK_FP64_MFMA_TF = 78.6
 # HBM bytes per launch of the substitution GEMM at this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs scaled by a 512 MiB copy (profiles/k_gemm_direct_solve_m4096_n4096.md).
 # Valid only for the GEMM source it was measured on (sha1 prefix of csrc/kgemm.hip).
-GEMM_TRAFFIC = {"kgemm_sha1": "2140b2487aa40a20", "bytes_per_launch": 291.7e6, "m": 4096, "n": 4096,
-                "nb": 16, "outer_nb": 256}
+GEMM_TRAFFIC = {"kgemm_sha1": "1b3e4341a23b55e1", "bytes_per_launch": 295.0e6, "m": 4096, "n": 4096,
+                "nb": 16, "outer_nb": 256,
+                # the pencil substitution (profiles/k_gemm_direct_pencil_m4096_n4096.md)
+                "pencil_bytes_per_launch": 476.9e6}
 PEAK_FP32_MFMA_TF = 157.3
 METRIC = "complex128 multi-shift solve GFLOP/s at m=n=4096 and % of MFMA peak vs plain FP64"
+METRIC_PENCIL = "complex128 generalized multi-shift solve GFLOP/s (8 m^2 n) at m=n=4096"
 
 
 def log(*a):
@@ -51,7 +58,7 @@ def dev(a, torch):
     return out
 
 
-def gemm_traffic(m, n, nb, outer_nb):
+def gemm_traffic(m, n, nb, outer_nb, pencil=False):
     import hashlib
     src = os.path.join(ROOT, "paper_1607_01477_amd", "csrc", "kgemm.hip")
     try:
@@ -61,7 +68,7 @@ def gemm_traffic(m, n, nb, outer_nb):
     t = GEMM_TRAFFIC
     if h != t["kgemm_sha1"] or (m, n, nb, outer_nb) != (t["m"], t["n"], t["nb"], t["outer_nb"]):
         return None
-    return t["bytes_per_launch"]
+    return t["pencil_bytes_per_launch"] if pencil else t["bytes_per_launch"]
 
 
 def _time(fn, torch, reps):
@@ -161,6 +168,10 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", choices=["solve", "pencil"], default="solve",
+                    help="solve: (U - l_j I) X = B, the headline; pencil: the generalized "
+                         "solve (U - l_j V) X = B at the same size (8 m^2 n flops), without "
+                         "the secondary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 4 device copies of 512 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -185,22 +196,34 @@ def main() -> int:
     import workloads as W
 
     m, n = args.m, args.n
+    pencil = args.workload == "pencil"
+    if pencil:
+        args.no_secondary = True
+        args.nb = 16
     t_gen = time.perf_counter()
-    w = W.c3_mixed(m=m, n=n)
+    w = W.c6_generalized(m=m, n=n) if pencil else W.c3_mixed(m=m, n=n)
     log("inputs generated in %.1fs" % (time.perf_counter() - t_gen))
     torch.cuda.set_device(0)
     U = dev(w.U, torch)
     lam = torch.from_numpy(w.shifts).cuda()
     B0 = dev(w.B, torch)
-    flops = 4.0 * m * m * n
+    flops = (8.0 if pencil else 4.0) * m * m * n
     opts = dict(nb=args.nb, outer_nb=args.outer_nb)
+    if pencil:
+        Vd = dev(w.extra["V"], torch)
+
+        def solve(X):
+            return P.mstrsm_gen(U, Vd, lam, X, outer_nb=args.outer_nb)
+    else:
+        def solve(X):
+            return P.mstrsm(U, lam, X, **opts)
 
     def fresh(k):
         return [B0.clone() for _ in range(k)]
 
     # ---- warmup
     for X in fresh(args.warmup):
-        P.mstrsm(U, lam, X, **opts)
+        solve(X)
     torch.cuda.synchronize()
     log("warmup done")
 
@@ -209,20 +232,25 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for X in Xs:
-        P.mstrsm(U, lam, X, **opts)
+        solve(X)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     gflops = flops / (ms_per_step * 1e-3) / 1e9
-    log("plain FP64: %.3f ms/solve, %.1f GFLOP/s" % (ms_per_step, gflops))
+    log("%s FP64: %.3f ms/solve, %.1f GFLOP/s" % (args.workload, ms_per_step, gflops))
 
     # accuracy of the timed result on sampled columns (true-modulus backward error)
     Xh = Xs[-1].cpu().numpy()
     cols = np.arange(0, n, max(1, n // 16))
     Ut = np.triu(w.U)
-    R = Ut @ Xh[:, cols] - Xh[:, cols] * w.shifts[cols][None, :] - w.B[:, cols]
-    offrow = np.abs(np.triu(w.U, 1)).sum(1)
-    nrm = np.max(offrow[:, None] + np.abs(np.diag(w.U)[:, None] - w.shifts[cols][None, :]), axis=0)
+    if pencil:
+        Vt = np.triu(w.extra["V"])
+        R = Ut @ Xh[:, cols] - (Vt @ Xh[:, cols]) * w.shifts[cols][None, :] - w.B[:, cols]
+        nrm = np.array([np.abs(Ut - w.shifts[j] * Vt).sum(1).max() for j in cols])
+    else:
+        R = Ut @ Xh[:, cols] - Xh[:, cols] * w.shifts[cols][None, :] - w.B[:, cols]
+        offrow = np.abs(np.triu(w.U, 1)).sum(1)
+        nrm = np.max(offrow[:, None] + np.abs(np.diag(w.U)[:, None] - w.shifts[cols][None, :]), axis=0)
     resid = float(np.max(np.max(np.abs(R), 0) / (nrm * np.max(np.abs(Xh[:, cols]), 0))))
     del Xs
 
@@ -231,7 +259,7 @@ def main() -> int:
     torch.cuda.synchronize()
     with P.profile() as pr:
         for X in Xs:
-            P.mstrsm(U, lam, X, **opts)
+            solve(X)
     torch.cuda.synchronize()
     del Xs
     prof = pr.result
@@ -246,8 +274,9 @@ def main() -> int:
         "peak": PEAK_FP64_MFMA_TF,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP64_MFMA_TF, 4),
-        "traffic": gemm_traffic(m, n, args.nb, args.outer_nb),
-        "kernel": "k_gemm_direct (substitution GEMM, FP64 MFMA 16x16x4)",
+        "traffic": gemm_traffic(m, n, args.nb, args.outer_nb, pencil),
+        "kernel": ("k_gemm_direct, pencil substitution C -= U X - V (lambda X) (FP64 MFMA 16x16x4)"
+                   if pencil else "k_gemm_direct (substitution GEMM, FP64 MFMA 16x16x4)"),
         "avg_launch_us": round(g["ms"] * 1e3 / max(1, g["launches"]), 2),
         "flops_per_launch": g["flops"] / max(1, g["launches"]),
         "kernel_ms_per_solve": split,
@@ -255,7 +284,7 @@ def main() -> int:
     }
 
     line = {
-        "metric": METRIC,
+        "metric": METRIC_PENCIL if pencil else METRIC,
         "value": round(gflops, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -267,8 +296,11 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "complex128 multi-shift solve, plain FP64, m=%d n=%d shifts (annulus-"
-                               "diagonal U, shifts in disk r=0.4), inputs resident in HBM" % (m, n),
+        "config": {"workload": ("complex128 generalized multi-shift solve (U - l_j V) X = B, FP64, "
+                                "m=%d n=%d shifts (annulus-diagonal U, V diagonal in [0.5, 1.5], "
+                                "shifts in disk r=0.2), inputs resident in HBM" % (m, n)) if pencil else
+                               ("complex128 multi-shift solve, plain FP64, m=%d n=%d shifts (annulus-"
+                                "diagonal U, shifts in disk r=0.4), inputs resident in HBM" % (m, n)),
                    "m": m, "n": n, "nb": args.nb, "outer_nb": args.outer_nb},
         "pct_fp64_mfma_peak": round(100.0 * gflops / 1e3 / PEAK_FP64_MFMA_TF, 2),
         "max_rel_residual_sampled": resid,
@@ -355,28 +387,35 @@ def main() -> int:
         if env_threads and env_threads.isdigit():
             cores = min(cores, int(env_threads))
         oracle.set_num_threads(cores)
+        if pencil:
+            def osolve(k):
+                return oracle.solve_gen(w.U, w.extra["V"], w.shifts[:k], w.B[:, :k])
+        else:
+            def osolve(k):
+                return oracle.solve(w.U, w.shifts[:k], w.B[:, :k])
+        fpc = flops / n   # flops per shift
         probe = min(n, 2 * cores)
         t0 = time.perf_counter()
-        oracle.solve(w.U, w.shifts[:probe], w.B[:, :probe])
+        osolve(probe)
         tp = time.perf_counter() - t0
         ncols = int(min(n, max(probe, probe * args.cpu_seconds / max(tp, 1e-3))))
         ncols = max(cores, (ncols // cores) * cores)
         t0 = time.perf_counter()
-        oracle.solve(w.U, w.shifts[:ncols], w.B[:, :ncols])
+        osolve(ncols)
         tc = time.perf_counter() - t0
-        cg = 4.0 * m * m * ncols / tc / 1e9
+        cg = fpc * ncols / tc / 1e9
         used = oracle.num_threads()
         # the same oracle on one thread, a smaller sample
         oracle.set_num_threads(1)
         n1 = max(1, min(ncols, int(ncols / max(1, cores) * 2)))
         t0 = time.perf_counter()
-        oracle.solve(w.U, w.shifts[:n1], w.B[:, :n1])
+        osolve(n1)
         t1 = time.perf_counter() - t0
         oracle.set_num_threads(cores)
         line["cpu_baseline"] = {"value": round(cg, 3), "unit": "GFLOP/s", "cores": used,
                                 "kind": "oracle",
                                 "sample": "%d of %d shifts of the m=%d workload (%.1f s)" % (ncols, n, m, tc),
-                                "one_thread": {"value": round(4.0 * m * m * n1 / t1 / 1e9, 3),
+                                "one_thread": {"value": round(fpc * n1 / t1 / 1e9, 3),
                                                "sample": "%d shifts (%.1f s)" % (n1, t1)}}
         log("cpu oracle: %d cols in %.1fs = %.2f GFLOP/s on %d threads" % (ncols, tc, cg, cores))
 

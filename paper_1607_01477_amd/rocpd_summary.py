@@ -13,7 +13,7 @@ import sqlite3
 import sys
 
 
-def short(name: str, width: int = 90) -> str:
+def short(name: str, width: int = 110) -> str:
     return name if len(name) <= width else name[: width - 3] + "..."
 
 
@@ -26,10 +26,10 @@ def summarize(db: str, by_grid: str | None = None, out=sys.stdout) -> None:
         if rows:
             total = sum(r[2] for r in rows)
             print("kernel trace (durations in microseconds)", file=out)
-            print("%-90s %7s %12s %10s %10s %10s %6s" % ("kernel", "calls", "total_us", "avg_us",
+            print("%-110s %7s %12s %10s %10s %10s %6s" % ("kernel", "calls", "total_us", "avg_us",
                                                        "min_us", "max_us", "pct"), file=out)
             for name, n, tot, avg, mn, mx in rows:
-                print("%-90s %7d %12.1f %10.2f %10.2f %10.2f %6.2f" % (
+                print("%-110s %7d %12.1f %10.2f %10.2f %10.2f %6.2f" % (
                     short(name), n, tot / 1e3, avg / 1e3, mn / 1e3, mx / 1e3, 100.0 * tot / total), file=out)
         if by_grid:
             rows = con.execute("select grid_x, workgroup_x, count(*), avg(duration) from kernels "
@@ -45,9 +45,9 @@ def summarize(db: str, by_grid: str | None = None, out=sys.stdout) -> None:
                            "order by kernel_name, counter_name").fetchall()
         if rows:
             print("\ncounters (per dispatch mean, total over dispatches)", file=out)
-            print("%-70s %-34s %6s %16s %18s" % ("kernel", "counter", "disp", "mean", "total"), file=out)
+            print("%-110s %-34s %6s %16s %18s" % ("kernel", "counter", "disp", "mean", "total"), file=out)
             for k, c, n, avg, tot in rows:
-                print("%-70s %-34s %6d %16.1f %18.1f" % (short(k, 70), c, n, avg, tot), file=out)
+                print("%-110s %-34s %6d %16.1f %18.1f" % (short(k), c, n, avg, tot), file=out)
 
 
 def main() -> int:
