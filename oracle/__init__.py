@@ -21,6 +21,10 @@ What each function follows (T. Moon, J. Poulson, arXiv 1607.01477):
   paper): ``gB = Y``, ``gU = -triu(Y X^H)``, ``glambda_j = x_j^H y_j``.
 * :func:`triang_eig` — TriangEig, Alg 6 (Sec. 4).
 * :func:`gen_triang_eig` — GeneralizedTriangEig (appendix, Alg 10).
+* :func:`eig_schur`, :func:`gen_eig_schur` — the rest of Eig (Alg 6) and of
+  GeneralizedEig (Alg 10) after the (generalized) Schur decomposition: the
+  back-transformation X = Q Z (resp. P Z), a library matmul, and columns
+  scaled to unit 2-norm.
 * :func:`lanczos_sigma_min` — second stage of the Van Loan/Lui method, Alg 7
   (Sec. 5): Lanczos on ``(U - zI)^{-H}(U - zI)^{-1}``.
 
@@ -255,6 +259,29 @@ def gen_triang_eig(T, S, nb: int = 64, omega_log2: int = OMEGA_LOG2):
     return lam, Z, k
 
 
+def _unit_columns(X) -> np.ndarray:
+    # every column scaled to unit 2-norm (columns that are zero stay zero)
+    nrm = np.sqrt(np.sum(X.real ** 2 + X.imag ** 2, axis=0))
+    return np.asfortranarray(X / np.where(nrm > 0, nrm, 1.0)[None, :])
+
+
+def eig_schur(T, Q, nb: int = 64, omega_log2: int = OMEGA_LOG2):
+    """Eig (Alg 6) after its Schur step: given A = Q T Q^H, lam, Z =
+    TriangEig(T), X = Q Z (the back-transformation), columns scaled to unit
+    2-norm. Returns (lam, X) with A X = X diag(lam)."""
+    lam, Z, _ = triang_eig(T, nb=nb, omega_log2=omega_log2)
+    return lam, _unit_columns(_cm(Q) @ Z)
+
+
+def gen_eig_schur(T, S, P, nb: int = 64, omega_log2: int = OMEGA_LOG2):
+    """GeneralizedEig (appendix, Alg 10) after its generalized Schur step:
+    given A = Q T P^H, B = Q S P^H, lam, Z = GeneralizedTriangEig(T, S),
+    X = P Z, columns scaled to unit 2-norm. Returns (lam, X) with
+    A X = B X diag(lam)."""
+    lam, Z, _ = gen_triang_eig(T, S, nb=nb, omega_log2=omega_log2)
+    return lam, _unit_columns(_cm(P) @ Z)
+
+
 def relative_residual(U, lam, X, B, k=None, cols=None) -> np.ndarray:
     """Per column ||(U - lam_j I) x_j - 2^-k_j b_j||_inf / (||U - lam_j I||_inf ||x_j||_inf)
     with the true modulus; absolute residual where x_j = 0."""
@@ -332,6 +359,7 @@ def lanczos_sigma_min(U, z, V0, iters: int = 15):
 
 
 __all__ = ["build", "solve", "solve_safe", "solve_adjoint", "gradient", "triang_eig",
+           "solve_gen", "solve_safe_gen", "gen_triang_eig", "eig_schur", "gen_eig_schur",
            "relative_residual", "lanczos_sigma_min", "num_threads", "set_num_threads",
            "OMEGA_LOG2"]
 

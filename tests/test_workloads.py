@@ -77,3 +77,14 @@ def test_c6_c7_generalized_pencils():
     S = w7.extra["S"]
     assert np.all(np.tril(S, -1) == 0) and np.all(np.diag(S).real >= 0.5)
     assert np.array_equal(w7.col_len, np.arange(128)) and w7.B is None
+
+
+def test_c8_c9_dense_unit_disk():
+    A = W.c8_dense_eig(m=200).extra["A"]
+    assert A.shape == (200, 200) and A.flags.f_contiguous
+    assert np.abs(A).max() <= 1.0
+    # area-uniform in the unit disk: E|z|^2 = 1/2
+    assert abs(np.mean(np.abs(A) ** 2) - 0.5) < 0.01
+    w = W.c9_dense_pencil(m=64)
+    assert w.extra["A"].shape == w.extra["B"].shape == (64, 64)
+    assert not np.array_equal(w.extra["A"], w.extra["B"])

@@ -29,7 +29,8 @@ import numpy as np
 __all__ = [
     "rng", "cnormal", "disk_uniform", "random_upper",
     "Workload", "c1_plain", "c2_triang_eig", "c3_mixed", "c4_pseudospectra",
-    "c5_adjoint", "c6_generalized", "c7_gen_triang_eig", "WORKLOADS", "nominal_flops",
+    "c5_adjoint", "c6_generalized", "c7_gen_triang_eig", "c8_dense_eig", "c9_dense_pencil",
+    "WORKLOADS", "nominal_flops",
 ]
 
 
@@ -193,6 +194,26 @@ def c7_gen_triang_eig(seed: int = 7, m: int = 2048) -> Workload:
                     np.arange(m, dtype=np.int32), extra={"S": S})
 
 
+def c8_dense_eig(seed: int = 8, m: int = 2048) -> Workload:
+    """General eigenproblem: A with iid entries area-uniform in the unit disk
+    (the paper's dense test matrices have entries uniform in the unit ball).
+    A is in extra["A"]; the Schur factors are computed by the caller."""
+    g = rng(seed)
+    A = np.asfortranarray(disk_uniform(g, m * m, 1.0).reshape(m, m))
+    return Workload("c8_dense_eig", np.zeros((0, 0), dtype=np.complex128),
+                    np.zeros(m, dtype=np.complex128), None, extra={"A": A})
+
+
+def c9_dense_pencil(seed: int = 9, m: int = 1024) -> Workload:
+    """Generalized eigenproblem A x = lambda B x with A and B iid entries
+    area-uniform in the unit disk; extra["A"], extra["B"]."""
+    g = rng(seed)
+    A = np.asfortranarray(disk_uniform(g, m * m, 1.0).reshape(m, m))
+    B = np.asfortranarray(disk_uniform(g, m * m, 1.0).reshape(m, m))
+    return Workload("c9_dense_pencil", np.zeros((0, 0), dtype=np.complex128),
+                    np.zeros(m, dtype=np.complex128), None, extra={"A": A, "B": B})
+
+
 WORKLOADS = {
     "c1_plain": c1_plain,
     "c2_triang_eig": c2_triang_eig,
@@ -201,6 +222,8 @@ WORKLOADS = {
     "c5_adjoint": c5_adjoint,
     "c6_generalized": c6_generalized,
     "c7_gen_triang_eig": c7_gen_triang_eig,
+    "c8_dense_eig": c8_dense_eig,
+    "c9_dense_pencil": c9_dense_pencil,
 }
 
 
