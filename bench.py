@@ -84,7 +84,8 @@ def _time(fn, torch, reps):
 def other_workloads(P, W, torch, np) -> dict:
     """Triangular eigenvectors (safe solve, variable-length columns), inverse
     Lanczos on a 100x100 shift grid, forward + backward through the solve, the
-    generalized (pencil) solve and generalized triangular eigenvectors."""
+    generalized (pencil) solve, generalized triangular eigenvectors and
+    general eigenvectors after a host Schur decomposition."""
     out = {}
     # triangular eigenvectors, m = 2048: sum_j 4 j^2 flops
     w = W.c2_triang_eig()
@@ -153,6 +154,27 @@ def other_workloads(P, W, torch, np) -> dict:
     out["c7_gen_triang_eig_m2048"] = {"ms": round(ms, 3), "gflops": round(fl / (ms * 1e-3) / 1e9, 2),
                                       "rescaled_columns": int((k > 0).sum().item())}
     log("generalized triangular eigenvectors m=2048: %.3f ms" % ms)
+    del T, S, Z
+    # general eigenvectors (Eig, Alg 6), m = 2048: host Schur (context), then
+    # TriangEig + X = Q Z (4 m^3 flops on the matrix cores) + unit columns on the GPU
+    import scipy.linalg as sla
+    A = W.c8_dense_eig().extra["A"]
+    t0 = time.perf_counter()
+    Th, Qh = sla.schur(A, output="complex")
+    t_schur = time.perf_counter() - t0
+    T, Q = dev(Th, torch), dev(Qh, torch)
+    ms = _time(lambda: P.eig_schur(T, Q), torch, 3)
+    ev, X, k = P.eig_schur(T, Q)
+    Xh, evh = X.cpu().numpy(), ev.cpu().numpy()
+    res = float(np.linalg.norm(A @ Xh - Xh * evh[None, :]) / np.linalg.norm(A))
+    with P.profile() as pr:
+        P.eig_schur(T, Q)
+    bt = pr.result["resid"]
+    out["c8_eig_m2048"] = {"gpu_ms": round(ms, 3), "host_schur_s": round(t_schur, 2),
+                           "backtransform_ms": round(bt["ms"], 3),
+                           "backtransform_tflops": round(bt["flops"] / (bt["ms"] * 1e-3) / 1e12, 2),
+                           "rel_residual_F": res}
+    log("eigenvectors m=2048: %.3f ms on the GPU (host Schur %.1f s), residual %.1e" % (ms, t_schur, res))
     return out
 
 

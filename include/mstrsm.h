@@ -203,6 +203,35 @@ mst_status mst_gen_triang_eig(int m, const void* T, int ldt, const void* S, int 
                               void* stream);
 
 /*
+ * mst_eig_schur — the rest of Eig, Alg 6 (Sec. 4), after the Schur
+ * decomposition A = Q T Q^H (computed by the caller, e.g. LAPACK xGEES on the
+ * host): eigenvalues diag(T), triangular eigenvectors Z = TriangEig(T), the
+ * back-transformation X = Q Z as a triangular product on the matrix cores,
+ * and every column of X scaled to unit 2-norm, so that A X = X diag(eigvals).
+ *   T, ldt        m x m upper triangular Schur factor, read only
+ *   Q, ldq        m x m unitary Schur vectors, read only
+ *   X, ldx        m x m output (may not alias T or Q)
+ *   eigvals       m complex output
+ *   scale_log2    nullable, m int32 output: k_j of TriangEig (Z(j,j) = 2^-k_j)
+ */
+mst_status mst_eig_schur(int m, const void* T, int ldt, const void* Q, int ldq, void* X, int ldx,
+                         void* eigvals, int* scale_log2, const mst_opts* opt, void* stream);
+
+/*
+ * mst_gen_eig_schur — the rest of GeneralizedEig, appendix (Alg 10), after the
+ * generalized Schur decomposition A = Q T P^H, B = Q S P^H (the caller's, e.g.
+ * LAPACK xGGES): eigenvalues T(j,j)/S(j,j), Z = GeneralizedTriangEig(T, S),
+ * X = P Z on the matrix cores, columns scaled to unit 2-norm, so that
+ * A X = B X diag(eigvals). S(j,j) must be nonzero.
+ *   T, S          m x m upper triangular, read only; P, ldp  m x m, read only
+ *   X, ldx        m x m output (may not alias the inputs)
+ * Supported: nb = 16 (the default); otherwise MST_EUNSUPPORTED.
+ */
+mst_status mst_gen_eig_schur(int m, const void* T, int ldt, const void* S, int lds, const void* P, int ldp,
+                             void* X, int ldx, void* eigvals, int* scale_log2, const mst_opts* opt,
+                             void* stream);
+
+/*
  * mst_lanczos_sigma_min — second stage of the Van Loan/Lui method (Alg 7,
  * Sec. 5): for every shift z_j, `iters` steps of plain Lanczos (no
  * reorthogonalisation) on (U - z_j I)^{-H} (U - z_j I)^{-1}, each product
@@ -233,7 +262,7 @@ enum {
     MST_PROF_GEMM_F64 = 0,   /* substitution GEMM, FP64 matrix cores */
     MST_PROF_GEMM_F32 = 1,   /* substitution GEMM, FP32 matrix cores */
     MST_PROF_DIAG = 2,       /* diagonal-block solves */
-    MST_PROF_RESID = 3,      /* residual and gradient products */
+    MST_PROF_RESID = 3,      /* residual, gradient and back-transformation products */
     MST_PROF_AUX = 4,        /* norms, rescaling, conversions, Lanczos vectors */
     MST_PROF_KINDS = 5
 };

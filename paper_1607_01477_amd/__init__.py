@@ -23,6 +23,7 @@ from ._lib import MstError, MstOpts
 
 __all__ = ["mstrsm", "mstrsm_safe", "mstrsm_adjoint", "grad_u", "grad_shift", "residual",
            "triang_eig", "lanczos_sigma_min", "mstrsm_gen", "mstrsm_safe_gen", "gen_triang_eig",
+           "eig_schur", "gen_eig_schur", "eig", "gen_eig",
            "solve", "MultiShiftSolve", "colmajor",
            "MstError", "version", "lib_path"]
 
@@ -275,6 +276,74 @@ def gen_triang_eig(T, S, *, outer_nb=0, omega_log2=0, fuse=True):
                                         _p(klog), ctypes.byref(o), _stream())
     _lib.check("mst_gen_triang_eig", rc)
     return ev, Z, klog
+
+
+def eig_schur(T, Q, *, nb=0, outer_nb=0, omega_log2=0):
+    """Eig (Alg 6) after the Schur step A = Q T Q^H: returns (eigvals, X,
+    scale_log2) with A X = X diag(eigvals), columns of X of unit 2-norm."""
+    T = _mat(T, "T")
+    Q = _mat(Q, "Q")
+    m = T.shape[0]
+    if T.shape != (m, m) or Q.shape != (m, m):
+        raise ValueError("T and Q must be square and of one size")
+    X = torch.empty_strided((m, m), (1, max(1, m)), dtype=torch.complex128, device=T.device)
+    ev = torch.empty(m, dtype=torch.complex128, device=T.device)
+    klog = torch.empty(m, dtype=torch.int32, device=T.device)
+    o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2)
+    rc = _lib.load().mst_eig_schur(m, _p(T), _ld(T), _p(Q), _ld(Q), _p(X), max(1, m), _p(ev), _p(klog),
+                                   ctypes.byref(o), _stream())
+    _lib.check("mst_eig_schur", rc)
+    return ev, X, klog
+
+
+def gen_eig_schur(T, S, P, *, outer_nb=0, omega_log2=0):
+    """GeneralizedEig (appendix, Alg 10) after A = Q T P^H, B = Q S P^H:
+    returns (eigvals, X, scale_log2) with A X = B X diag(eigvals), unit columns."""
+    T = _mat(T, "T")
+    S = _mat(S, "S")
+    P = _mat(P, "P")
+    m = T.shape[0]
+    if T.shape != (m, m) or S.shape != (m, m) or P.shape != (m, m):
+        raise ValueError("T, S and P must be square and of one size")
+    X = torch.empty_strided((m, m), (1, max(1, m)), dtype=torch.complex128, device=T.device)
+    ev = torch.empty(m, dtype=torch.complex128, device=T.device)
+    klog = torch.empty(m, dtype=torch.int32, device=T.device)
+    o = _opts(outer_nb=outer_nb, omega_log2=omega_log2)
+    rc = _lib.load().mst_gen_eig_schur(m, _p(T), _ld(T), _p(S), _ld(S), _p(P), _ld(P), _p(X), max(1, m),
+                                       _p(ev), _p(klog), ctypes.byref(o), _stream())
+    _lib.check("mst_gen_eig_schur", rc)
+    return ev, X, klog
+
+
+def eig(A, *, nb=0, outer_nb=0):
+    """Eigenpairs of a general square A (Alg 6): the Schur decomposition
+    A = Q T Q^H on the host (LAPACK through SciPy), then TriangEig, the
+    back-transformation X = Q Z and unit columns on the GPU. Returns
+    (eigvals, X) as device tensors."""
+    import numpy as np
+    import scipy.linalg as sla
+    dev = A.device if isinstance(A, torch.Tensor) and A.is_cuda else torch.device("cuda")
+    An = A.detach().cpu().numpy() if isinstance(A, torch.Tensor) else np.asarray(A)
+    T, Q = sla.schur(An.astype(np.complex128), output="complex")
+    ev, X, _ = eig_schur(torch.from_numpy(T).to(dev), torch.from_numpy(Q).to(dev), nb=nb,
+                         outer_nb=outer_nb)
+    return ev, X
+
+
+def gen_eig(A, B, *, outer_nb=0):
+    """Eigenpairs of the pencil A x = lambda B x (appendix, Alg 10): the QZ
+    decomposition A = Q T P^H, B = Q S P^H on the host (LAPACK through SciPy),
+    then GeneralizedTriangEig, X = P Z and unit columns on the GPU.
+    Infinite eigenvalues (S(j,j) = 0) are not supported."""
+    import numpy as np
+    import scipy.linalg as sla
+    dev = A.device if isinstance(A, torch.Tensor) and A.is_cuda else torch.device("cuda")
+    An = A.detach().cpu().numpy() if isinstance(A, torch.Tensor) else np.asarray(A)
+    Bn = B.detach().cpu().numpy() if isinstance(B, torch.Tensor) else np.asarray(B)
+    T, S, _, P = sla.qz(An.astype(np.complex128), Bn.astype(np.complex128), output="complex")
+    ev, X, _ = gen_eig_schur(torch.from_numpy(T).to(dev), torch.from_numpy(S).to(dev),
+                             torch.from_numpy(P).to(dev), outer_nb=outer_nb)
+    return ev, X
 
 
 def lanczos_sigma_min(U, z, V0, iters=15, *, nb=0, outer_nb=0):

@@ -481,6 +481,36 @@ mst_status plain_solve(int m, int n, const zd* U, long ldu, const zd* lam, zd* B
     return MST_OK;
 }
 
+// Eigenvectors from a (generalized) Schur form: triangular eigenvectors Z into
+// workspace, X = Qb Z on the matrix cores (Z upper triangular), columns of X
+// scaled to unit 2-norm. S == nullptr: Alg 6; otherwise Alg 10.
+mst_status eig_from_schur(int m, const zd* T, long ldt, const zd* S, long lds, const zd* Qb, long ldq,
+                          zd* X, long ldx, zd* eig, int* klog, const Opts& o, hipStream_t s) {
+    Workspace ws(s);
+    zd* Z;
+    int* col_len;
+    double* scale;
+    HIPCHK(ws_get(ws, (size_t)m * m, &Z));
+    HIPCHK(ws_get(ws, (size_t)m, &col_len));
+    HIPCHK(ws_get(ws, (size_t)m, &scale));
+    if (S) {
+        HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_gen_triang_setup(m, T, ldt, S, lds, Z, m, eig, col_len, s); }));
+    } else {
+        HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_triang_setup(m, T, ldt, Z, m, eig, col_len, s); }));
+    }
+    mst_status st = safe_solve(m, m, T, ldt, eig, Z, m, col_len, scale, klog, o, s, ws, S, lds);
+    if (st != MST_OK) return st;
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_triang_diag(m, Z, m, scale, s); }));
+    GemmArgs g{};
+    g.M = m; g.N = m; g.K = m; g.op = GOP_TRMM;
+    g.A = Qb; g.lda = ldq;
+    g.B = Z; g.ldb = m;
+    g.C = X; g.ldc = ldx;
+    HIPCHK(timed(MST_PROF_RESID, 4.0 * m * (double)m * m, s, [&] { return launch_gemm_f64(g, s); }));
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_normalize_cols(m, m, X, ldx, s); }));
+    return MST_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -703,6 +733,42 @@ mst_status mst_gen_triang_eig(int m, const void* T, int ldt, const void* S, int 
     if (st != MST_OK) return st;
     HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_triang_diag(m, (zd*)Z, ldz, scale, s); }));
     return MST_OK;
+}
+
+mst_status mst_eig_schur(int m, const void* T, int ldt, const void* Q, int ldq, void* X, int ldx,
+                         void* eigvals, int* scale_log2, const mst_opts* opt, void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    mst_status st;
+    if ((st = check_mat(T, ldt, m, m, 2, 3)) != MST_OK) return st;
+    if ((st = check_mat(Q, ldq, m, m, 4, 5)) != MST_OK) return st;
+    if ((st = check_mat(X, ldx, m, m, 6, 7)) != MST_OK) return st;
+    if (m > 0 && !eigvals) return bad(8);
+    Opts o;
+    if ((st = read_opts(opt, o, 10)) != MST_OK) return st;
+    if (o.precision != 0) return MST_EUNSUPPORTED;
+    if (m == 0) return MST_OK;
+    return eig_from_schur(m, (const zd*)T, ldt, nullptr, 0, (const zd*)Q, ldq, (zd*)X, ldx, (zd*)eigvals,
+                          scale_log2, o, (hipStream_t)stream);
+}
+
+mst_status mst_gen_eig_schur(int m, const void* T, int ldt, const void* S, int lds, const void* P, int ldp,
+                             void* X, int ldx, void* eigvals, int* scale_log2, const mst_opts* opt,
+                             void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    mst_status st;
+    if ((st = check_mat(T, ldt, m, m, 2, 3)) != MST_OK) return st;
+    if ((st = check_mat(S, lds, m, m, 4, 5)) != MST_OK) return st;
+    if ((st = check_mat(P, ldp, m, m, 6, 7)) != MST_OK) return st;
+    if ((st = check_mat(X, ldx, m, m, 8, 9)) != MST_OK) return st;
+    if (m > 0 && !eigvals) return bad(10);
+    Opts o;
+    if ((st = read_opts(opt, o, 12)) != MST_OK) return st;
+    if (o.nb != 16 || o.precision != 0) return MST_EUNSUPPORTED;
+    if (m == 0) return MST_OK;
+    return eig_from_schur(m, (const zd*)T, ldt, (const zd*)S, lds, (const zd*)P, ldp, (zd*)X, ldx,
+                          (zd*)eigvals, scale_log2, o, (hipStream_t)stream);
 }
 
 mst_status mst_lanczos_sigma_min(int m, int N, const void* U, int ldu, const void* z, void* V, int ldv,

@@ -71,6 +71,7 @@ enum GemmOp : int {
     GOP_RESID = 1,    // C = B0 - acc + lam_c * Bop(row, c)   (A upper triangular, global indices)
     GOP_NEG_TRIU = 2, // C = -acc on and above the diagonal, 0 below
     GOP_GEN_SUB = 3,  // C = 2^-dk_c * C - A B + lam_c * (A2 B)   (pencil substitution)
+    GOP_TRMM = 4,     // C = A B, B upper triangular (its strict lower triangle is not read)
 };
 struct GemmArgs {
     int M, N, K;

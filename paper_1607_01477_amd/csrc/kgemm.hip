@@ -346,7 +346,8 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(GemmArgs g) {
 // share A rows / B columns through L1.
 template <typename T, int DEPTH, int OP, bool A_CT, bool SAFE, bool VARLEN>
 __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
-    static_assert(OP == GOP_SUB || OP == GOP_NEG_TRIU || OP == GOP_RESID || OP == GOP_GEN_SUB,
+    static_assert(OP == GOP_SUB || OP == GOP_NEG_TRIU || OP == GOP_RESID || OP == GOP_GEN_SUB ||
+                      OP == GOP_TRMM,
                   "direct GEMM op");
     static_assert(OP == GOP_SUB || OP == GOP_GEN_SUB || (!A_CT && !SAFE && !VARLEN),
                   "triangular products: plain A only");
@@ -356,6 +357,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
     constexpr bool TRI = OP == GOP_NEG_TRIU;
     constexpr bool RES = OP == GOP_RESID;
     constexpr bool GEN = OP == GOP_GEN_SUB;
+    constexpr bool TRM = OP == GOP_TRMM;
     using Tr = Traits<T>;
     using CT = typename Tr::C;
     using V = typename Tr::V;
@@ -369,6 +371,11 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
         // hardware deals workgroup w to XCD w % 8)
         tm = blockIdx.x / TN;
         tn = blockIdx.x - tm * TN;
+    } else if (TRM) {
+        // work grows with the tile column (K runs to the column): column
+        // major, heaviest columns first, each column spread over all XCDs
+        tn = TN - 1 - blockIdx.x / TM;
+        tm = blockIdx.x - (TN - 1 - tn) * TM;
     } else {
         tile_coords(TM, TN, tm, tn);
     }
@@ -444,7 +451,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             for (int v = 0; v < 4; ++v) {
                 const int row = rw + i * 16 + Tr::out_row(lq, v);
                 CT c{0, 0};
-                if (!TRI && !GEN && col < g.N && row < cl) {
+                if (!TRI && !GEN && !TRM && col < g.N && row < cl) {
                     if (RES) {
                         const zd b0 = g.B0[(long)col * g.ldb0 + row];
                         const CT x = B[(long)col * g.ldb + row];
@@ -470,8 +477,8 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
     // flight for later steps. Elements outside the product are zeroed where
     // they are consumed (the clamped load may return anything, even NaN).
     const int nks = (g.K + 3) / 4;
-    const int kfirst = RES ? (rw >> 2) : 0;   // U(row, k) = 0 for k < row
-    const int nloc = nks - kfirst;
+    const int kfirst0 = RES ? (rw >> 2) : 0;   // U(row, k) = 0 for k < row
+    const int nloc0 = nks - kfirst0;
     const int ra0 = min(rw + lr, g.M - 1), ra1 = min(rw + 16 + lr, g.M - 1);
     const int cb0 = min(cw + lr, g.N - 1), cb1 = min(cw + 16 + lr, g.N - 1);
     const bool oka0 = rw + lr < g.M, oka1 = rw + 16 + lr < g.M;
@@ -497,7 +504,8 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
         }
     }
 
-    auto kloop = [&](auto mask_tag, const CT* __restrict__ A, long lda) __attribute__((always_inline)) {
+    auto kloop = [&](auto mask_tag, const CT* __restrict__ A, long lda, int kfirst, int nloc)
+        __attribute__((always_inline)) {
         constexpr bool MASK = decltype(mask_tag)::value;
         CT pa0[DEPTH], pa1[DEPTH], pb0[DEPTH], pb1[DEPTH];
         int qe0[DEPTH] = {}, qe1[DEPTH] = {};
@@ -541,7 +549,9 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                     u0 = u0 && k >= rw + lr;
                     u1 = u1 && k >= rw + 16 + lr;
                 }
-                const bool v0 = k < blim0, v1 = k < blim1;
+                // (TRM: B(k, c) = 0 below the diagonal, k > c)
+                const bool v0 = k < blim0 && (!TRM || k <= cw + lr);
+                const bool v1 = k < blim1 && (!TRM || k <= cw + 16 + lr);
                 a0.re = u0 ? a0.re : T(0); a0.im = u0 ? a0.im : T(0);
                 a1.re = u1 ? a1.re : T(0); a1.im = u1 ? a1.im : T(0);
                 b0.re = v0 ? b0.re : T(0); b0.im = v0 ? b0.im : T(0);
@@ -556,10 +566,11 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 // FP64: every sign is an MFMA source modifier (the last operand's
                 // bit 0 negates A), so the loop spends no VALU on negation:
                 //   Re -= ar br - a'i b'i,  Im -= ar b'i + a'i br
-                constexpr int NRR = 1;
-                constexpr int NII = (A_CT != TRI) ? 1 : 0;   // + sa sb ai bi
-                constexpr int NRI = TRI ? 0 : 1;             // - sb ar bi
-                constexpr int NIR = A_CT ? 0 : 1;            // - sa ai br
+                // (TRM: acc += A B, i.e. Re += ar br - ai bi, Im += ar bi + ai br)
+                constexpr int NRR = TRM ? 0 : 1;
+                constexpr int NII = TRM ? 1 : ((A_CT != TRI) ? 1 : 0);   // + sa sb ai bi
+                constexpr int NRI = (TRI || TRM) ? 0 : 1;               // - sb ar bi
+                constexpr int NIR = (A_CT || TRM) ? 0 : 1;              // - sa ai br
                 accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.re, b0.re, accR[0][0], 0, 0, NRR);
                 accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.re, b1.re, accR[0][1], 0, 0, NRR);
                 accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.re, b0.re, accR[1][0], 0, 0, NRR);
@@ -661,14 +672,14 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             if (l0 + d < nloc) mma(kfirst + l0 + d, pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
     };
     // interior tiles of the plain forms need no masking at all
-    const bool unmasked = full && (g.K & 3) == 0 && nloc >= DEPTH && !RES && plain_ok;
+    const bool unmasked = full && (g.K & 3) == 0 && nloc0 >= DEPTH && !RES && plain_ok;
     if (GEN) {
         // pencil: acc = -A2 B, then acc = lam_c * (A2 B) per column (once per
         // tile, not per k-step), then acc -= A B; C is added in the epilogue
         if (unmasked)
-            kloop(std::false_type{}, (const CT*)g.A2, g.lda2);
+            kloop(std::false_type{}, (const CT*)g.A2, g.lda2, 0, nloc0);
         else
-            kloop(std::true_type{}, (const CT*)g.A2, g.lda2);
+            kloop(std::true_type{}, (const CT*)g.A2, g.lda2, 0, nloc0);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -680,10 +691,23 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                     accI[i][j][v] = -(lamv[j].re * im + lamv[j].im * r);
                 }
     }
-    if (unmasked)
-        kloop(std::false_type{}, A, g.lda);
-    else
-        kloop(std::true_type{}, A, g.lda);
+    if (TRM) {
+        // B upper triangular: column c needs k <= c. k-steps below the
+        // wavefront's first column need no mask; the (at most 8) steps across
+        // its 32 columns are masked, and nothing past its last column is read.
+        const int nk = (min(g.K, cw + 32) + 3) / 4;
+        const int nfree = min(cw / 4, nk);
+        int done = 0;
+        if (full && (g.K & 3) == 0 && nfree >= DEPTH) {
+            kloop(std::false_type{}, A, g.lda, 0, nfree);
+            done = nfree;
+        }
+        kloop(std::true_type{}, A, g.lda, done, nk - done);
+    } else if (unmasked) {
+        kloop(std::false_type{}, A, g.lda, kfirst0, nloc0);
+    } else {
+        kloop(std::true_type{}, A, g.lda, kfirst0, nloc0);
+    }
 
     // ---- epilogue
 #pragma unroll
@@ -764,6 +788,9 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
             if (safe) return go_direct<double, GOP_GEN_SUB, false, true, false>(g, s);
             if (varlen) return hipErrorInvalidValue;
             return go_direct<double, GOP_GEN_SUB, false, false, false>(g, s);
+        case GOP_TRMM:
+            if (g.a_ct || g.b_ct || safe || varlen || g.staged) return hipErrorInvalidValue;
+            return go_direct<double, GOP_TRMM, false, false, false>(g, s);
         case GOP_NEG_TRIU:
             if (g.a_ct || !g.b_ct || safe || varlen) return hipErrorInvalidValue;
             if (g.staged) return go<double, false, true, GOP_NEG_TRIU, false, false>(g, s);
