@@ -11,6 +11,8 @@ What each function follows (T. Moon, J. Poulson, arXiv 1607.01477):
   for each shift, the per-column content of Alg 3.
 * :func:`solve_safe` — Alg 4 (Sec. 3) per column (``nb=0``), or Alg 5 (Sec. 3)
   with decision block size ``nb``; scale factors ``s_j = 2^-k_j``.
+* :func:`solve_op` — the lower-triangular and (conjugate-)transposed variants
+  of the footnote to Sec. 2, op(A - lambda_j I) x_j = b_j.
 * :func:`solve_gen` — the generalized solve ``(U - lambda_j V) x_j = b_j``
   of the appendix (Alg 8), unblocked: back substitution on the shifted pencil.
 * :func:`solve_safe_gen` — its safe form, Alg 9: Alg 4 on each shifted
@@ -80,8 +82,9 @@ def _load():
             lib.oracle_mstrsm_safe.argtypes = [I, I, P, I, P, P, I, P, P, P, I, I, I, P]
             lib.oracle_mstrsm_gen.argtypes = [I, I, P, I, P, I, P, P, I]
             lib.oracle_mstrsm_safe_gen.argtypes = [I, I, P, I, P, I, P, P, I, P, P, P, I, I, I]
+            lib.oracle_mstrsm_op.argtypes = [I, I, I, I, P, I, P, P, I]
             for f in (lib.oracle_mstrsm, lib.oracle_mstrsm_adjoint, lib.oracle_mstrsm_safe,
-                      lib.oracle_mstrsm_gen, lib.oracle_mstrsm_safe_gen):
+                      lib.oracle_mstrsm_gen, lib.oracle_mstrsm_safe_gen, lib.oracle_mstrsm_op):
                 f.restype = I
             lib.oracle_num_threads.restype = I
             lib.oracle_set_num_threads.argtypes = [I]
@@ -116,6 +119,24 @@ def solve(U, lam, B) -> np.ndarray:
     rc = _load().oracle_mstrsm(m, n, _ptr(U), max(1, m), _ptr(lam), _ptr(X), max(1, m))
     if rc != 0:
         raise RuntimeError("oracle_mstrsm failed: %d" % rc)
+    return X
+
+
+def solve_op(A, lam, B, uplo: str = "U", op: str = "N") -> np.ndarray:
+    """X with op(A - lam[j] I) X[:, j] = B[:, j] for A upper ('U') or lower
+    ('L') triangular and op 'N', 'T' (transpose) or 'C' (conjugate
+    transpose): the variants of the footnote to Sec. 2 (back substitution when
+    op(A) is upper triangular, forward substitution when it is lower)."""
+    A = _cm(A)
+    lam = np.ascontiguousarray(lam, dtype=np.complex128)
+    X = _cm(B).copy(order="F")
+    m, n = X.shape
+    if A.shape != (m, m) or lam.shape != (n,):
+        raise ValueError("shape mismatch")
+    rc = _load().oracle_mstrsm_op(ord(uplo), ord(op), m, n, _ptr(A), max(1, m), _ptr(lam), _ptr(X),
+                                  max(1, m))
+    if rc != 0:
+        raise RuntimeError("oracle_mstrsm_op failed: %d" % rc)
     return X
 
 
@@ -359,7 +380,7 @@ def lanczos_sigma_min(U, z, V0, iters: int = 15):
 
 
 __all__ = ["build", "solve", "solve_safe", "solve_adjoint", "gradient", "triang_eig",
-           "solve_gen", "solve_safe_gen", "gen_triang_eig", "eig_schur", "gen_eig_schur",
+           "solve_gen", "solve_safe_gen", "gen_triang_eig", "eig_schur", "gen_eig_schur", "solve_op",
            "relative_residual", "lanczos_sigma_min", "num_threads", "set_num_threads",
            "OMEGA_LOG2"]
 

@@ -131,6 +131,53 @@ int oracle_mstrsm_gen(int m, int n, const double* Up, int ldu, const double* Vp,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Variants of the footnote to Sec. 2: op(A - lambda_j I) x_j = b_j with A   */
+/* upper (uplo 'U') or lower (uplo 'L') triangular and op the identity ('N'),*/
+/* the transpose ('T') or the conjugate transpose ('C'). The operator        */
+/* E = op(A - lambda I) is triangular: upper for (U,N), (L,T), (L,C), solved */
+/* by back substitution; lower for (U,T), (U,C), (L,N), solved by forward    */
+/* substitution. Entries: E(r,c) = A(r,c) for 'N', A(c,r) for 'T',           */
+/* conj(A(c,r)) for 'C'; diagonal A(r,r) - lambda, conjugated for 'C'. The   */
+/* other triangle of A is never read.                                        */
+/* ------------------------------------------------------------------------ */
+static inline zc opel(const zc* A, int lda, int trans, int conj, int r, int c) {
+    zc a = trans ? AT(A, lda, c, r) : AT(A, lda, r, c);
+    return conj ? zconj(a) : a;
+}
+
+static void trsv_op(int m, const zc* A, int lda, int upper_e, int trans, int conj, zc lam, zc* b) {
+    if (upper_e) {
+        for (int i = m - 1; i >= 0; --i) {
+            zc d = zsub(opel(A, lda, trans, conj, i, i), conj ? zconj(lam) : lam);
+            zc x = zdiv(b[i], d);
+            b[i] = x;
+            for (int r = 0; r < i; ++r) b[r] = zaxpy_neg(b[r], opel(A, lda, trans, conj, r, i), x);
+        }
+    } else {
+        for (int i = 0; i < m; ++i) {
+            zc d = zsub(opel(A, lda, trans, conj, i, i), conj ? zconj(lam) : lam);
+            zc x = zdiv(b[i], d);
+            b[i] = x;
+            for (int r = i + 1; r < m; ++r) b[r] = zaxpy_neg(b[r], opel(A, lda, trans, conj, r, i), x);
+        }
+    }
+}
+
+int oracle_mstrsm_op(int uplo, int op, int m, int n, const double* Ap, int lda, const double* lamp,
+                     double* Bp, int ldb) {
+    if (m < 0 || n < 0 || lda < (m > 1 ? m : 1) || ldb < (m > 1 ? m : 1)) return -1;
+    if ((uplo != 'U' && uplo != 'L') || (op != 'N' && op != 'T' && op != 'C')) return -2;
+    const int trans = op != 'N', conj = op == 'C';
+    const int upper_e = (uplo == 'U') == (op == 'N');
+    const zc* A = (const zc*)Ap;
+    const zc* lam = (const zc*)lamp;
+    zc* B = (zc*)Bp;
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) trsv_op(m, A, lda, upper_e, trans, conj, lam[j], &AT(B, ldb, 0, j));
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Adjoint solve: (U - lambda_j I)^H y_j = g_j. U^H is lower triangular, so */
 /* this is forward substitution (the lower-triangular variant the paper     */
 /* notes in its footnote to Sec. 2):                                        */
