@@ -84,8 +84,9 @@ def _time(fn, torch, reps):
 def other_workloads(P, W, torch, np) -> dict:
     """Triangular eigenvectors (safe solve, variable-length columns), inverse
     Lanczos on a 100x100 shift grid, forward + backward through the solve, the
-    generalized (pencil) solve, generalized triangular eigenvectors and
-    general eigenvectors after a host Schur decomposition."""
+    generalized (pencil) solve, generalized triangular eigenvectors, general
+    eigenvectors after a host Schur decomposition, and the lower-triangular /
+    transposed variants."""
     out = {}
     # triangular eigenvectors, m = 2048: sum_j 4 j^2 flops
     w = W.c2_triang_eig()
@@ -175,6 +176,21 @@ def other_workloads(P, W, torch, np) -> dict:
                            "backtransform_tflops": round(bt["flops"] / (bt["ms"] * 1e-3) / 1e12, 2),
                            "rel_residual_F": res}
     log("eigenvectors m=2048: %.3f ms on the GPU (host Schur %.1f s), residual %.1e" % (ms, t_schur, res))
+    del T, Q, X
+    # lower-triangular and transposed variants, m = 4096, n = 2048 (4 m^2 n flops each)
+    w = W.c5_adjoint()
+    Ud = dev(w.U, torch)
+    Ld = dev(np.asfortranarray(w.U.T.copy()), torch)
+    sv = torch.from_numpy(w.shifts).cuda()
+    Bv = dev(w.B, torch)
+    fl = W.nominal_flops(w.m, w.n)
+    var = {}
+    for uplo, op in (("L", "N"), ("L", "T"), ("L", "C"), ("U", "T")):
+        A = Ld if uplo == "L" else Ud
+        msv = _time(lambda: P.mstrsm_op(A, sv, Bv, uplo=uplo, op=op), torch, 3)
+        var[uplo + op] = {"ms": round(msv, 3), "gflops": round(fl / (msv * 1e-3) / 1e9, 2)}
+    out["variants_m4096_n2048"] = var
+    log("variants m=4096 n=2048: %s" % ", ".join("%s %.3f ms" % (k, v["ms"]) for k, v in var.items()))
     return out
 
 

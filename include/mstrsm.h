@@ -119,6 +119,26 @@ mst_status mstrsm_adjoint(int m, int n, const void* U, int ldu, const void* shif
                           void* G, int ldg, const mst_opts* opt, void* stream);
 
 /*
+ * mstrsm_op — the lower-triangular and right-side variants the footnote to
+ * Sec. 2 mentions, and the transposed ones:
+ *   side 'L':  op(A - shifts[j] I) X(:,j) = B(:,j)
+ *   side 'R':  X(:,j)^T op(A - shifts[j] I) = B(:,j)^T   (the row vector x_j is
+ *              stored as the column X(:,j); op 'N' or 'T' only)
+ * with A upper ('U') or lower ('L') triangular and op 'N' (identity), 'T'
+ * (transpose) or 'C' (conjugate transpose, so the shift enters conjugated).
+ * When op(A) is upper triangular the solve is back substitution (Alg 3),
+ * when lower forward substitution (blocks top to bottom); the triangle of A
+ * that the variant does not use is never read. (U, 'N') is mstrsm and honours
+ * opt->precision; every other variant is FP64 only (precision 1 gives
+ * MST_EUNSUPPORTED). Plain solves: no scaling, like mstrsm.
+ *   side, uplo, op   the characters above (as int)
+ *   A, lda           m x m triangular, read only
+ *   B, ldb           m x n; on entry the right-hand sides, on exit X
+ */
+mst_status mstrsm_op(int side, int uplo, int op, int m, int n, const void* A, int lda,
+                     const void* shifts, void* B, int ldb, const mst_opts* opt, void* stream);
+
+/*
  * Gradient pieces of a real loss L through X = solve(U, shifts, B), given
  * Y = adjoint solve of dL/dX (gradient convention dL/dRe z + i dL/dIm z).
  * The gradient of B is Y itself.

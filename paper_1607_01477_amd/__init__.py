@@ -23,7 +23,7 @@ from ._lib import MstError, MstOpts
 
 __all__ = ["mstrsm", "mstrsm_safe", "mstrsm_adjoint", "grad_u", "grad_shift", "residual",
            "triang_eig", "lanczos_sigma_min", "mstrsm_gen", "mstrsm_safe_gen", "gen_triang_eig",
-           "eig_schur", "gen_eig_schur", "eig", "gen_eig",
+           "eig_schur", "gen_eig_schur", "eig", "gen_eig", "mstrsm_op",
            "solve", "MultiShiftSolve", "colmajor",
            "MstError", "version", "lib_path"]
 
@@ -162,6 +162,25 @@ def mstrsm_adjoint(U, shifts, G, *, nb=0, outer_nb=0, fuse=True, overlap=False, 
                                     _stream())
     _lib.check("mstrsm_adjoint", rc)
     return Y
+
+
+def mstrsm_op(A, shifts, B, *, uplo="U", op="N", side="L", nb=0, outer_nb=0, fuse=True,
+              precision=0, max_sweeps=2):
+    """Variants of the footnote to Sec. 2: X with op(A - shifts[j] I) X[:, j] = B[:, j]
+    (side "L") or X[:, j]^T op(A - shifts[j] I) = B[:, j]^T (side "R"), A upper
+    ("U") or lower ("L") triangular, op "N", "T" or "C" (side "R": "N" or "T").
+    B is overwritten when it is already column-major complex128."""
+    A = _mat(A, "A")
+    X = _mat(B, "B")
+    m, n = X.shape
+    if A.shape != (m, m):
+        raise ValueError("A must be %d x %d" % (m, m))
+    s = _vec(shifts, n, "shifts")
+    o = _opts(nb=nb, outer_nb=outer_nb, fuse=fuse, precision=precision, max_sweeps=max_sweeps)
+    rc = _lib.load().mstrsm_op(ord(side), ord(uplo), ord(op), m, n, _p(A), _ld(A), _p(s), _p(X), _ld(X),
+                               ctypes.byref(o), _stream())
+    _lib.check("mstrsm_op", rc)
+    return X
 
 
 def grad_u(Y, X):

@@ -184,7 +184,11 @@ constexpr int kSuperRows = 1024;
 hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long ldu32,
                         const zd* lam, zd* B, long ldb, zf* W32, long ldw, const Opts& o,
                         const SafeState* safe, const int* col_len, hipStream_t s,
-                        const zd* V = nullptr, long ldv = 0) {
+                        const zd* V = nullptr, long ldv = 0, int ev = EV_UPPER_N) {
+    // ev: EV_UPPER_N, or EV_LOWER_T / EV_LOWER_C (plain FP64): back substitution
+    // with E(r, c) = A(c, r) (conjugated for EV_LOWER_C) read from A's lower triangle
+    const bool etr = ev_tr(ev);
+    const int amode = etr ? (ev_cj(ev) ? 1 : 2) : 0;
     const int nb = o.nb, P = o.outer / o.nb;
     const int nblk = (m + nb - 1) / nb;
     const int nob = (nblk + P - 1) / P;
@@ -209,7 +213,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             g.kb = safe->kb; g.n_kb = n; g.q_cur = qa; g.q_c = (qb + 1 < nblk) ? qb + 1 : -1;
         }
         if (!mixed) {
-            g.A = U + (long)x0 * ldu + r0; g.lda = ldu;
+            g.A = etr ? U + (long)r0 * ldu + x0 : U + (long)x0 * ldu + r0; g.lda = ldu; g.a_ct = amode;
             g.B = B + x0; g.ldb = ldb;
             g.C = B + r0; g.ldc = ldb;
             if (V) {
@@ -243,7 +247,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             b.safe.omega_log2 = o.omega_log2;
         }
         const double fl = (V ? 8.0 : 4.0) * b.rows * (double)b.rows * n;
-        return timed(MST_PROF_DIAG, fl, st, [&] { return launch_block(false, b, st); });
+        return timed(MST_PROF_DIAG, fl, st, [&] { return launch_block(ev, b, st); });
     };
 
     if (fused && o.overlap && nob > 2) {
@@ -301,7 +305,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             } else {
                 d.safe.omega_log2 = o.omega_log2;
             }
-            hipError_t e = timed(MST_PROF_DIAG, (V ? 8.0 : 4.0) * bs * bs * (double)n, s, [&] { return launch_diag(nb, false, d, s); });
+            hipError_t e = timed(MST_PROF_DIAG, (V ? 8.0 : 4.0) * bs * bs * (double)n, s, [&] { return launch_diag(nb, ev, d, s); });
             if (e != hipSuccess) return e;
             if (q > qa) {
                 GemmArgs g{};
@@ -312,7 +316,8 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
                     g.kb = safe->kb; g.n_kb = n; g.q_cur = q; g.q_c = (q + 1 < nblk) ? q + 1 : -1;
                 }
                 if (!mixed) {
-                    g.A = U + (long)i0 * ldu + qa * nb; g.lda = ldu;
+                    g.A = etr ? U + (long)(qa * nb) * ldu + i0 : U + (long)i0 * ldu + qa * nb;
+                    g.lda = ldu; g.a_ct = amode;
                     g.B = B + i0; g.ldb = ldb;
                     g.C = B + qa * nb; g.ldc = ldb;
                     if (V) {
@@ -348,8 +353,12 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
 }
 
 // ---------------------------------------------------------------- adjoint block loop
+// ev: EV_UPPER_C (the adjoint), EV_UPPER_T, or EV_LOWER_N (E(r, c) = A(r, c) from
+// A's lower triangle): forward substitution, blocks top to bottom
 hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* G, long ldg,
-                        const Opts& o, hipStream_t s) {
+                        const Opts& o, hipStream_t s, int ev = EV_UPPER_C) {
+    const bool etr = ev_tr(ev);
+    const int amode = etr ? (ev_cj(ev) ? 1 : 2) : 0;
     const int nb = o.nb, P = o.outer / o.nb;
     const int nblk = (m + nb - 1) / nb;
     const int nob = (nblk + P - 1) / P;
@@ -363,7 +372,7 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
             b.U = U; b.ldu = ldu; b.lam = lam; b.B = G; b.ldb = ldg;
             b.safe.omega_log2 = o.omega_log2;
             const double fl = 4.0 * b.rows * (double)b.rows * n;
-            hipError_t e = timed(MST_PROF_DIAG, fl, s, [&] { return launch_block(true, b, s); });
+            hipError_t e = timed(MST_PROF_DIAG, fl, s, [&] { return launch_block(ev, b, s); });
             if (e != hipSuccess) return e;
         }
         for (int q = qa; q <= qb && !fused; ++q) {
@@ -373,13 +382,13 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
             d.m = m; d.n = n; d.i0 = i0; d.bs = bs; d.q = q;
             d.U = U; d.ldu = ldu; d.lam = lam; d.B = G; d.ldb = ldg;
             d.safe.omega_log2 = o.omega_log2;
-            hipError_t e = timed(MST_PROF_DIAG, 4.0 * bs * bs * (double)n, s, [&] { return launch_diag(nb, true, d, s); });
+            hipError_t e = timed(MST_PROF_DIAG, 4.0 * bs * bs * (double)n, s, [&] { return launch_diag(nb, ev, d, s); });
             if (e != hipSuccess) return e;
             if (q < qb) {
-                // G(i1:end) -= U(i0:i1, i1:end)^H Y(i0:i1)
+                // G(i1:end) -= E(i1:end, i0:i1) Y(i0:i1), E = U^H for the adjoint
                 GemmArgs g{};
                 g.M = end - i1; g.N = n; g.K = bs; g.op = GOP_SUB; g.staged = o.staged;
-                g.A = U + (long)i1 * ldu + i0; g.lda = ldu; g.a_ct = 1;
+                g.A = etr ? U + (long)i1 * ldu + i0 : U + (long)i0 * ldu + i1; g.lda = ldu; g.a_ct = amode;
                 g.B = G + i0; g.ldb = ldg;
                 g.C = G + i1; g.ldc = ldg;
                 e = timed(MST_PROF_GEMM_F64, gemm_flops(g), s, [&] { return launch_gemm_f64(g, s); });
@@ -390,7 +399,7 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
             const int r0 = qa * nb;
             GemmArgs g{};
             g.M = m - end; g.N = n; g.K = end - r0; g.op = GOP_SUB; g.staged = o.staged;
-            g.A = U + (long)end * ldu + r0; g.lda = ldu; g.a_ct = 1;
+            g.A = etr ? U + (long)end * ldu + r0 : U + (long)r0 * ldu + end; g.lda = ldu; g.a_ct = amode;
             g.B = G + r0; g.ldb = ldg;
             g.C = G + end; g.ldc = ldg;
             hipError_t e = timed(MST_PROF_GEMM_F64, gemm_flops(g), s, [&] { return launch_gemm_f64(g, s); });
@@ -577,6 +586,48 @@ mst_status mstrsm_adjoint(int m, int n, const void* U, int ldu, const void* shif
     if (o.precision != 0) return MST_EUNSUPPORTED;
     if (m == 0 || n == 0) return MST_OK;
     HIPCHK(adjoint_loop(m, n, (const zd*)U, ldu, (const zd*)shifts, (zd*)G, ldg, o, (hipStream_t)stream));
+    return MST_OK;
+}
+
+mst_status mstrsm_op(int side, int uplo, int op, int m, int n, const void* A, int lda, const void* shifts,
+                     void* B, int ldb, const mst_opts* opt, void* stream) {
+    t_bad_arg = 0;
+    if (side != 'L' && side != 'R') return bad(1);
+    if (uplo != 'U' && uplo != 'L') return bad(2);
+    if (op != 'N' && op != 'T' && op != 'C') return bad(3);
+    if (m < 0) return bad(4);
+    if (n < 0) return bad(5);
+    mst_status st;
+    if ((st = check_mat(A, lda, m, n > 0 ? m : 0, 6, 7)) != MST_OK) return st;
+    if (n > 0 && m > 0 && !shifts) return bad(8);
+    if ((st = check_mat(B, ldb, m, n, 9, 10)) != MST_OK) return st;
+    Opts o;
+    if ((st = read_opts(opt, o, 11)) != MST_OK) return st;
+    // right side: x op(A - l I) = b for the row vector x, i.e. op(A - l I)^T x^T = b^T
+    int eop = op;
+    if (side == 'R') {
+        if (op == 'C') return MST_EUNSUPPORTED;
+        eop = (op == 'N') ? 'T' : 'N';
+    }
+    if (o.precision != 0 && !(uplo == 'U' && eop == 'N')) return MST_EUNSUPPORTED;
+    if (m == 0 || n == 0) return MST_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const zd* Az = (const zd*)A;
+    const zd* lz = (const zd*)shifts;
+    zd* Bz = (zd*)B;
+    if (uplo == 'U' && eop == 'N') {
+        Workspace ws(s);
+        return plain_solve(m, n, Az, lda, lz, Bz, ldb, o, s, ws);
+    }
+    int ev;
+    if (uplo == 'U') ev = (eop == 'T') ? EV_UPPER_T : EV_UPPER_C;
+    else ev = (eop == 'N') ? EV_LOWER_N : (eop == 'T') ? EV_LOWER_T : EV_LOWER_C;
+    if (ev_fwd(ev)) {
+        HIPCHK(adjoint_loop(m, n, Az, lda, lz, Bz, ldb, o, s, ev));
+    } else {
+        HIPCHK(forward_loop(m, n, Az, lda, nullptr, 0, lz, Bz, ldb, nullptr, 0, o, nullptr, nullptr, s,
+                            nullptr, 0, ev));
+    }
     return MST_OK;
 }
 

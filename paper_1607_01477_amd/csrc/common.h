@@ -24,10 +24,32 @@ struct SafeState {
     const double* delta_v;
 };
 
+// ---------------------------------------------------------------- solve variants
+// The triangular operator a solve substitutes with: E = op(A) for A upper or
+// lower triangular (the variants of the footnote to Sec. 2). Bits:
+//   1: forward substitution (E lower triangular; otherwise back substitution)
+//   2: E(r, c) = A(c, r) (transposed storage access)
+//   4: conjugated entries (and shifts)
+enum SolveVariant : int {
+    EV_UPPER_N = 0,   // (U - l I) x = b                     back substitution
+    EV_LOWER_N = 1,   // (L - l I) x = b                     forward
+    EV_LOWER_T = 2,   // (L - l I)^T x = b                   back
+    EV_UPPER_T = 3,   // (U - l I)^T x = b                   forward
+    EV_LOWER_C = 6,   // (L - l I)^H x = b                   back
+    EV_UPPER_C = 7,   // (U - l I)^H x = b (the adjoint)     forward
+};
+constexpr bool ev_fwd(int ev) { return (ev & 1) != 0; }
+constexpr bool ev_tr(int ev) { return (ev & 2) != 0; }
+constexpr bool ev_cj(int ev) { return (ev & 4) != 0; }
+// A is lower triangular exactly when the access is transposed for back
+// substitution or direct for forward substitution
+constexpr bool ev_lower_a(int ev) { return ev_tr(ev) != ev_fwd(ev); }
+
 // ---------------------------------------------------------------- diagonal blocks
 // Solves the nb-row diagonal block [i0, i0+bs) for all n shifts in place.
-//   adjoint = false: (U(I1,I1) - lambda_j I) x = b        (back substitution, Alg 1)
-//   adjoint = true : (U(I1,I1) - lambda_j I)^H y = g      (forward substitution)
+//   ev = EV_UPPER_N: (U(I1,I1) - lambda_j I) x = b        (back substitution, Alg 1)
+//   ev = EV_UPPER_C: (U(I1,I1) - lambda_j I)^H y = g      (forward substitution)
+//   other SolveVariant values: the lower and transposed variants (plain FP64 only)
 // safe != nullptr: Alg 4 phase 2 with Alg 5's column bound and decisions, block index q.
 // b32 != nullptr (mixed precision): the right-hand side is read from b32 (FP32),
 // solved in FP64, and written both to B (FP64) and back to b32 (rounded).
@@ -43,7 +65,7 @@ struct DiagArgs {
     SafeState safe;
     int use_safe;
 };
-hipError_t launch_diag(int nb, bool adjoint, const DiagArgs& a, hipStream_t s);
+hipError_t launch_diag(int nb, int ev, const DiagArgs& a, hipStream_t s);
 
 // Whole outer block [iS, iS+rows) (rows <= block_rows_max(), iS a multiple of nb,
 // first diagonal block index qa) for all n shifts: the diagonal blocks in
@@ -62,7 +84,7 @@ struct BlockArgs {
 };
 int block_rows_max();
 bool block_fusable(int nb);   // nb handled by the fused kernel (16 or 32)
-hipError_t launch_block(bool adjoint, const BlockArgs& a, hipStream_t s);
+hipError_t launch_block(int ev, const BlockArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- MFMA GEMM
 // C(M x N) <- epilogue(acc), acc = A(M x K) * B(K x N), complex.
@@ -75,7 +97,8 @@ enum GemmOp : int {
 };
 struct GemmArgs {
     int M, N, K;
-    const void* A; long lda; int a_ct;   // a_ct: A(r,k) = conj(a[r*lda + k]); else a[k*lda + r]
+    const void* A; long lda; int a_ct;   // a_ct: 1 A(r,k) = conj(a[r*lda + k]); 2 a[r*lda + k];
+                                         // 0 a[k*lda + r]
     const void* B; long ldb; int b_ct;   // b_ct: B(k,c) = conj(b[k*ldb + c]); else b[c*ldb + k]
     void* C; long ldc;
     int op;

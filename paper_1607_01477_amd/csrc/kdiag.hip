@@ -129,13 +129,20 @@ __device__ inline double group_max(double v) {
     return v;
 }
 
-// Us[i*NB + r]: coefficient of unknown i in row r of the block system, zero on
-// and outside the triangle that the substitution uses:
-//   forward: U(i0+r, i0+i) for r < i;  adjoint: conj(U(i0+i, i0+r)) for r > i.
-// Ud[r]: the diagonal U(i0+r, i0+r) (conjugated for the adjoint).
+// Us[i*NB + r]: coefficient of unknown i in row r of the block system E, zero
+// on and outside the triangle that the substitution uses (E = op(A) of the
+// variant EV, see ev_fwd / ev_tr / ev_cj):
+//   back substitution (E upper): E(i0+r, i0+i) for r < i;
+//   forward substitution (E lower): E(i0+r, i0+i) for r > i;
+// with E(r, c) = A(r, c), A(c, r) (transposed) or conj(A(c, r)).
+// Ud[r]: the diagonal of E. The element pair (rr <= c) of the loop below is
+// read from A's upper triangle, A(rr, c), when A is upper triangular and from
+// its lower triangle, A(c, rr), when A is lower (EV transposes exactly when the
+// substitution direction differs from A's triangle).
 // All loads of a thread are issued before its LDS stores so their latencies overlap.
-template <int NB, bool ADJ>
+template <int NB, int EV>
 __device__ inline void stage_diag(zd* Us, zd* Ud, const zd* U, long ldu, int i0, int bs) {
+    constexpr bool FWD = ev_fwd(EV), CJ = ev_cj(EV), LOWA = ev_lower_a(EV);
     constexpr int PER = (NB * NB) / kWG;
     zd st[PER];
 #pragma unroll
@@ -143,17 +150,18 @@ __device__ inline void stage_diag(zd* Us, zd* Ud, const zd* U, long ldu, int i0,
         const int t = threadIdx.x + e * kWG;
         const int c = t / NB, rr = t - c * NB;
         st[e] = zd{0.0, 0.0};
-        if (rr <= c && c < bs) st[e] = U[(long)(i0 + c) * ldu + i0 + rr];
+        if (rr <= c && c < bs)
+            st[e] = LOWA ? U[(long)(i0 + rr) * ldu + i0 + c] : U[(long)(i0 + c) * ldu + i0 + rr];
     }
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const int t = threadIdx.x + e * kWG;
         const int c = t / NB, rr = t - c * NB;
-        const zd v = ADJ ? zd{st[e].re, -st[e].im} : st[e];
+        const zd v = CJ ? zd{st[e].re, -st[e].im} : st[e];
         if (rr == c) {
             Ud[rr] = v;
             Us[c * NB + rr] = zd{0.0, 0.0};
-        } else if (!ADJ) {
+        } else if (!FWD) {
             Us[c * NB + rr] = v;
         } else {
             Us[rr * NB + c] = v;
@@ -166,9 +174,11 @@ __device__ inline void stage_diag(zd* Us, zd* Ud, const zd* U, long ldu, int i0,
 // receives the solution; kblk the block's scale exponent (safe variant).
 // GEN: the block of a pencil, U' = U - lambda V per shift (nb = 16, one shift
 // per lane group): pivots and coefficients are formed from both staged blocks.
-template <int NB, int SPW, bool ADJ, bool SAFE, bool GEN = false>
+template <int NB, int SPW, int EV, bool SAFE, bool GEN = false>
 struct BlockSolve {
-    static_assert(!GEN || (NB == 16 && SPW == 1 && !ADJ), "pencil blocks: nb 16, forward");
+    static_assert(!GEN || (NB == 16 && SPW == 1 && EV == 0), "pencil blocks: nb 16, upper, op N");
+    static constexpr bool ADJ = ev_fwd(EV);   // forward substitution (E lower triangular)
+    static constexpr bool CJ = ev_cj(EV);
     double br[SPW], bi[SPW], pr[SPW], pi[SPW], cdl[SPW], Gs[SPW], Ms[SPW];
     int pe[SPW], kblk[SPW];
 
@@ -189,7 +199,7 @@ struct BlockSolve {
                     di = d.im;
                 } else {
                     dr = u.re - lam[s].re;
-                    di = ADJ ? (u.im + lam[s].im) : (u.im - lam[s].im);
+                    di = CJ ? (u.im + lam[s].im) : (u.im - lam[s].im);
                 }
                 if (SAFE && dr == 0.0 && di == 0.0) dr = delta;
             }
@@ -477,16 +487,16 @@ struct BlockSolve {
     }
 };
 
-template <int NB, int SPW, bool ADJ, bool SAFE, bool MIXED, bool VARLEN, bool GEN = false>
+template <int NB, int SPW, int EV, bool SAFE, bool MIXED, bool VARLEN, bool GEN = false>
 __global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
-    static_assert(!GEN || (NB == 16 && !ADJ && !MIXED), "pencil: nb 16, forward, FP64");
+    static_assert(!GEN || (NB == 16 && EV == 0 && !MIXED), "pencil: nb 16, upper, op N, FP64");
     __shared__ zd Us[NB * NB];
     __shared__ zd Ud[NB];
     __shared__ zd Vs[GEN ? NB * NB : 1];
     __shared__ zd Vd[GEN ? NB : 1];
     const int bs = a.bs, i0 = a.i0;
-    stage_diag<NB, ADJ>(Us, Ud, a.U, a.ldu, i0, bs);
-    if (GEN) stage_diag<NB, false>(Vs, Vd, a.V, a.ldv, i0, bs);
+    stage_diag<NB, EV>(Us, Ud, a.U, a.ldu, i0, bs);
+    if (GEN) stage_diag<NB, 0>(Vs, Vd, a.V, a.ldv, i0, bs);
     __syncthreads();
 
     constexpr int G = 64 / NB;
@@ -500,7 +510,7 @@ __global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
     const double delta = SAFE ? (GEN ? fmax(*a.safe.delta, *a.safe.delta_v) : *a.safe.delta) : 0.0;
     const double cn_l = (SAFE && !GEN && r < bs) ? a.safe.cn_in[i0 + r] : 0.0;
 
-    BlockSolve<NB, SPW, ADJ, SAFE, GEN> S;
+    BlockSolve<NB, SPW, EV, SAFE, GEN> S;
     int jj[SPW], Lr[SPW];
     zd lam[SPW];
     bool jv[SPW];
@@ -618,10 +628,12 @@ constexpr int kAW = 4;                 // wavefronts that solve diagonal blocks;
 // GEN: the pencil U - lambda_j V (Alg 8 / Alg 9): the V blocks are staged
 // beside U's, the solving wavefronts form U - lambda V per shift, and the
 // matrix-core update adds V times lambda x to the subtraction of U x.
-template <int NB, bool ADJ, bool SAFE, bool MIXED, bool VARLEN, bool GEN = false>
-__global__ __launch_bounds__(block_threads(NB, ADJ, SAFE, GEN)) void k_block(BlockArgs a) {
+template <int NB, int EV, bool SAFE, bool MIXED, bool VARLEN, bool GEN = false>
+__global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_block(BlockArgs a) {
     static_assert(NB == 16 || NB == 32, "fused outer block: nb 16 or 32");
-    static_assert(!GEN || (NB == 16 && !ADJ && !MIXED), "pencil: nb 16, forward, FP64");
+    static_assert(!GEN || (NB == 16 && EV == 0 && !MIXED), "pencil: nb 16, upper, op N, FP64");
+    constexpr bool ADJ = ev_fwd(EV);          // forward substitution (E lower triangular)
+    constexpr bool TR = ev_tr(EV), CJ = ev_cj(EV), LOWA = ev_lower_a(EV);
     constexpr int G = 64 / NB;
     constexpr int kWGB = block_threads(NB, ADJ, SAFE, GEN);
     constexpr int NWAVE = kWGB / 64;
@@ -754,16 +766,16 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE, GEN)) void k_block(Blo
             if (t < NBB) {
                 const int c = t / NB, rr = t - c * NB;
                 v = rr <= c && c < g.bs;
-                off = v ? (long)(i0 + c) * ld + i0 + rr : off;
+                off = v ? (LOWA ? (long)(i0 + rr) * ld + i0 + c : (long)(i0 + c) * ld + i0 + rr) : off;
             } else if (t < 2 * NBB) {
                 const int t2 = t - NBB;
-                if (!ADJ) {
-                    // coefficient of x_p(k) in row r: U(i0 + r, p0 + k)
+                if (!TR) {
+                    // coefficient of x_p(k) in row r: A(i0 + r, p0 + k)
                     const int k = t2 / NB, r = t2 - k * NB;
                     v = r < g.bs && k < g.bsp;
                     off = v ? (long)(p0 + k) * ld + i0 + r : off;
                 } else {
-                    // adjoint: conj(U(p0 + k, i0 + r)), conjugated at the store
+                    // transposed: A(p0 + k, i0 + r) (conjugated at the store for CJ)
                     const int r = t2 / NB, k = t2 - r * NB;
                     v = r < g.bs && k < g.bsp;
                     off = v ? (long)(i0 + r) * ld + p0 + k : off;
@@ -778,7 +790,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE, GEN)) void k_block(Blo
         for (int e = 0; e < PERS; ++e) {
             const int t0 = tid + e * kWGB;
             zd v = usv[e] ? ust[e] : zd{0.0, 0.0};
-            if (ADJ) v.im = -v.im;
+            if (CJ) v.im = -v.im;
             if (GEN && t0 >= 2 * NBB) {
                 const int t = t0 - 2 * NBB;
                 if (t < NBB) {
@@ -810,7 +822,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE, GEN)) void k_block(Blo
             } else if (t < 2 * NBB) {
                 const int t2 = t - NBB;
                 int k, r;
-                if (!ADJ) {
+                if (!TR) {
                     k = t2 / NB;
                     r = t2 - k * NB;
                 } else {
@@ -862,7 +874,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE, GEN)) void k_block(Blo
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int k = min(ks * 4 + lq, g.bsp - 1);
-            if (!ADJ) dst[ks] = a.U[(long)(iS + g.p0 + k) * a.ldu + iS + arow];
+            if (!TR) dst[ks] = a.U[(long)(iS + g.p0 + k) * a.ldu + iS + arow];
             else dst[ks] = a.U[(long)(iS + arow) * a.ldu + iS + g.p0 + k];
             if constexpr (GEN) dstv[ks] = a.V[(long)(iS + g.p0 + k) * a.ldv + iS + arow];
         }
@@ -893,7 +905,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE, GEN)) void k_block(Blo
 
         if (wave < kAW) {
             // ---- rows of block q: apply x of block p, then back substitution
-            BlockSolve<NB, SPW, ADJ, SAFE, GEN> S;
+            BlockSolve<NB, SPW, EV, SAFE, GEN> S;
             bool act[SPW];
 #pragma unroll
             for (int s = 0; s < SPW; ++s) {
@@ -1017,7 +1029,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE, GEN)) void k_block(Blo
                     const zd xb = Bl[lr * kSP + g.p0 + k];
                     const bool ok = rowok && k < g.bsp;
                     const double ar = ok ? -af[ks].re : 0.0;
-                    const double ai = ok ? (ADJ ? af[ks].im : -af[ks].im) : 0.0;
+                    const double ai = ok ? (CJ ? af[ks].im : -af[ks].im) : 0.0;
                     accR = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb.re, accR, 0, 0, 0);
                     accI = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xb.im, accI, 0, 0, 0);
                     accR2 = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, xb.im, accR2, 0, 0, 0);
@@ -1090,7 +1102,7 @@ __global__ __launch_bounds__(block_threads(NB, ADJ, SAFE, GEN)) void k_block(Blo
     }
 }
 
-template <int NB, int SPW, bool ADJ>
+template <int NB, int SPW, int EV>
 hipError_t launch_nb(const DiagArgs& a, hipStream_t s) {
     constexpr int per_wg = (kWG / 64) * (64 / NB) * SPW;
     const dim3 grid((a.n + per_wg - 1) / per_wg);
@@ -1098,86 +1110,115 @@ hipError_t launch_nb(const DiagArgs& a, hipStream_t s) {
     const bool mixed = a.b32 != nullptr;
     const bool varlen = a.col_len != nullptr;
     if (a.V != nullptr) {
-        if constexpr (NB == 16 && !ADJ) {
+        if constexpr (NB == 16 && EV == EV_UPPER_N) {
             if (mixed || (varlen && !safe)) return hipErrorInvalidValue;
             if (safe && varlen)
-                hipLaunchKernelGGL((k_diag<16, SPW, false, true, false, true, true>), grid, dim3(kWG), 0, s, a);
+                hipLaunchKernelGGL((k_diag<16, SPW, 0, true, false, true, true>), grid, dim3(kWG), 0, s, a);
             else if (safe)
-                hipLaunchKernelGGL((k_diag<16, SPW, false, true, false, false, true>), grid, dim3(kWG), 0, s, a);
+                hipLaunchKernelGGL((k_diag<16, SPW, 0, true, false, false, true>), grid, dim3(kWG), 0, s, a);
             else
-                hipLaunchKernelGGL((k_diag<16, SPW, false, false, false, false, true>), grid, dim3(kWG), 0, s, a);
+                hipLaunchKernelGGL((k_diag<16, SPW, 0, false, false, false, true>), grid, dim3(kWG), 0, s, a);
             return hipGetLastError();
         } else {
             return hipErrorInvalidValue;
         }
     }
-    if (ADJ) {
+    if constexpr (EV != EV_UPPER_N) {
+        // the other variants: plain FP64 solves only
         if (safe || mixed || varlen) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_diag<NB, SPW, true, false, false, false>), grid, dim3(kWG), 0, s, a);
+        hipLaunchKernelGGL((k_diag<NB, SPW, EV, false, false, false>), grid, dim3(kWG), 0, s, a);
     } else if (safe) {
         if (mixed) return hipErrorInvalidValue;
         if (varlen)
-            hipLaunchKernelGGL((k_diag<NB, SPW, false, true, false, true>), grid, dim3(kWG), 0, s, a);
+            hipLaunchKernelGGL((k_diag<NB, SPW, 0, true, false, true>), grid, dim3(kWG), 0, s, a);
         else
-            hipLaunchKernelGGL((k_diag<NB, SPW, false, true, false, false>), grid, dim3(kWG), 0, s, a);
+            hipLaunchKernelGGL((k_diag<NB, SPW, 0, true, false, false>), grid, dim3(kWG), 0, s, a);
     } else {
         if (varlen) return hipErrorInvalidValue;
         if (mixed)
-            hipLaunchKernelGGL((k_diag<NB, SPW, false, false, true, false>), grid, dim3(kWG), 0, s, a);
+            hipLaunchKernelGGL((k_diag<NB, SPW, 0, false, true, false>), grid, dim3(kWG), 0, s, a);
         else
-            hipLaunchKernelGGL((k_diag<NB, SPW, false, false, false, false>), grid, dim3(kWG), 0, s, a);
+            hipLaunchKernelGGL((k_diag<NB, SPW, 0, false, false, false>), grid, dim3(kWG), 0, s, a);
     }
     return hipGetLastError();
 }
 
-template <int NB, bool ADJ>
+template <int NB, int EV>
 hipError_t launch_blk(const BlockArgs& a, hipStream_t s) {
     const dim3 grid((a.n + kCols - 1) / kCols);
     const bool safe = a.use_safe != 0;
     const bool mixed = a.b32 != nullptr;
     const bool varlen = a.col_len != nullptr;
     if (a.V != nullptr) {
-        if constexpr (NB == 16 && !ADJ) {
+        if constexpr (NB == 16 && EV == EV_UPPER_N) {
             if (mixed || (varlen && !safe)) return hipErrorInvalidValue;
             const dim3 blk(block_threads(16, false, safe, true));
             if (safe && varlen)
-                hipLaunchKernelGGL((k_block<16, false, true, false, true, true>), grid, blk, 0, s, a);
+                hipLaunchKernelGGL((k_block<16, 0, true, false, true, true>), grid, blk, 0, s, a);
             else if (safe)
-                hipLaunchKernelGGL((k_block<16, false, true, false, false, true>), grid, blk, 0, s, a);
+                hipLaunchKernelGGL((k_block<16, 0, true, false, false, true>), grid, blk, 0, s, a);
             else
-                hipLaunchKernelGGL((k_block<16, false, false, false, false, true>), grid, blk, 0, s, a);
+                hipLaunchKernelGGL((k_block<16, 0, false, false, false, true>), grid, blk, 0, s, a);
             return hipGetLastError();
         } else {
             return hipErrorInvalidValue;
         }
     }
-    if (ADJ) {
+    if constexpr (EV != EV_UPPER_N) {
+        // the other variants: plain FP64 solves only
         if (safe || mixed || varlen) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_block<NB, true, false, false, false>), grid, dim3(block_threads(NB, true, false)), 0, s, a);
+        hipLaunchKernelGGL((k_block<NB, EV, false, false, false>), grid,
+                           dim3(block_threads(NB, ev_fwd(EV), false)), 0, s, a);
     } else if (safe) {
         if (mixed) return hipErrorInvalidValue;
         if (varlen)
-            hipLaunchKernelGGL((k_block<NB, false, true, false, true>), grid, dim3(block_threads(NB, false, true)), 0, s, a);
+            hipLaunchKernelGGL((k_block<NB, 0, true, false, true>), grid, dim3(block_threads(NB, false, true)), 0, s, a);
         else
-            hipLaunchKernelGGL((k_block<NB, false, true, false, false>), grid, dim3(block_threads(NB, false, true)), 0, s, a);
+            hipLaunchKernelGGL((k_block<NB, 0, true, false, false>), grid, dim3(block_threads(NB, false, true)), 0, s, a);
     } else {
         if (varlen) return hipErrorInvalidValue;
         if (mixed)
-            hipLaunchKernelGGL((k_block<NB, false, false, true, false>), grid, dim3(block_threads(NB, false, false)), 0, s, a);
+            hipLaunchKernelGGL((k_block<NB, 0, false, true, false>), grid, dim3(block_threads(NB, false, false)), 0, s, a);
         else
-            hipLaunchKernelGGL((k_block<NB, false, false, false, false>), grid, dim3(block_threads(NB, false, false)), 0, s, a);
+            hipLaunchKernelGGL((k_block<NB, 0, false, false, false>), grid, dim3(block_threads(NB, false, false)), 0, s, a);
     }
     return hipGetLastError();
 }
 
+template <int NB, int SPW>
+hipError_t launch_nb_ev(int ev, const DiagArgs& a, hipStream_t s) {
+    switch (ev) {
+        case EV_UPPER_N: return launch_nb<NB, SPW, EV_UPPER_N>(a, s);
+        case EV_UPPER_C: return launch_nb<NB, SPW, EV_UPPER_C>(a, s);
+        case EV_UPPER_T: return launch_nb<NB, SPW, EV_UPPER_T>(a, s);
+        case EV_LOWER_N: return launch_nb<NB, SPW, EV_LOWER_N>(a, s);
+        case EV_LOWER_T: return launch_nb<NB, SPW, EV_LOWER_T>(a, s);
+        case EV_LOWER_C: return launch_nb<NB, SPW, EV_LOWER_C>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int NB>
+hipError_t launch_blk_ev(int ev, const BlockArgs& a, hipStream_t s) {
+    switch (ev) {
+        case EV_UPPER_N: return launch_blk<NB, EV_UPPER_N>(a, s);
+        case EV_UPPER_C: return launch_blk<NB, EV_UPPER_C>(a, s);
+        case EV_UPPER_T: return launch_blk<NB, EV_UPPER_T>(a, s);
+        case EV_LOWER_N: return launch_blk<NB, EV_LOWER_N>(a, s);
+        case EV_LOWER_T: return launch_blk<NB, EV_LOWER_T>(a, s);
+        case EV_LOWER_C: return launch_blk<NB, EV_LOWER_C>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
-hipError_t launch_diag(int nb, bool adjoint, const DiagArgs& a, hipStream_t s) {
+hipError_t launch_diag(int nb, int ev, const DiagArgs& a, hipStream_t s) {
     if (a.bs <= 0 || a.bs > nb || a.n <= 0) return hipErrorInvalidValue;
     switch (nb) {
-        case 64: return adjoint ? launch_nb<64, 4, true>(a, s) : launch_nb<64, 4, false>(a, s);
-        case 32: return adjoint ? launch_nb<32, 2, true>(a, s) : launch_nb<32, 2, false>(a, s);
-        case 16: return adjoint ? launch_nb<16, 1, true>(a, s) : launch_nb<16, 1, false>(a, s);
+        case 64: return launch_nb_ev<64, 4>(ev, a, s);
+        case 32: return launch_nb_ev<32, 2>(ev, a, s);
+        case 16: return launch_nb_ev<16, 1>(ev, a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1186,11 +1227,11 @@ int block_rows_max() { return kRowsMax; }
 
 bool block_fusable(int nb) { return nb == 16 || nb == 32; }
 
-hipError_t launch_block(bool adjoint, const BlockArgs& a, hipStream_t s) {
+hipError_t launch_block(int ev, const BlockArgs& a, hipStream_t s) {
     if (a.rows <= 0 || a.rows > kRowsMax || a.n <= 0 || a.iS % a.nb) return hipErrorInvalidValue;
     switch (a.nb) {
-        case 32: return adjoint ? launch_blk<32, true>(a, s) : launch_blk<32, false>(a, s);
-        case 16: return adjoint ? launch_blk<16, true>(a, s) : launch_blk<16, false>(a, s);
+        case 32: return launch_blk_ev<32>(ev, a, s);
+        case 16: return launch_blk_ev<16>(ev, a, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -344,15 +344,18 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(GemmArgs g) {
 // and no workgroup barrier are needed and each wavefront keeps its matrix pipe
 // fed on its own. The 4 wavefronts of a workgroup cover a 64 x 64 tile and
 // share A rows / B columns through L1.
-template <typename T, int DEPTH, int OP, bool A_CT, bool SAFE, bool VARLEN>
+// AM: A operand access: 0 plain A(r,k) = a[k*lda + r]; 1 conjugate transpose
+// A(r,k) = conj(a[r*lda + k]); 2 transpose A(r,k) = a[r*lda + k].
+template <typename T, int DEPTH, int OP, int AM, bool SAFE, bool VARLEN>
 __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
+    constexpr bool A_TR = AM != 0, A_CJ = AM == 1;
     static_assert(OP == GOP_SUB || OP == GOP_NEG_TRIU || OP == GOP_RESID || OP == GOP_GEN_SUB ||
                       OP == GOP_TRMM,
                   "direct GEMM op");
-    static_assert(OP == GOP_SUB || OP == GOP_GEN_SUB || (!A_CT && !SAFE && !VARLEN),
+    static_assert(OP == GOP_SUB || OP == GOP_GEN_SUB || (!A_TR && !SAFE && !VARLEN),
                   "triangular products: plain A only");
-    static_assert(OP != GOP_GEN_SUB || (sizeof(T) == 8 && !A_CT), "pencil substitution: FP64, plain A");
-    static_assert(sizeof(T) == 8 || (OP == GOP_SUB && !A_CT && !SAFE && !VARLEN),
+    static_assert(OP != GOP_GEN_SUB || (sizeof(T) == 8 && !A_TR), "pencil substitution: FP64, plain A");
+    static_assert(sizeof(T) == 8 || (OP == GOP_SUB && !A_TR && !SAFE && !VARLEN),
                   "FP32: plain substitution only");
     constexpr bool TRI = OP == GOP_NEG_TRIU;
     constexpr bool RES = OP == GOP_RESID;
@@ -516,7 +519,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 // stay inside U's upper triangle: below it the element is never used
                 a0 = A[(long)max(k, ra0) * lda + ra0];
                 a1 = A[(long)max(k, ra1) * lda + ra1];
-            } else if (!A_CT) {
+            } else if (!A_TR) {
                 const CT* ap = A + (long)k * lda;
                 a0 = ap[ra0];
                 a1 = ap[ra1];
@@ -562,15 +565,15 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 b1.re = ldexp(b1.re, e1 - kq1); b1.im = ldexp(b1.im, e1 - kq1);
             }
             if constexpr (sizeof(T) == 8) {
-                // acc -= A' B' with A' = conj(A) for A_CT, B' = conj(B) for TRI.
+                // acc -= A' B' with A' = conj(A) for A_CJ, B' = conj(B) for TRI.
                 // FP64: every sign is an MFMA source modifier (the last operand's
                 // bit 0 negates A), so the loop spends no VALU on negation:
                 //   Re -= ar br - a'i b'i,  Im -= ar b'i + a'i br
                 // (TRM: acc += A B, i.e. Re += ar br - ai bi, Im += ar bi + ai br)
                 constexpr int NRR = TRM ? 0 : 1;
-                constexpr int NII = TRM ? 1 : ((A_CT != TRI) ? 1 : 0);   // + sa sb ai bi
+                constexpr int NII = TRM ? 1 : ((A_CJ != TRI) ? 1 : 0);   // + sa sb ai bi
                 constexpr int NRI = (TRI || TRM) ? 0 : 1;               // - sb ar bi
-                constexpr int NIR = (A_CT || TRM) ? 0 : 1;              // - sa ai br
+                constexpr int NIR = (A_CJ || TRM) ? 0 : 1;              // - sa ai br
                 accR[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.re, b0.re, accR[0][0], 0, 0, NRR);
                 accR[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.re, b1.re, accR[0][1], 0, 0, NRR);
                 accR[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.re, b0.re, accR[1][0], 0, 0, NRR);
@@ -615,9 +618,9 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             // per refill, so the loop spends one address add per operand
             // instead of recomputing products; the main loop runs while every
             // refill lies inside K, a short guarded tail drains the ring.
-            const long sA = A_CT ? 4 : 4L * lda, sB = TRI ? 4L * g.ldb : 4;
-            const CT* qa0 = A_CT ? A + (long)ra0 * lda + lq : A + (long)lq * lda + ra0;
-            const CT* qa1 = A_CT ? A + (long)ra1 * lda + lq : qa0 + 16;
+            const long sA = A_TR ? 4 : 4L * lda, sB = TRI ? 4L * g.ldb : 4;
+            const CT* qa0 = A_TR ? A + (long)ra0 * lda + lq : A + (long)lq * lda + ra0;
+            const CT* qa1 = A_TR ? A + (long)ra1 * lda + lq : qa0 + 16;
             const CT* qb0 = TRI ? B + (long)lq * g.ldb + cb0 : B + (long)cb0 * g.ldb + lq;
             const CT* qb1 = TRI ? qb0 + 16 : B + (long)cb1 * g.ldb + lq;
             auto next = [&](CT& a0, CT& a1, CT& b0, CT& b1) __attribute__((always_inline)) {
@@ -747,10 +750,10 @@ hipError_t go(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T, int OP, bool A_CT, bool SAFE, bool VARLEN>
+template <typename T, int OP, int AM, bool SAFE, bool VARLEN>
 hipError_t go_direct(const GemmArgs& g, hipStream_t s) {
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
-    hipLaunchKernelGGL((k_gemm_direct<T, 4, OP, A_CT, SAFE, VARLEN>), dim3(TM * TN), dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((k_gemm_direct<T, 4, OP, AM, SAFE, VARLEN>), dim3(TM * TN), dim3(NT), 0, s, g);
     return hipGetLastError();
 }
 
@@ -762,11 +765,15 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
     const bool varlen = g.col_len != nullptr;
     switch (g.op) {
         case GOP_SUB:
-            if (g.b_ct) return hipErrorInvalidValue;
+            if (g.b_ct || g.a_ct < 0 || g.a_ct > 2) return hipErrorInvalidValue;
+            if (g.a_ct == 2) {
+                if (safe || varlen || g.staged) return hipErrorInvalidValue;
+                return go_direct<double, GOP_SUB, 2, false, false>(g, s);
+            }
             if (g.a_ct) {
                 if (safe || varlen) return hipErrorInvalidValue;
                 if (g.staged) return go<double, true, false, GOP_SUB, false, false>(g, s);
-                return go_direct<double, GOP_SUB, true, false, false>(g, s);
+                return go_direct<double, GOP_SUB, 1, false, false>(g, s);
             }
             if (g.staged) {
                 if (safe && varlen) return go<double, false, false, GOP_SUB, true, true>(g, s);
@@ -774,28 +781,28 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
                 if (varlen) return hipErrorInvalidValue;
                 return go<double, false, false, GOP_SUB, false, false>(g, s);
             }
-            if (safe && varlen) return go_direct<double, GOP_SUB, false, true, true>(g, s);
-            if (safe) return go_direct<double, GOP_SUB, false, true, false>(g, s);
+            if (safe && varlen) return go_direct<double, GOP_SUB, 0, true, true>(g, s);
+            if (safe) return go_direct<double, GOP_SUB, 0, true, false>(g, s);
             if (varlen) return hipErrorInvalidValue;
-            return go_direct<double, GOP_SUB, false, false, false>(g, s);
+            return go_direct<double, GOP_SUB, 0, false, false>(g, s);
         case GOP_RESID:
             if (g.a_ct || g.b_ct || safe || varlen) return hipErrorInvalidValue;
             if (g.staged) return go<double, false, false, GOP_RESID, false, false>(g, s);
-            return go_direct<double, GOP_RESID, false, false, false>(g, s);
+            return go_direct<double, GOP_RESID, 0, false, false>(g, s);
         case GOP_GEN_SUB:
             if (g.a_ct || g.b_ct || !g.A2 || !g.glam || g.staged) return hipErrorInvalidValue;
-            if (safe && varlen) return go_direct<double, GOP_GEN_SUB, false, true, true>(g, s);
-            if (safe) return go_direct<double, GOP_GEN_SUB, false, true, false>(g, s);
+            if (safe && varlen) return go_direct<double, GOP_GEN_SUB, 0, true, true>(g, s);
+            if (safe) return go_direct<double, GOP_GEN_SUB, 0, true, false>(g, s);
             if (varlen) return hipErrorInvalidValue;
-            return go_direct<double, GOP_GEN_SUB, false, false, false>(g, s);
+            return go_direct<double, GOP_GEN_SUB, 0, false, false>(g, s);
         case GOP_TRMM:
             if (g.a_ct || g.b_ct || safe || varlen || g.staged) return hipErrorInvalidValue;
-            return go_direct<double, GOP_TRMM, false, false, false>(g, s);
+            return go_direct<double, GOP_TRMM, 0, false, false>(g, s);
         case GOP_NEG_TRIU:
             if (g.a_ct || !g.b_ct || safe || varlen) return hipErrorInvalidValue;
             if (g.staged) return go<double, false, true, GOP_NEG_TRIU, false, false>(g, s);
             if (g.M != g.N) return hipErrorInvalidValue;
-            return go_direct<double, GOP_NEG_TRIU, false, false, false>(g, s);
+            return go_direct<double, GOP_NEG_TRIU, 0, false, false>(g, s);
         default:
             return hipErrorInvalidValue;
     }
@@ -806,7 +813,7 @@ hipError_t launch_gemm_f32(const GemmArgs& g, hipStream_t s) {
     if (g.op != GOP_SUB || g.a_ct || g.b_ct || g.kb != nullptr || g.col_len != nullptr)
         return hipErrorInvalidValue;
     if (g.staged) return go<float, false, false, GOP_SUB, false, false>(g, s);
-    return go_direct<float, GOP_SUB, false, false, false>(g, s);
+    return go_direct<float, GOP_SUB, 0, false, false>(g, s);
 }
 
 }  // namespace mst

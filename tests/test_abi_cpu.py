@@ -68,3 +68,24 @@ def test_generalized_argument_errors_without_gpu():
     assert lib.mstrsm_gen(3, 2, fake, 3, fake, 3, fake, fake, 3, ctypes.byref(o), None) == \
         _lib.MST_EUNSUPPORTED
     assert lib.mstrsm_gen(0, 5, None, 1, None, 1, None, None, 1, None, None) == _lib.MST_OK
+
+
+def test_variant_argument_errors_without_gpu():
+    from paper_1607_01477_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(4096)
+    assert lib.mstrsm_op(ord("X"), ord("U"), ord("N"), 3, 2, fake, 3, fake, fake, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 1
+    assert lib.mstrsm_op(ord("L"), ord("Q"), ord("N"), 3, 2, fake, 3, fake, fake, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 2
+    assert lib.mstrsm_op(ord("L"), ord("U"), ord("H"), 3, 2, fake, 3, fake, fake, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 3
+    assert lib.mstrsm_op(ord("L"), ord("L"), ord("T"), 3, 2, fake, 2, fake, fake, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 7
+    # right side with the conjugate transpose is not offered
+    assert lib.mstrsm_op(ord("R"), ord("U"), ord("C"), 3, 2, fake, 3, fake, fake, 3, None, None) == \
+        _lib.MST_EUNSUPPORTED
+    o = _lib.MstOpts()
+    o.precision = 1
+    assert lib.mstrsm_op(ord("L"), ord("L"), ord("N"), 3, 2, fake, 3, fake, fake, 3, ctypes.byref(o), None) == \
+        _lib.MST_EUNSUPPORTED
