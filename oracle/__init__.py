@@ -27,6 +27,7 @@ What each function follows (T. Moon, J. Poulson, arXiv 1607.01477):
   GeneralizedEig (Alg 10) after the (generalized) Schur decomposition: the
   back-transformation X = Q Z (resp. P Z), a library matmul, and columns
   scaled to unit 2-norm.
+* :func:`portrait_grid` — the grid of the automatic pseudospectra window.
 * :func:`lanczos_sigma_min` — second stage of the Van Loan/Lui method, Alg 7
   (Sec. 5): Lanczos on ``(U - zI)^{-H}(U - zI)^{-1}``.
 
@@ -303,6 +304,26 @@ def gen_eig_schur(T, S, P, nb: int = 64, omega_log2: int = OMEGA_LOG2):
     return lam, _unit_columns(_cm(P) @ Z)
 
 
+def portrait_grid(eigs, nx: int, ny: int, pad: float = 0.2, min_side: float = 1e-2):
+    """Grid of a spectral portrait (the automatic window of the pseudospectra
+    driver): the square around the eigenvalues' bounding box, side
+    (1 + 2 pad) max(re span, im span), at least min_side max(1, max|lambda|),
+    nx x ny points with endpoints, point (ix, iy) at index iy nx + ix."""
+    ev = np.asarray(eigs, dtype=np.complex128)
+    re0, re1 = float(np.min(ev.real)), float(np.max(ev.real))
+    im0, im1 = float(np.min(ev.imag)), float(np.max(ev.imag))
+    side = (1.0 + 2.0 * pad) * max(re1 - re0, im1 - im0)
+    side = max(side, min_side * max(1.0, float(np.max(np.abs(ev)))))
+    cx, cy = (re0 + re1) / 2.0, (im0 + im1) / 2.0
+    pts = np.empty(nx * ny, dtype=np.complex128)
+    for iy in range(ny):
+        y = cy - side / 2.0 + side * (iy / (ny - 1) if ny > 1 else 0.5)
+        for ix in range(nx):
+            x = cx - side / 2.0 + side * (ix / (nx - 1) if nx > 1 else 0.5)
+            pts[iy * nx + ix] = complex(x, y)
+    return pts
+
+
 def relative_residual(U, lam, X, B, k=None, cols=None) -> np.ndarray:
     """Per column ||(U - lam_j I) x_j - 2^-k_j b_j||_inf / (||U - lam_j I||_inf ||x_j||_inf)
     with the true modulus; absolute residual where x_j = 0."""
@@ -381,6 +402,7 @@ def lanczos_sigma_min(U, z, V0, iters: int = 15):
 
 __all__ = ["build", "solve", "solve_safe", "solve_adjoint", "gradient", "triang_eig",
            "solve_gen", "solve_safe_gen", "gen_triang_eig", "eig_schur", "gen_eig_schur", "solve_op",
+           "portrait_grid",
            "relative_residual", "lanczos_sigma_min", "num_threads", "set_num_threads",
            "OMEGA_LOG2"]
 
