@@ -393,27 +393,59 @@ class MultiShiftSolve(torch.autograd.Function):
     dL/dRe z + i dL/dIm z, as torch uses for complex tensors)."""
 
     @staticmethod
-    def forward(ctx, U, shifts, B, nb, outer_nb, precision, max_sweeps):
+    def forward(ctx, U, shifts, B, nb, outer_nb, precision, max_sweeps, recompute):
         X = _fcopy(B)
         mstrsm(U, shifts, X, nb=nb, outer_nb=outer_nb, precision=precision, max_sweeps=max_sweeps)
-        ctx.save_for_backward(U, shifts, X)
         ctx.nb, ctx.outer_nb = nb, outer_nb
+        ctx.precision, ctx.max_sweeps = precision, max_sweeps
+        ctx.recompute = int(recompute)
+        if ctx.recompute > 0:
+            # X is not kept: the backward pass solves again, recompute columns at a time
+            ctx.save_for_backward(U, shifts, B)
+        else:
+            ctx.save_for_backward(U, shifts, X)
         return X
 
     @staticmethod
     def backward(ctx, gX):
-        U, shifts, X = ctx.saved_tensors
-        Y = _fcopy(gX)
-        mstrsm_adjoint(U, shifts, Y, nb=ctx.nb, outer_nb=ctx.outer_nb)
-        gU = grad_u(Y, X) if ctx.needs_input_grad[0] else None
-        gs = grad_shift(X, Y) if ctx.needs_input_grad[1] else None
-        gB = Y if ctx.needs_input_grad[2] else None
-        return gU, gs, gB, None, None, None, None
+        if ctx.recompute <= 0:
+            U, shifts, X = ctx.saved_tensors
+            Y = _fcopy(gX)
+            mstrsm_adjoint(U, shifts, Y, nb=ctx.nb, outer_nb=ctx.outer_nb)
+            gU = grad_u(Y, X) if ctx.needs_input_grad[0] else None
+            gs = grad_shift(X, Y) if ctx.needs_input_grad[1] else None
+            gB = Y if ctx.needs_input_grad[2] else None
+            return gU, gs, gB, None, None, None, None, None
+        U, shifts, B = ctx.saved_tensors
+        n = B.shape[1]
+        gU = None
+        gs = torch.empty(n, dtype=torch.complex128, device=B.device) if ctx.needs_input_grad[1] else None
+        gB = torch.empty_strided(B.shape, (1, max(1, B.shape[0])), dtype=torch.complex128,
+                                 device=B.device) if ctx.needs_input_grad[2] else None
+        for c0 in range(0, n, ctx.recompute):
+            c1 = min(n, c0 + ctx.recompute)
+            sc = shifts[c0:c1].contiguous()
+            Xc = _fcopy(B[:, c0:c1])
+            mstrsm(U, sc, Xc, nb=ctx.nb, outer_nb=ctx.outer_nb, precision=ctx.precision,
+                   max_sweeps=ctx.max_sweeps)
+            Yc = _fcopy(gX[:, c0:c1])
+            mstrsm_adjoint(U, sc, Yc, nb=ctx.nb, outer_nb=ctx.outer_nb)
+            if ctx.needs_input_grad[0]:
+                g = grad_u(Yc, Xc)
+                gU = g if gU is None else gU.add_(g)
+            if gs is not None:
+                gs[c0:c1] = grad_shift(Xc, Yc)
+            if gB is not None:
+                gB[:, c0:c1] = Yc
+        return gU, gs, gB, None, None, None, None, None
 
 
-def solve(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2):
-    """Differentiable multi-shift solve (see MultiShiftSolve)."""
-    return MultiShiftSolve.apply(U, shifts, B, nb, outer_nb, precision, max_sweeps)
+def solve(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2, recompute=0):
+    """Differentiable multi-shift solve (see MultiShiftSolve). recompute > 0:
+    X is not stored for the backward pass; it is solved again there, that many
+    columns at a time, so the backward pass holds two m x recompute blocks
+    instead of the m x n solution."""
+    return MultiShiftSolve.apply(U, shifts, B, nb, outer_nb, precision, max_sweeps, recompute)
 
 
 class profile:

@@ -290,6 +290,27 @@ def test_autograd_matches_oracle_gradient(P, oracle_mod):
     np.testing.assert_allclose(host(U.grad), gU, rtol=0, atol=1e-11 * np.abs(gU).max())
 
 
+@pytest.mark.parametrize("chunk", [7, 64, 1000])
+def test_autograd_recompute_matches(P, oracle_mod, chunk):
+    # X recomputed in the backward pass, chunk columns at a time: the same
+    # gradients (gB, gshift column by column bit for bit; gU summed over chunks)
+    import torch
+    w = W.c5_adjoint(m=300, n=130)
+    Wt = torch.from_numpy(w.extra["W"]).cuda()
+    grads = []
+    for rc in (0, chunk):
+        U = dev(w.U).requires_grad_(True)
+        s = dev(w.shifts).requires_grad_(True)
+        B = dev(w.B).requires_grad_(True)
+        X = P.solve(U, s, B, recompute=rc)
+        (Wt * X.abs() ** 2).sum().backward()
+        grads.append((host(U.grad), host(s.grad), host(B.grad)))
+    (gU0, gs0, gB0), (gU1, gs1, gB1) = grads
+    assert np.array_equal(gB0, gB1) and np.array_equal(gs0, gs1)
+    np.testing.assert_allclose(gU1, gU0, rtol=0, atol=1e-13 * np.abs(gU0).max())
+    assert np.all(np.tril(gU1, -1) == 0)
+
+
 def test_autograd_finite_differences(P):
     import torch
     w = W.c5_adjoint(m=40, n=7)
