@@ -16,11 +16,13 @@ Also reported on the same line:
   secondary     the FP32-GEMM + FP64-refinement form of the same solve, its
                 time to FP64 accuracy and its error against the FP64 result.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload solve|pencil]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload solve|pencil|safe|triang_eig]
 
 --workload pencil times the generalized solve (U - l_j V) X = B (appendix,
-Alg 8) at the same size instead (8 m^2 n flops per solve), with its own
-roofline and CPU-oracle lines and no secondary measurements.
+Alg 8) at the same size instead (8 m^2 n flops per solve); safe the safe
+solve of the same inputs; triang_eig the triangular eigenvectors at m = 2048
+(sum 4 j^2 flops). Each has its own roofline and CPU-oracle lines and no
+secondary measurements.
 """
 from __future__ import annotations
 
@@ -44,6 +46,8 @@ GEMM_TRAFFIC = {"kgemm_sha1": "1b3e4341a23b55e1", "bytes_per_launch": 295.0e6, "
 PEAK_FP32_MFMA_TF = 157.3
 METRIC = "complex128 multi-shift solve GFLOP/s at m=n=4096 and % of MFMA peak vs plain FP64"
 METRIC_PENCIL = "complex128 generalized multi-shift solve GFLOP/s (8 m^2 n) at m=n=4096"
+METRIC_SAFE = "complex128 safe multi-shift solve GFLOP/s at m=n=4096"
+METRIC_TEIG = "complex128 triangular eigenvectors GFLOP/s (sum 4 j^2) at m=2048"
 
 
 def log(*a):
@@ -206,10 +210,12 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["solve", "pencil"], default="solve",
+    ap.add_argument("--workload", choices=["solve", "pencil", "safe", "triang_eig"], default="solve",
                     help="solve: (U - l_j I) X = B, the headline; pencil: the generalized "
-                         "solve (U - l_j V) X = B at the same size (8 m^2 n flops), without "
-                         "the secondary measurements")
+                         "solve (U - l_j V) X = B at the same size (8 m^2 n flops); safe: the "
+                         "safe solve of the headline inputs; triang_eig: triangular "
+                         "eigenvectors at m = 2048 (sum 4 j^2 flops). The last three "
+                         "without the secondary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 4 device copies of 512 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -233,25 +239,45 @@ def main() -> int:
     import paper_1607_01477_amd as P
     import workloads as W
 
-    m, n = args.m, args.n
     pencil = args.workload == "pencil"
-    if pencil:
+    safe = args.workload == "safe"
+    teig = args.workload == "triang_eig"
+    if args.workload != "solve":
         args.no_secondary = True
+    if pencil:
         args.nb = 16
+    if teig:
+        args.m = args.n = min(args.m, 2048)
+    m, n = args.m, args.n
     t_gen = time.perf_counter()
-    w = W.c6_generalized(m=m, n=n) if pencil else W.c3_mixed(m=m, n=n)
+    if pencil:
+        w = W.c6_generalized(m=m, n=n)
+    elif teig:
+        w = W.c2_triang_eig(m=m)
+    else:
+        w = W.c3_mixed(m=m, n=n)
     log("inputs generated in %.1fs" % (time.perf_counter() - t_gen))
     torch.cuda.set_device(0)
     U = dev(w.U, torch)
     lam = torch.from_numpy(w.shifts).cuda()
     B0 = dev(w.B, torch)
     flops = (8.0 if pencil else 4.0) * m * m * n
+    if teig:
+        flops = W.nominal_flops(m, m, w.col_len)
     opts = dict(nb=args.nb, outer_nb=args.outer_nb)
+    teig_out = {}
     if pencil:
         Vd = dev(w.extra["V"], torch)
 
         def solve(X):
             return P.mstrsm_gen(U, Vd, lam, X, outer_nb=args.outer_nb)
+    elif safe:
+        def solve(X):
+            return P.mstrsm_safe(U, lam, X, **opts)
+    elif teig:
+        def solve(X):
+            # X: unused placeholder (the eigenvector matrix is allocated by the call)
+            teig_out["r"] = P.triang_eig(U, **opts)
     else:
         def solve(X):
             return P.mstrsm(U, lam, X, **opts)
@@ -278,10 +304,14 @@ def main() -> int:
     log("%s FP64: %.3f ms/solve, %.1f GFLOP/s" % (args.workload, ms_per_step, gflops))
 
     # accuracy of the timed result on sampled columns (true-modulus backward error)
-    Xh = Xs[-1].cpu().numpy()
+    Xh = teig_out["r"][1].cpu().numpy() if teig else Xs[-1].cpu().numpy()
     cols = np.arange(0, n, max(1, n // 16))
     Ut = np.triu(w.U)
-    if pencil:
+    if teig:
+        ev = teig_out["r"][0].cpu().numpy()
+        R = Ut @ Xh[:, cols] - Xh[:, cols] * ev[cols][None, :]
+        nrm = np.full(len(cols), np.abs(Ut).sum(1).max())
+    elif pencil:
         Vt = np.triu(w.extra["V"])
         R = Ut @ Xh[:, cols] - (Vt @ Xh[:, cols]) * w.shifts[cols][None, :] - w.B[:, cols]
         nrm = np.array([np.abs(Ut - w.shifts[j] * Vt).sum(1).max() for j in cols])
@@ -322,7 +352,7 @@ def main() -> int:
     }
 
     line = {
-        "metric": METRIC_PENCIL if pencil else METRIC,
+        "metric": {"pencil": METRIC_PENCIL, "safe": METRIC_SAFE, "triang_eig": METRIC_TEIG}.get(args.workload, METRIC),
         "value": round(gflops, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -337,8 +367,11 @@ def main() -> int:
         "config": {"workload": ("complex128 generalized multi-shift solve (U - l_j V) X = B, FP64, "
                                 "m=%d n=%d shifts (annulus-diagonal U, V diagonal in [0.5, 1.5], "
                                 "shifts in disk r=0.2), inputs resident in HBM" % (m, n)) if pencil else
-                               ("complex128 multi-shift solve, plain FP64, m=%d n=%d shifts (annulus-"
-                                "diagonal U, shifts in disk r=0.4), inputs resident in HBM" % (m, n)),
+                               ("complex128 triangular eigenvectors (safe solve, variable-length "
+                                "columns), m=%d, CN(0,1) entries with 5%% repeated eigenvalues" % m) if teig else
+                               ("complex128 multi-shift solve, %s FP64, m=%d n=%d shifts (annulus-"
+                                "diagonal U, shifts in disk r=0.4), inputs resident in HBM"
+                                % ("safe" if safe else "plain", m, n)),
                    "m": m, "n": n, "nb": args.nb, "outer_nb": args.outer_nb},
         "pct_fp64_mfma_peak": round(100.0 * gflops / 1e3 / PEAK_FP64_MFMA_TF, 2),
         "max_rel_residual_sampled": resid,
@@ -428,10 +461,21 @@ def main() -> int:
         if pencil:
             def osolve(k):
                 return oracle.solve_gen(w.U, w.extra["V"], w.shifts[:k], w.B[:, :k])
+        elif safe:
+            def osolve(k):
+                return oracle.solve_safe(w.U, w.shifts[:k], w.B[:, :k], nb=args.nb)
+        elif teig:
+            def osolve(k):
+                # the last k columns (the longest ones)
+                sl = slice(n - k, n)
+                return oracle.solve_safe(w.U, w.shifts[sl], w.B[:, sl], col_len=w.col_len[sl], nb=args.nb)
         else:
             def osolve(k):
                 return oracle.solve(w.U, w.shifts[:k], w.B[:, :k])
         fpc = flops / n   # flops per shift
+
+        def oflops(k):
+            return W.nominal_flops(m, k, w.col_len[n - k:]) if teig else fpc * k
         probe = min(n, 2 * cores)
         t0 = time.perf_counter()
         osolve(probe)
@@ -441,7 +485,7 @@ def main() -> int:
         t0 = time.perf_counter()
         osolve(ncols)
         tc = time.perf_counter() - t0
-        cg = fpc * ncols / tc / 1e9
+        cg = oflops(ncols) / tc / 1e9
         used = oracle.num_threads()
         # the same oracle on one thread, a smaller sample
         oracle.set_num_threads(1)
@@ -453,7 +497,7 @@ def main() -> int:
         line["cpu_baseline"] = {"value": round(cg, 3), "unit": "GFLOP/s", "cores": used,
                                 "kind": "oracle",
                                 "sample": "%d of %d shifts of the m=%d workload (%.1f s)" % (ncols, n, m, tc),
-                                "one_thread": {"value": round(fpc * n1 / t1 / 1e9, 3),
+                                "one_thread": {"value": round(oflops(n1) / t1 / 1e9, 3),
                                                "sample": "%d shifts (%.1f s)" % (n1, t1)}}
         log("cpu oracle: %d cols in %.1fs = %.2f GFLOP/s on %d threads" % (ncols, tc, cg, cores))
 
