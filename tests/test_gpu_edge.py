@@ -1,0 +1,80 @@
+"""Edge cases and full-size checks across the entry points (GPU): empty
+problems leave every buffer untouched; the default launch configuration of the
+triangular eigenvectors and of the safe solve at the benchmark size against
+the oracle with the same decision block size."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import announce, colerr, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1607_01477_amd as P
+    P._lib.load()
+    return P
+
+
+def test_empty_problems_touch_nothing(P):
+    import torch
+    lib = P._lib.load()
+    s = P._stream()
+    B = dev(W.cnormal(W.rng(1), (5, 3)))
+    keep = host(B).copy()
+    U = dev(W.random_upper(W.rng(2), 5, 1.0, np.ones(5)))
+    lam = dev(np.zeros(3, dtype=np.complex128))
+    p = P._p
+    # n = 0: nothing is read or written
+    assert lib.mstrsm(5, 0, p(U), 5, p(lam), p(B), 5, None, s) == 0
+    assert lib.mstrsm_adjoint(5, 0, p(U), 5, p(lam), p(B), 5, None, s) == 0
+    assert lib.mstrsm_gen(5, 0, p(U), 5, p(U), 5, p(lam), p(B), 5, None, s) == 0
+    assert lib.mstrsm_op(ord("L"), ord("L"), ord("N"), 5, 0, p(U), 5, p(lam), p(B), 5, None, s) == 0
+    # m = 0
+    assert lib.mstrsm(0, 3, None, 1, p(lam), None, 1, None, s) == 0
+    assert lib.mst_triang_eig(0, None, 1, None, 1, None, None, None, s) == 0
+    assert lib.mst_gen_triang_eig(0, None, 1, None, 1, None, 1, None, None, None, s) == 0
+    assert lib.mst_eig_schur(0, None, 1, None, 1, None, 1, None, None, None, s) == 0
+    # safe with m = 0: s_j = 1, k_j = 0
+    sc = torch.full((3,), -1.0, dtype=torch.float64, device="cuda")
+    kl = torch.full((3,), -1, dtype=torch.int32, device="cuda")
+    assert lib.mstrsm_safe(0, 3, None, 1, p(lam), None, 1, None, p(sc), p(kl), None, s) == 0
+    assert lib.mstrsm_safe_gen(0, 3, None, 1, None, 1, p(lam), None, 1, None, p(sc), p(kl), None, s) == 0
+    torch.cuda.synchronize()
+    assert np.all(host(sc) == 1.0) and np.all(host(kl) == 0)
+    assert np.array_equal(host(B), keep)
+
+
+def test_triang_eig_c2_default_configuration(P, oracle_mod):
+    # the benchmark's launch configuration (nb = 16, fused outer blocks)
+    w = W.c2_triang_eig()
+    announce("c2 triangular eigenvectors, nb = 16")
+    ev, Z, k = P.triang_eig(dev(w.U))
+    ev, Z, k = host(ev), host(Z), host(k)
+    lo, Zo, ko = oracle_mod.triang_eig(w.U, nb=16)
+    assert np.array_equal(ev, lo)
+    assert np.array_equal(k, ko), np.nonzero(k != ko)[0][:10]
+    T = w.U
+    R = T @ Z - Z * ev[None, :]
+    rel = np.max(np.abs(R), axis=0) / (np.abs(T).sum(1).max() * np.max(np.abs(Z), axis=0))
+    assert rel.max() <= 1e-13
+
+
+def test_safe_full_size_sampled(P, oracle_mod):
+    w = W.c3_mixed()
+    announce("c3 safe 4096x4096 (sampled columns)")
+    X, s, k = P.mstrsm_safe(dev(w.U), dev(w.shifts), dev(w.B))
+    X, k = host(X), host(k)
+    cols = np.unique(np.concatenate([np.sort(W.rng(334).choice(w.n, 16, replace=False)), [0, w.n - 1]]))
+    Xo, so, ko = oracle_mod.solve_safe(w.U, w.shifts[cols], w.B[:, cols], nb=16)
+    assert np.array_equal(k[cols], ko) and np.all(k == 0)
+    assert colerr(X[:, cols], Xo).max() <= 1e-12
+    rr = oracle_mod.relative_residual(w.U, w.shifts, X, w.B, k=k, cols=cols)
+    assert rr.max() <= 1e-13
