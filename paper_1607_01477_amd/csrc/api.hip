@@ -395,16 +395,27 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
                 if (e != hipSuccess) return e;
             }
         }
-        if (end < m) {
-            const int r0 = qa * nb;
+        // Two-level deferral, as in the back-substitution loop: rows below ob
+        // inside its group of outer blocks (kSuperRows rows) get Y of ob
+        // (K = outer_nb); the rows below the whole group get Y of all its
+        // outer blocks in one product once the group is solved.
+        const int Gp = (o.outer < kSuperRows) ? kSuperRows / o.outer : 1;
+        const int g_lo = (ob / Gp) * Gp;
+        const int g_hi = (g_lo + Gp - 1 < nob - 1) ? g_lo + Gp - 1 : nob - 1;
+        const int g_end = ((g_hi * P + P) * nb < m) ? (g_hi * P + P) * nb : m;
+        // rows [r1, r2) -= E(r1:r2, x0:x1) Y(x0:x1)
+        auto below = [&](int x0, int x1, int r1, int r2) -> hipError_t {
+            if (r2 <= r1) return hipSuccess;
             GemmArgs g{};
-            g.M = m - end; g.N = n; g.K = end - r0; g.op = GOP_SUB; g.staged = o.staged;
-            g.A = etr ? U + (long)end * ldu + r0 : U + (long)r0 * ldu + end; g.lda = ldu; g.a_ct = amode;
-            g.B = G + r0; g.ldb = ldg;
-            g.C = G + end; g.ldc = ldg;
-            hipError_t e = timed(MST_PROF_GEMM_F64, gemm_flops(g), s, [&] { return launch_gemm_f64(g, s); });
-            if (e != hipSuccess) return e;
-        }
+            g.M = r2 - r1; g.N = n; g.K = x1 - x0; g.op = GOP_SUB; g.staged = o.staged;
+            g.A = etr ? U + (long)r1 * ldu + x0 : U + (long)x0 * ldu + r1; g.lda = ldu; g.a_ct = amode;
+            g.B = G + x0; g.ldb = ldg;
+            g.C = G + r1; g.ldc = ldg;
+            return timed(MST_PROF_GEMM_F64, gemm_flops(g), s, [&] { return launch_gemm_f64(g, s); });
+        };
+        hipError_t e = below(qa * nb, end, end, g_end);
+        if (e != hipSuccess) return e;
+        if (ob == g_hi && (e = below(g_lo * P * nb, g_end, g_end, m)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
