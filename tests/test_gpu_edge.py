@@ -78,3 +78,44 @@ def test_safe_full_size_sampled(P, oracle_mod):
     assert colerr(X[:, cols], Xo).max() <= 1e-12
     rr = oracle_mod.relative_residual(w.U, w.shifts, X, w.B, k=k, cols=cols)
     assert rr.max() <= 1e-13
+
+
+def test_ragged_large_sizes(P, oracle_mod):
+    # sizes that are multiples of nothing: every block, tile and outer block ragged
+    w = W.c3_mixed(seed=31, m=3001, n=2999)
+    announce("plain 3001 x 2999 (sampled columns)")
+    X = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B)))
+    cols = np.array([0, 1, 15, 16, 17, 1500, 2997, 2998])
+    Xo = oracle_mod.solve(w.U, w.shifts[cols], w.B[:, cols])
+    assert colerr(X[:, cols], Xo).max() <= 1e-12
+    rr = oracle_mod.relative_residual(w.U, w.shifts, X, w.B, cols=cols)
+    assert rr.max() <= 1e-13
+    Y = host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B)))
+    Yo = oracle_mod.solve_adjoint(w.U, w.shifts[cols], w.B[:, cols])
+    assert colerr(Y[:, cols], Yo).max() <= 1e-12
+
+
+def test_side_stream_and_determinism(P):
+    # the library only uses the stream it is given (workspace included), and
+    # repeated calls give identical bits (safe and pencil forms too)
+    import torch
+    w = W.c6_generalized(seed=32, m=700, n=300)
+    U, V, lam = dev(w.U), dev(w.extra["V"]), dev(w.shifts)
+    ref = host(P.mstrsm(U, lam, dev(w.B)))
+    side = torch.cuda.Stream()
+    B = dev(w.B)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        X = P.mstrsm(U, lam, B)
+    side.synchronize()
+    assert np.array_equal(host(X), ref)
+    # safe form on a growth problem (unscaled off-diagonal) with rescaling
+    g = W.rng(33)
+    Ug = dev(W.random_upper(g, 700, 1.0, W.cnormal(g, 700)))
+    a = P.mstrsm_safe(Ug, lam, dev(w.B), omega_log2=30)
+    b = P.mstrsm_safe(Ug, lam, dev(w.B), omega_log2=30)
+    assert np.array_equal(host(a[0]), host(b[0])) and np.array_equal(host(a[2]), host(b[2]))
+    assert np.any(host(a[2]) > 0)
+    g1 = host(P.mstrsm_gen(U, V, lam, dev(w.B)))
+    g2 = host(P.mstrsm_gen(U, V, lam, dev(w.B)))
+    assert np.array_equal(g1, g2)
