@@ -11,6 +11,7 @@ What each function follows (T. Moon, J. Poulson, arXiv 1607.01477):
   for each shift, the per-column content of Alg 3.
 * :func:`solve_safe` — Alg 4 (Sec. 3) per column (``nb=0``), or Alg 5 (Sec. 3)
   with decision block size ``nb``; scale factors ``s_j = 2^-k_j``.
+* :func:`solve_real` — the real-arithmetic solve (real U, shifts and B).
 * :func:`solve_op` — the lower-triangular and (conjugate-)transposed variants
   of the footnote to Sec. 2, op(A - lambda_j I) x_j = b_j.
 * :func:`solve_gen` — the generalized solve ``(U - lambda_j V) x_j = b_j``
@@ -84,8 +85,10 @@ def _load():
             lib.oracle_mstrsm_gen.argtypes = [I, I, P, I, P, I, P, P, I]
             lib.oracle_mstrsm_safe_gen.argtypes = [I, I, P, I, P, I, P, P, I, P, P, P, I, I, I]
             lib.oracle_mstrsm_op.argtypes = [I, I, I, I, P, I, P, P, I]
+            lib.oracle_mstrsm_real.argtypes = [I, I, P, I, P, P, I]
             for f in (lib.oracle_mstrsm, lib.oracle_mstrsm_adjoint, lib.oracle_mstrsm_safe,
-                      lib.oracle_mstrsm_gen, lib.oracle_mstrsm_safe_gen, lib.oracle_mstrsm_op):
+                      lib.oracle_mstrsm_gen, lib.oracle_mstrsm_safe_gen, lib.oracle_mstrsm_op,
+                      lib.oracle_mstrsm_real):
                 f.restype = I
             lib.oracle_num_threads.restype = I
             lib.oracle_set_num_threads.argtypes = [I]
@@ -120,6 +123,21 @@ def solve(U, lam, B) -> np.ndarray:
     rc = _load().oracle_mstrsm(m, n, _ptr(U), max(1, m), _ptr(lam), _ptr(X), max(1, m))
     if rc != 0:
         raise RuntimeError("oracle_mstrsm failed: %d" % rc)
+    return X
+
+
+def solve_real(U, lam, B) -> np.ndarray:
+    """Real arithmetic: X with (U - lam[j] I) X[:, j] = B[:, j], U, lam, B real
+    (back substitution, Alg 1, in float64)."""
+    U = np.asfortranarray(np.asarray(U, dtype=np.float64))
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    X = np.asfortranarray(np.asarray(B, dtype=np.float64)).copy(order="F")
+    m, n = X.shape
+    if U.shape != (m, m) or lam.shape != (n,):
+        raise ValueError("shape mismatch")
+    rc = _load().oracle_mstrsm_real(m, n, _ptr(U), max(1, m), _ptr(lam), _ptr(X), max(1, m))
+    if rc != 0:
+        raise RuntimeError("oracle_mstrsm_real failed: %d" % rc)
     return X
 
 
@@ -402,7 +420,7 @@ def lanczos_sigma_min(U, z, V0, iters: int = 15):
 
 __all__ = ["build", "solve", "solve_safe", "solve_adjoint", "gradient", "triang_eig",
            "solve_gen", "solve_safe_gen", "gen_triang_eig", "eig_schur", "gen_eig_schur", "solve_op",
-           "portrait_grid",
+           "portrait_grid", "solve_real",
            "relative_residual", "lanczos_sigma_min", "num_threads", "set_num_threads",
            "OMEGA_LOG2"]
 

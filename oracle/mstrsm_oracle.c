@@ -178,6 +178,27 @@ int oracle_mstrsm_op(int uplo, int op, int m, int n, const double* Ap, int lda, 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Real arithmetic (the paper's future work, in its plainest form): U, the    */
+/* shifts and B real, (U - lambda_j I) x_j = b_j by back substitution, Alg 1: */
+/* x_i = (b_i - sum_{k>i} U(i,k) x_k) / (U(i,i) - lambda_j), updates applied  */
+/* column by column as in the complex solve.                                  */
+/* ------------------------------------------------------------------------ */
+int oracle_mstrsm_real(int m, int n, const double* U, int ldu, const double* lam, double* B, int ldb) {
+    if (m < 0 || n < 0 || ldu < (m > 1 ? m : 1) || ldb < (m > 1 ? m : 1)) return -1;
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) {
+        double* b = &B[(size_t)j * ldb];
+        for (int i = m - 1; i >= 0; --i) {
+            double x = b[i] / (U[(size_t)i * ldu + i] - lam[j]);
+            b[i] = x;
+            const double* col = &U[(size_t)i * ldu];
+            for (int r = 0; r < i; ++r) b[r] = b[r] - col[r] * x;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Adjoint solve: (U - lambda_j I)^H y_j = g_j. U^H is lower triangular, so */
 /* this is forward substitution (the lower-triangular variant the paper     */
 /* notes in its footnote to Sec. 2):                                        */

@@ -88,3 +88,11 @@ def test_c8_c9_dense_unit_disk():
     w = W.c9_dense_pencil(m=64)
     assert w.extra["A"].shape == w.extra["B"].shape == (64, 64)
     assert not np.array_equal(w.extra["A"], w.extra["B"])
+
+
+def test_c10_real():
+    w = W.c10_real(m=300, n=50)
+    assert w.U.dtype == np.float64 and w.B.dtype == np.float64 and w.shifts.dtype == np.float64
+    assert np.all(np.tril(w.U, -1) == 0)
+    d = np.abs(np.diag(w.U))
+    assert d.min() >= 0.5 and d.max() <= 2.0 and np.abs(w.shifts).max() <= 0.4

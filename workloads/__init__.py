@@ -29,7 +29,7 @@ import numpy as np
 __all__ = [
     "rng", "cnormal", "disk_uniform", "random_upper",
     "Workload", "c1_plain", "c2_triang_eig", "c3_mixed", "c4_pseudospectra",
-    "c5_adjoint", "c6_generalized", "c7_gen_triang_eig", "c8_dense_eig", "c9_dense_pencil",
+    "c5_adjoint", "c6_generalized", "c7_gen_triang_eig", "c8_dense_eig", "c9_dense_pencil", "c10_real",
     "WORKLOADS", "nominal_flops",
 ]
 
@@ -214,6 +214,18 @@ def c9_dense_pencil(seed: int = 9, m: int = 1024) -> Workload:
                     np.zeros(m, dtype=np.complex128), None, extra={"A": A, "B": B})
 
 
+def c10_real(seed: int = 10, m: int = 4096, n: int = 4096) -> Workload:
+    """Real arithmetic: U real upper triangular, off-diagonal N(0,1)/sqrt(m),
+    diagonal of random sign with modulus uniform in [0.5, 2]; real shifts
+    uniform in [-0.4, 0.4]; B iid N(0,1). Arrays are float64."""
+    g = rng(seed)
+    U = np.triu(g.standard_normal((m, m)) / math.sqrt(m), 1)
+    U[np.arange(m), np.arange(m)] = np.where(g.random(m) < 0.5, -1.0, 1.0) * (0.5 + 1.5 * g.random(m))
+    lam = -0.4 + 0.8 * g.random(n)
+    B = np.asfortranarray(g.standard_normal((m, n)))
+    return Workload("c10_real", np.asfortranarray(U), lam, B)
+
+
 WORKLOADS = {
     "c1_plain": c1_plain,
     "c2_triang_eig": c2_triang_eig,
@@ -224,6 +236,7 @@ WORKLOADS = {
     "c7_gen_triang_eig": c7_gen_triang_eig,
     "c8_dense_eig": c8_dense_eig,
     "c9_dense_pencil": c9_dense_pencil,
+    "c10_real": c10_real,
 }
 
 
