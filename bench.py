@@ -48,6 +48,7 @@ METRIC = "complex128 multi-shift solve GFLOP/s at m=n=4096 and % of MFMA peak vs
 METRIC_PENCIL = "complex128 generalized multi-shift solve GFLOP/s (8 m^2 n) at m=n=4096"
 METRIC_SAFE = "complex128 safe multi-shift solve GFLOP/s at m=n=4096"
 METRIC_TEIG = "complex128 triangular eigenvectors GFLOP/s (sum 4 j^2) at m=2048"
+METRIC_REAL = "float64 real multi-shift solve GFLOP/s (m^2 n) at m=n=4096"
 
 
 def log(*a):
@@ -57,7 +58,8 @@ def log(*a):
 def dev(a, torch):
     import numpy as np
     a = np.asfortranarray(a)
-    out = torch.empty_strided(a.shape, (1, a.shape[0]), dtype=torch.complex128, device="cuda")
+    dt = torch.float64 if a.dtype == np.float64 else torch.complex128
+    out = torch.empty_strided(a.shape, (1, a.shape[0]), dtype=dt, device="cuda")
     out.copy_(torch.from_numpy(a))
     return out
 
@@ -210,12 +212,13 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["solve", "pencil", "safe", "triang_eig"], default="solve",
+    ap.add_argument("--workload", choices=["solve", "pencil", "safe", "triang_eig", "real"], default="solve",
                     help="solve: (U - l_j I) X = B, the headline; pencil: the generalized "
                          "solve (U - l_j V) X = B at the same size (8 m^2 n flops); safe: the "
                          "safe solve of the headline inputs; triang_eig: triangular "
-                         "eigenvectors at m = 2048 (sum 4 j^2 flops). The last three "
-                         "without the secondary measurements")
+                         "eigenvectors at m = 2048 (sum 4 j^2 flops); real: the real-"
+                         "arithmetic solve at the same size (m^2 n flops). All but the "
+                         "first without the secondary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 4 device copies of 512 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -242,6 +245,7 @@ def main() -> int:
     pencil = args.workload == "pencil"
     safe = args.workload == "safe"
     teig = args.workload == "triang_eig"
+    real = args.workload == "real"
     if args.workload != "solve":
         args.no_secondary = True
     if pencil:
@@ -254,6 +258,8 @@ def main() -> int:
         w = W.c6_generalized(m=m, n=n)
     elif teig:
         w = W.c2_triang_eig(m=m)
+    elif real:
+        w = W.c10_real(m=m, n=n)
     else:
         w = W.c3_mixed(m=m, n=n)
     log("inputs generated in %.1fs" % (time.perf_counter() - t_gen))
@@ -261,7 +267,7 @@ def main() -> int:
     U = dev(w.U, torch)
     lam = torch.from_numpy(w.shifts).cuda()
     B0 = dev(w.B, torch)
-    flops = (8.0 if pencil else 4.0) * m * m * n
+    flops = (8.0 if pencil else 1.0 if real else 4.0) * m * m * n
     if teig:
         flops = W.nominal_flops(m, m, w.col_len)
     opts = dict(nb=args.nb, outer_nb=args.outer_nb)
@@ -274,6 +280,9 @@ def main() -> int:
     elif safe:
         def solve(X):
             return P.mstrsm_safe(U, lam, X, **opts)
+    elif real:
+        def solve(X):
+            return P.mstrsm_real(U, lam, X, outer_nb=args.outer_nb)
     elif teig:
         def solve(X):
             # X: unused placeholder (the eigenvector matrix is allocated by the call)
@@ -342,9 +351,10 @@ def main() -> int:
         "peak": PEAK_FP64_MFMA_TF,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP64_MFMA_TF, 4),
-        "traffic": gemm_traffic(m, n, args.nb, args.outer_nb, pencil),
+        "traffic": None if real else gemm_traffic(m, n, args.nb, args.outer_nb, pencil),
         "kernel": ("k_gemm_direct, pencil substitution C -= U X - V (lambda X) (FP64 MFMA 16x16x4)"
-                   if pencil else "k_gemm_direct (substitution GEMM, FP64 MFMA 16x16x4)"),
+                   if pencil else "k_gemm_real (real substitution GEMM, FP64 MFMA 16x16x4)" if real
+                   else "k_gemm_direct (substitution GEMM, FP64 MFMA 16x16x4)"),
         "avg_launch_us": round(g["ms"] * 1e3 / max(1, g["launches"]), 2),
         "flops_per_launch": g["flops"] / max(1, g["launches"]),
         "kernel_ms_per_solve": split,
@@ -352,7 +362,8 @@ def main() -> int:
     }
 
     line = {
-        "metric": {"pencil": METRIC_PENCIL, "safe": METRIC_SAFE, "triang_eig": METRIC_TEIG}.get(args.workload, METRIC),
+        "metric": {"pencil": METRIC_PENCIL, "safe": METRIC_SAFE, "triang_eig": METRIC_TEIG,
+                   "real": METRIC_REAL}.get(args.workload, METRIC),
         "value": round(gflops, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -369,10 +380,12 @@ def main() -> int:
                                 "shifts in disk r=0.2), inputs resident in HBM" % (m, n)) if pencil else
                                ("complex128 triangular eigenvectors (safe solve, variable-length "
                                 "columns), m=%d, CN(0,1) entries with 5%% repeated eigenvalues" % m) if teig else
+                               ("float64 real-arithmetic multi-shift solve, m=%d n=%d real shifts in "
+                                "[-0.4, 0.4], inputs resident in HBM" % (m, n)) if real else
                                ("complex128 multi-shift solve, %s FP64, m=%d n=%d shifts (annulus-"
                                 "diagonal U, shifts in disk r=0.4), inputs resident in HBM"
                                 % ("safe" if safe else "plain", m, n)),
-                   "m": m, "n": n, "nb": args.nb, "outer_nb": args.outer_nb},
+                   "m": m, "n": n, "nb": 64 if real else args.nb, "outer_nb": args.outer_nb},
         "pct_fp64_mfma_peak": round(100.0 * gflops / 1e3 / PEAK_FP64_MFMA_TF, 2),
         # the paper's own speedups, on its CPU hardware (context, not targets)
         "paper_context": {
@@ -471,6 +484,9 @@ def main() -> int:
         elif safe:
             def osolve(k):
                 return oracle.solve_safe(w.U, w.shifts[:k], w.B[:, :k], nb=args.nb)
+        elif real:
+            def osolve(k):
+                return oracle.solve_real(w.U, w.shifts[:k], w.B[:, :k])
         elif teig:
             def osolve(k):
                 # the last k columns (the longest ones)

@@ -139,6 +139,21 @@ mst_status mstrsm_op(int side, int uplo, int op, int m, int n, const void* A, in
                      const void* shifts, void* B, int ldb, const mst_opts* opt, void* stream);
 
 /*
+ * mstrsm_real — real-arithmetic multi-shift solve (the paper's future work, in
+ * its plainest form): U, the shifts and B real (float64),
+ *     (U - shifts[j] I) X(:,j) = B(:,j),
+ * back substitution in diagonal blocks of 64 rows with the substitution on the
+ * FP64 matrix cores (Alg 3 with real operands). Plain: no scaling, like mstrsm.
+ *   U, ldu     m x m upper triangular float64, read only (strict lower triangle not read)
+ *   shifts     n float64
+ *   B, ldb     m x n float64; on entry B, on exit X
+ *   opt        nullable; outer_nb (a multiple of 64, default 256) is used, nb is not
+ *              (the diagonal blocks are 64 rows); precision must be 0
+ */
+mst_status mstrsm_real(int m, int n, const double* U, int ldu, const double* shifts, double* B,
+                       int ldb, const mst_opts* opt, void* stream);
+
+/*
  * Gradient pieces of a real loss L through X = solve(U, shifts, B), given
  * Y = adjoint solve of dL/dX (gradient convention dL/dRe z + i dL/dIm z).
  * The gradient of B is Y itself.

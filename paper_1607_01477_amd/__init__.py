@@ -23,7 +23,7 @@ from ._lib import MstError, MstOpts
 
 __all__ = ["mstrsm", "mstrsm_safe", "mstrsm_adjoint", "grad_u", "grad_shift", "residual",
            "triang_eig", "lanczos_sigma_min", "mstrsm_gen", "mstrsm_safe_gen", "gen_triang_eig",
-           "eig_schur", "gen_eig_schur", "eig", "gen_eig", "mstrsm_op",
+           "eig_schur", "gen_eig_schur", "eig", "gen_eig", "mstrsm_op", "mstrsm_real",
            "solve", "MultiShiftSolve", "colmajor",
            "MstError", "version", "lib_path"]
 
@@ -180,6 +180,26 @@ def mstrsm_op(A, shifts, B, *, uplo="U", op="N", side="L", nb=0, outer_nb=0, fus
     rc = _lib.load().mstrsm_op(ord(side), ord(uplo), ord(op), m, n, _p(A), _ld(A), _p(s), _p(X), _ld(X),
                                ctypes.byref(o), _stream())
     _lib.check("mstrsm_op", rc)
+    return X
+
+
+def mstrsm_real(U, shifts, B, *, outer_nb=0):
+    """Real arithmetic: X with (U - shifts[j] I) X[:, j] = B[:, j] for real U,
+    shifts and B (float64; B overwritten when it is already column-major
+    float64). Diagonal blocks of 64 rows."""
+    for t, name in ((U, "U"), (B, "B")):
+        if t.dim() != 2:
+            raise ValueError("%s must be a matrix" % name)
+        _dev(t, name)
+    U = colmajor(U, torch.float64)
+    X = colmajor(B, torch.float64)
+    m, n = X.shape
+    if U.shape != (m, m):
+        raise ValueError("U must be %d x %d" % (m, m))
+    s = _vec(shifts, n, "shifts", torch.float64)
+    o = _opts(outer_nb=outer_nb)
+    rc = _lib.load().mstrsm_real(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), ctypes.byref(o), _stream())
+    _lib.check("mstrsm_real", rc)
     return X
 
 

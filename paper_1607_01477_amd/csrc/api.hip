@@ -431,6 +431,54 @@ hipError_t residual(int m, int n, const zd* U, long ldu, const zd* lam, const zd
     return timed(MST_PROF_RESID, 4.0 * m * (double)m * n, s, [&] { return launch_gemm_f64(g, s); });
 }
 
+// Real-arithmetic solve: diagonal blocks of 64 rows (bottom to top), the rows
+// of each outer block updated after each of its diagonal blocks, and the
+// two-level deferral above the outer blocks as in forward_loop.
+hipError_t real_loop(int m, int n, const double* U, long ldu, const double* lam, double* B, long ldb,
+                     int outer, hipStream_t s) {
+    constexpr int nb = 64;
+    const int P = outer / nb;
+    const int nblk = (m + nb - 1) / nb;
+    const int nob = (nblk + P - 1) / P;
+    auto q_first = [&](int ob) { return ob * P; };
+    auto row_end = [&](int ob) {
+        const int qe = (ob * P + P < nblk ? ob * P + P : nblk);
+        return (qe * nb < m) ? qe * nb : m;
+    };
+    // B(r0:r1) -= U(r0:r1, x0:x1) X(x0:x1)
+    auto gemm = [&](int r0, int r1, int x0, int x1) -> hipError_t {
+        if (r1 <= r0 || x1 <= x0) return hipSuccess;
+        RealGemmArgs g{};
+        g.M = r1 - r0; g.N = n; g.K = x1 - x0;
+        g.A = U + (long)x0 * ldu + r0; g.lda = ldu;
+        g.B = B + x0; g.ldb = ldb;
+        g.C = B + r0; g.ldc = ldb;
+        return timed(MST_PROF_GEMM_F64, 2.0 * g.M * (double)g.N * g.K, s, [&] { return launch_gemm_real(g, s); });
+    };
+    for (int ob = nob - 1; ob >= 0; --ob) {
+        const int qa = q_first(ob), qb = (ob * P + P < nblk ? ob * P + P : nblk) - 1;
+        for (int q = qb; q >= qa; --q) {
+            const int i0 = q * nb, bs = (m - i0 < nb) ? m - i0 : nb;
+            RealDiagArgs d{};
+            d.m = m; d.n = n; d.i0 = i0; d.bs = bs;
+            d.U = U; d.ldu = ldu; d.lam = lam; d.B = B; d.ldb = ldb;
+            hipError_t e = timed(MST_PROF_DIAG, 1.0 * bs * bs * (double)n, s, [&] { return launch_diag_real(d, s); });
+            if (e != hipSuccess) return e;
+            if (q > qa && (e = gemm(qa * nb, i0, i0, i0 + bs)) != hipSuccess) return e;
+        }
+        if (qa > 0) {
+            const int G = (outer < kSuperRows) ? kSuperRows / outer : 1;
+            const int g_lo = (ob / G) * G;
+            const int g_hi = (g_lo + G - 1 < nob - 1) ? g_lo + G - 1 : nob - 1;
+            const int g0 = q_first(g_lo) * nb;
+            hipError_t e = gemm(g0, qa * nb, qa * nb, row_end(ob));
+            if (e != hipSuccess) return e;
+            if (ob == g_lo && g0 > 0 && (e = gemm(0, g0, g0, row_end(g_hi))) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
 mst_status check_mat(const void* p, int ld, int rows, int cols, int ppos, int ldpos) {
     if (ld < (rows > 1 ? rows : 1)) return bad(ldpos);
     if ((long)rows * cols > 0 && p == nullptr) return bad(ppos);
@@ -639,6 +687,25 @@ mst_status mstrsm_op(int side, int uplo, int op, int m, int n, const void* A, in
         HIPCHK(forward_loop(m, n, Az, lda, nullptr, 0, lz, Bz, ldb, nullptr, 0, o, nullptr, nullptr, s,
                             nullptr, 0, ev));
     }
+    return MST_OK;
+}
+
+mst_status mstrsm_real(int m, int n, const double* U, int ldu, const double* shifts, double* B, int ldb,
+                       const mst_opts* opt, void* stream) {
+    t_bad_arg = 0;
+    if (m < 0) return bad(1);
+    if (n < 0) return bad(2);
+    mst_status st;
+    if ((st = check_mat(U, ldu, m, n > 0 ? m : 0, 3, 4)) != MST_OK) return st;
+    if (n > 0 && m > 0 && !shifts) return bad(5);
+    if ((st = check_mat(B, ldb, m, n, 6, 7)) != MST_OK) return st;
+    Opts o;
+    if ((st = read_opts(opt, o, 8)) != MST_OK) return st;
+    if (o.precision != 0) return MST_EUNSUPPORTED;
+    const int outer = (opt && opt->outer_nb) ? opt->outer_nb : 256;
+    if (outer < 64 || outer % 64) return bad(8);
+    if (m == 0 || n == 0) return MST_OK;
+    HIPCHK(real_loop(m, n, U, ldu, shifts, B, ldb, outer, (hipStream_t)stream));
     return MST_OK;
 }
 

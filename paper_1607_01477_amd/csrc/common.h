@@ -118,6 +118,25 @@ struct GemmArgs {
 hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s);
 hipError_t launch_gemm_f32(const GemmArgs& g, hipStream_t s);
 
+// ---------------------------------------------------------------- real arithmetic
+// C(M x N) -= A(M x K) B(K x N), float64, column-major, A plain.
+struct RealGemmArgs {
+    int M, N, K;
+    const double* A; long lda;
+    const double* B; long ldb;
+    double* C; long ldc;
+};
+hipError_t launch_gemm_real(const RealGemmArgs& g, hipStream_t s);
+// Diagonal block [i0, i0 + bs) (bs <= 64) of the real solve (U - lambda_j I) x = b,
+// all n shifts, in place in B.
+struct RealDiagArgs {
+    int m, n, i0, bs;
+    const double* U; long ldu;
+    const double* lam;
+    double* B; long ldb;
+};
+hipError_t launch_diag_real(const RealDiagArgs& a, hipStream_t s);
+
 // ---------------------------------------------------------------- auxiliary kernels
 hipError_t launch_norms(int m, const zd* U, long ldu, int nb, double* cn_in, double* above,
                         double* colmax, double* above_sum, double* delta, hipStream_t s);

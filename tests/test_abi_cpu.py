@@ -89,3 +89,16 @@ def test_variant_argument_errors_without_gpu():
     o.precision = 1
     assert lib.mstrsm_op(ord("L"), ord("L"), ord("N"), 3, 2, fake, 3, fake, fake, 3, ctypes.byref(o), None) == \
         _lib.MST_EUNSUPPORTED
+
+
+def test_real_argument_errors_without_gpu():
+    from paper_1607_01477_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(4096)
+    assert lib.mstrsm_real(3, 2, None, 3, fake, fake, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 3
+    o = _lib.MstOpts()
+    o.outer_nb = 96
+    assert lib.mstrsm_real(3, 2, fake, 3, fake, fake, 3, ctypes.byref(o), None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 8
+    assert lib.mstrsm_real(0, 4, None, 1, None, None, 1, None, None) == _lib.MST_OK
