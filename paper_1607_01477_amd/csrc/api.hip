@@ -431,12 +431,14 @@ hipError_t residual(int m, int n, const zd* U, long ldu, const zd* lam, const zd
     return timed(MST_PROF_RESID, 4.0 * m * (double)m * n, s, [&] { return launch_gemm_f64(g, s); });
 }
 
-// Real-arithmetic solve: diagonal blocks of 64 rows (bottom to top), the rows
-// of each outer block updated after each of its diagonal blocks, and the
-// two-level deferral above the outer blocks as in forward_loop.
+// Real-arithmetic solve: fused blocks of up to 256 rows (bottom to top; the
+// 64-row diagonal blocks and the updates inside a fused block in one kernel),
+// the rows of each outer block updated after each of its fused blocks, and
+// the two-level deferral above the outer blocks as in forward_loop.
 hipError_t real_loop(int m, int n, const double* U, long ldu, const double* lam, double* B, long ldb,
                      int outer, hipStream_t s) {
-    constexpr int nb = 64;
+    // fused blocks: the largest of 256, 192, 128, 64 rows that divides the outer block
+    const int nb = (outer % 256 == 0) ? 256 : (outer % 192 == 0) ? 192 : (outer % 128 == 0) ? 128 : 64;
     const int P = outer / nb;
     const int nblk = (m + nb - 1) / nb;
     const int nob = (nblk + P - 1) / P;
@@ -462,7 +464,7 @@ hipError_t real_loop(int m, int n, const double* U, long ldu, const double* lam,
             RealDiagArgs d{};
             d.m = m; d.n = n; d.i0 = i0; d.bs = bs;
             d.U = U; d.ldu = ldu; d.lam = lam; d.B = B; d.ldb = ldb;
-            hipError_t e = timed(MST_PROF_DIAG, 1.0 * bs * bs * (double)n, s, [&] { return launch_diag_real(d, s); });
+            hipError_t e = timed(MST_PROF_DIAG, 1.0 * bs * bs * (double)n, s, [&] { return launch_block_real(d, s); });
             if (e != hipSuccess) return e;
             if (q > qa && (e = gemm(qa * nb, i0, i0, i0 + bs)) != hipSuccess) return e;
         }

@@ -136,6 +136,9 @@ struct RealDiagArgs {
     double* B; long ldb;
 };
 hipError_t launch_diag_real(const RealDiagArgs& a, hipStream_t s);
+// Block [i0, i0 + bs) (bs <= 256) of the real solve, diagonal blocks and the
+// updates inside the block fused, all n shifts, in place in B.
+hipError_t launch_block_real(const RealDiagArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- auxiliary kernels
 hipError_t launch_norms(int m, const zd* U, long ldu, int nb, double* cn_in, double* above,

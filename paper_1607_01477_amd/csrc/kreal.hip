@@ -17,8 +17,6 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int RNT = 256;            // threads per workgroup
-constexpr int RBM = 64, RBN = 64;   // GEMM workgroup tile (four 32 x 32 wavefront tiles)
-constexpr int RDEPTH = 4;           // k-steps of operands in flight
 
 // Workgroup -> tile: groups of 8 row tiles, one contiguous range of tiles per
 // XCD (the hardware deals workgroup w to XCD w % 8).
@@ -36,120 +34,168 @@ __device__ inline void real_tile(int TM, int TN, int& tm, int& tn) {
     tn = in / gsz;
 }
 
-// C(M x N) -= A(M x K) B(K x N), all column-major. FP64 output layout of the
-// 16 x 16 x 4 product: lane l, item v holds column l % 16, row l / 16 + 4 v;
-// operands A(i, k) at lane i + 16 k, B(k, j) at lane j + 16 k.
+// C(M x N) -= A(M x K) B(K x N), all column-major, K > 0. Four wavefronts in a
+// 2 x 2 arrangement, each with a (16 TI) x (16 TJ) tile of C: TI x TJ products
+// of 16 x 16 x 4 per k-step from TI + TJ operand loads, DEPTH k-steps of
+// operands in flight. FP64 output layout of the 16 x 16 x 4 product: lane l,
+// item v holds column l % 16, row l / 16 + 4 v; operands A(i, k) at lane
+// i + 16 k, B(k, j) at lane j + 16 k. The first k-step takes C as its
+// accumulator input, one column subtile at a time, so that C never occupies
+// more than TI x 4 registers outside the accumulators.
+template <int TI, int TJ, int DEPTH>
 __global__ __launch_bounds__(RNT) void k_gemm_real(RealGemmArgs g) {
-    const int TM = (g.M + RBM - 1) / RBM, TN = (g.N + RBN - 1) / RBN;
+    constexpr int WM = 16 * TI, WN = 16 * TJ, BM = 2 * WM, BN = 2 * WN;
+    const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
     int tm, tn;
     real_tile(TM, TN, tm, tn);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lq = lane >> 4;
-    const int rw = tm * RBM + (wave >> 1) * 32, cw = tn * RBN + (wave & 1) * 32;
-    const bool full = rw + 32 <= g.M && cw + 32 <= g.N;
+    const int rw = tm * BM + (wave >> 1) * WM, cw = tn * BN + (wave & 1) * WN;
+    const bool full = rw + WM <= g.M && cw + WN <= g.N;
     const double* __restrict__ A = g.A;
     const double* __restrict__ B = g.B;
     double* __restrict__ C = g.C;
-
-    v4d acc[2][2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int col = cw + j * 16 + lr;
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = rw + i * 16 + lq + 4 * v;
-                acc[i][j][v] = (col < g.N && row < g.M) ? C[(long)col * g.ldc + row] : 0.0;
-            }
-    }
-    // acc -= a b: the negation is the MFMA's source modifier on A
-    auto mma = [&](double a0, double a1, double b0, double b1) __attribute__((always_inline)) {
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 1);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 1);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 1);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 1);
-    };
     const int nks = (g.K + 3) / 4;
-    const int ra0 = min(rw + lr, g.M - 1), ra1 = min(rw + 16 + lr, g.M - 1);
-    const int cb0 = min(cw + lr, g.N - 1), cb1 = min(cw + 16 + lr, g.N - 1);
-    double pa0[RDEPTH], pa1[RDEPTH], pb0[RDEPTH], pb1[RDEPTH];
-    if (full && (g.K & 3) == 0 && nks >= RDEPTH) {
-        // interior tile: no masking, one running pointer per operand
-        const long sA = 4L * g.lda;
-        const double* qa0 = A + (long)lq * g.lda + ra0;
-        const double* qa1 = qa0 + 16;
-        const double* qb0 = B + (long)cb0 * g.ldb + lq;
-        const double* qb1 = B + (long)cb1 * g.ldb + lq;
-        auto next = [&](double& a0, double& a1, double& b0, double& b1) __attribute__((always_inline)) {
-            a0 = *qa0; a1 = *qa1; b0 = *qb0; b1 = *qb1;
-            qa0 += sA; qa1 += sA; qb0 += 4; qb1 += 4;
-        };
+
+    v4d acc[TI][TJ];
+    // acc -= a b: the negation is the MFMA's source modifier on A
+    auto mma = [&](const double (&a)[TI], const double (&b)[TJ]) __attribute__((always_inline)) {
 #pragma unroll
-        for (int d = 0; d < RDEPTH; ++d) next(pa0[d], pa1[d], pb0[d], pb1[d]);
-        int l0 = 0;
-        for (; l0 + 2 * RDEPTH <= nks; l0 += RDEPTH) {
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
-            for (int d = 0; d < RDEPTH; ++d) {
-                mma(pa0[d], pa1[d], pb0[d], pb1[d]);
+            for (int j = 0; j < TJ; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 1);
+    };
+    // the first k-step: acc = C - a b, column subtile by column subtile
+    auto first = [&](const double (&a)[TI], const double (&b)[TJ]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            const int col = cw + j * 16 + lr;
+            v4d c[TI];
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rw + i * 16 + lq + 4 * v;
+                    c[i][v] = (col < g.N && row < g.M) ? C[(long)col * g.ldc + row] : 0.0;
+                }
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], c[i], 0, 0, 1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    int ra[TI], cb[TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) ra[i] = min(rw + 16 * i + lr, g.M - 1);
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) cb[j] = min(cw + 16 * j + lr, g.N - 1);
+    double pa[DEPTH][TI], pb[DEPTH][TJ];
+    // k-step l lives in ring slot l % DEPTH; fetch(l, slot) loads it,
+    // consume(l, slot) multiplies it in
+    auto ring = [&](auto fetch, auto consume, auto consume_first) __attribute__((always_inline)) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) fetch(d, pa[d], pb[d]);
+        consume_first(pa[0], pb[0]);
+        if (DEPTH < nks) fetch(DEPTH, pa[0], pb[0]);
+        int l0 = 1;
+        for (; l0 + 2 * DEPTH <= nks; l0 += DEPTH) {
+#pragma unroll
+            for (int d = 0; d < DEPTH; ++d) {
+                const int sl = (1 + d) % DEPTH;
+                consume(l0 + d, pa[sl], pb[sl]);
                 __builtin_amdgcn_sched_barrier(0);
-                next(pa0[d], pa1[d], pb0[d], pb1[d]);
+                fetch(l0 + d + DEPTH, pa[sl], pb[sl]);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
 #pragma unroll
-        for (int d = 0; d < RDEPTH; ++d) {
-            mma(pa0[d], pa1[d], pb0[d], pb1[d]);
-            if (l0 + d + RDEPTH < nks) next(pa0[d], pa1[d], pb0[d], pb1[d]);
+        for (int d = 0; d < DEPTH; ++d) {
+            const int sl = (1 + d) % DEPTH;
+            if (l0 + d < nks) {
+                consume(l0 + d, pa[sl], pb[sl]);
+                if (l0 + d + DEPTH < nks) fetch(l0 + d + DEPTH, pa[sl], pb[sl]);
+            }
         }
 #pragma unroll
-        for (int d = 0; d < RDEPTH; ++d)
-            if (l0 + RDEPTH + d < nks) mma(pa0[d], pa1[d], pb0[d], pb1[d]);
-    } else if (nks > 0) {
+        for (int d = 0; d < DEPTH; ++d) {
+            const int sl = (1 + d) % DEPTH;
+            if (l0 + DEPTH + d < nks) consume(l0 + DEPTH + d, pa[sl], pb[sl]);
+        }
+    };
+    if (full && (g.K & 3) == 0 && nks >= DEPTH) {
+        // interior tile: no masking, one running pointer per operand row / column
+        const long sA = 4L * g.lda;
+        const double* qa = A + (long)lq * g.lda + ra[0];
+        const double* qb[TJ];
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) qb[j] = B + (long)cb[j] * g.ldb + lq;
+        auto next = [&](int, double (&a)[TI], double (&b)[TJ]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < TI; ++i) a[i] = qa[16 * i];
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) { b[j] = *qb[j]; qb[j] += 4; }
+            qa += sA;
+        };
+        auto use = [&](int, const double (&a)[TI], const double (&b)[TJ]) __attribute__((always_inline)) {
+            mma(a, b);
+        };
+        ring(next, use, first);
+    } else {
         // edge tile: clamped unconditional loads, values outside zeroed at use
-        const bool oka0 = rw + lr < g.M, oka1 = rw + 16 + lr < g.M;
-        const bool okb0 = cw + lr < g.N, okb1 = cw + 16 + lr < g.N;
-        auto load = [&](int ks, double& a0, double& a1, double& b0, double& b1) __attribute__((always_inline)) {
+        bool oka[TI], okb[TJ];
+#pragma unroll
+        for (int i = 0; i < TI; ++i) oka[i] = rw + 16 * i + lr < g.M;
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) okb[j] = cw + 16 * j + lr < g.N;
+        auto load = [&](int ks, double (&a)[TI], double (&b)[TJ]) __attribute__((always_inline)) {
             const int k = min(ks * 4 + lq, g.K - 1);
             const double* ap = A + (long)k * g.lda;
-            a0 = ap[ra0];
-            a1 = ap[ra1];
-            b0 = B[(long)cb0 * g.ldb + k];
-            b1 = B[(long)cb1 * g.ldb + k];
+#pragma unroll
+            for (int i = 0; i < TI; ++i) a[i] = ap[ra[i]];
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) b[j] = B[(long)cb[j] * g.ldb + k];
         };
-        auto use = [&](int ks, double a0, double a1, double b0, double b1) __attribute__((always_inline)) {
+        auto masked = [&](int ks, const double (&a)[TI], const double (&b)[TJ], double (&am)[TI],
+                          double (&bm)[TJ]) __attribute__((always_inline)) {
             const bool kin = ks * 4 + lq < g.K;
-            mma((kin && oka0) ? a0 : 0.0, (kin && oka1) ? a1 : 0.0, (kin && okb0) ? b0 : 0.0,
-                (kin && okb1) ? b1 : 0.0);
+#pragma unroll
+            for (int i = 0; i < TI; ++i) am[i] = (kin && oka[i]) ? a[i] : 0.0;
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) bm[j] = (kin && okb[j]) ? b[j] : 0.0;
         };
-#pragma unroll
-        for (int d = 0; d < RDEPTH; ++d) load(min(d, nks - 1), pa0[d], pa1[d], pb0[d], pb1[d]);
-        int l0 = 0;
-        for (; l0 + RDEPTH <= nks; l0 += RDEPTH) {
-#pragma unroll
-            for (int d = 0; d < RDEPTH; ++d) {
-                use(l0 + d, pa0[d], pa1[d], pb0[d], pb1[d]);
-                __builtin_amdgcn_sched_barrier(0);
-                load(min(l0 + d + RDEPTH, nks - 1), pa0[d], pa1[d], pb0[d], pb1[d]);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < RDEPTH; ++d)
-            if (l0 + d < nks) use(l0 + d, pa0[d], pa1[d], pb0[d], pb1[d]);
+        auto use = [&](int ks, const double (&a)[TI], const double (&b)[TJ]) __attribute__((always_inline)) {
+            double am[TI], bm[TJ];
+            masked(ks, a, b, am, bm);
+            mma(am, bm);
+        };
+        auto use_first = [&](const double (&a)[TI], const double (&b)[TJ]) __attribute__((always_inline)) {
+            double am[TI], bm[TJ];
+            masked(0, a, b, am, bm);
+            first(am, bm);
+        };
+        ring(load, use, use_first);
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < TJ; ++j) {
         const int col = cw + j * 16 + lr;
         if (col >= g.N) continue;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = rw + i * 16 + lq + 4 * v;
                 if (row < g.M) C[(long)col * g.ldc + row] = acc[i][j][v];
             }
     }
+}
+
+template <int TI, int TJ, int DEPTH>
+hipError_t launch_gemm_real_t(const RealGemmArgs& g, hipStream_t s) {
+    constexpr int BM = 32 * TI, BN = 32 * TJ;
+    const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
+    hipLaunchKernelGGL((k_gemm_real<TI, TJ, DEPTH>), dim3(TM * TN), dim3(RNT), 0, s, g);
+    return hipGetLastError();
 }
 
 // Value of lane i (wave-uniform) to every lane.
@@ -206,14 +252,134 @@ __global__ __launch_bounds__(RNT) void k_diag_real(RealDiagArgs a) {
         if (jv[s] && r < bs) a.B[(long)(j0 + s) * a.ldb + i0 + r] = b[s];
 }
 
+// One block [i0, i0 + bs) of up to 256 rows for all shifts, in place in B.
+// Each wavefront owns S shifts and all rows of the block: lane r holds rows
+// r, r + 64, r + 128, r + 192 (row groups g = 0..3). The 64-row diagonal
+// blocks are taken bottom-up; inside diagonal block C, step i broadcasts the
+// finished x(64 C + i) with v_readlane and applies column 64 C + i of U both
+// to the rows of block C above it (pivot-scaled, as in k_diag_real) and to
+// all rows of the groups g < C (unscaled; they are scaled when their own
+// diagonal block starts). No LDS and no barriers: the columns of U are read
+// straight from memory, R steps ahead of their use.
+template <int C, int S, int R>
+__device__ __forceinline__ void block_real_sub(const RealDiagArgs& a, double (&b)[4][S], const double (&lam)[S],
+                                               const bool (&jv)[S], int lane) {
+    const int bs = a.bs;
+    const int rc = 64 * C + lane;                      // local row of this lane in group C
+    const int ie = min(63, bs - 64 * C - 1);            // last step of the (possibly partial) block
+    const double* __restrict__ Ub = a.U + (long)a.i0 * a.ldu + a.i0;   // U(i0, i0)
+    double p[S];
+    {
+        const bool on = rc < bs;
+        const double d = on ? Ub[(long)rc * a.ldu + rc] : 1.0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            p[s] = (on && jv[s]) ? 1.0 / (d - lam[s]) : 0.0;
+            b[C][s] *= p[s];
+        }
+    }
+    const int rcl = min(rc, bs - 1);                   // clamped row for the loads of group C
+    // Steps ie + 1 .. T - 1 (T a multiple of R) only pad a partial block: lane
+    // `step` then holds b = 0, so x = 0 and the step changes nothing; their
+    // column is clamped into the block.
+    const int T = (ie + R) / R * R;
+    auto fetch = [&](int step, double (&u)[C + 1]) __attribute__((always_inline)) {
+        const double* col = Ub + (long)(64 * C + min(max(step, 0), ie)) * a.ldu;
+#pragma unroll
+        for (int g = 0; g < C; ++g) u[g] = col[64 * g + lane];
+        u[C] = col[rcl];
+    };
+    double uq[R][C + 1];
+    // issue order = use order (the load counter is waited on in order)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        fetch(T - 1 - r, uq[r]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int i = T - 1; i >= 0; i -= R) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int step = i - r;
+            const double uc = (lane < step) ? uq[r][C] : 0.0;
+            double x[S];
+            // the diagonal block first: its next pivot row is on the critical path
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                x[s] = readlane_d(b[C][s], step);
+                b[C][s] = fma(-(uc * p[s]), x[s], b[C][s]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            double ug[C > 0 ? C : 1];
+#pragma unroll
+            for (int g = 0; g < C; ++g) ug[g] = uq[r][g];
+            fetch(step - R, uq[r]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int g = 0; g < C; ++g) b[g][s] = fma(-ug[g], x[s], b[g][s]);
+        }
+    }
+}
+
+template <int S, int R>
+__global__ __launch_bounds__(RNT) void k_block_real(RealDiagArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j0 = (blockIdx.x * (RNT / 64) + wave) * S;
+    if (j0 >= a.n) return;
+    const int nsub = (a.bs + 63) / 64;
+    double b[4][S], lam[S];
+    bool jv[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int j = j0 + s;
+        jv[s] = j < a.n;
+        lam[s] = jv[s] ? a.lam[j] : 0.0;
+        const double* bc = a.B + (long)(jv[s] ? j : j0) * a.ldb + a.i0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int r = 64 * g + lane;
+            b[g][s] = (jv[s] && r < a.bs) ? bc[r] : 0.0;
+        }
+    }
+    if (nsub > 3) block_real_sub<3, S, R>(a, b, lam, jv, lane);
+    if (nsub > 2) block_real_sub<2, S, R>(a, b, lam, jv, lane);
+    if (nsub > 1) block_real_sub<1, S, R>(a, b, lam, jv, lane);
+    block_real_sub<0, S, R>(a, b, lam, jv, lane);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (!jv[s]) continue;
+        double* bc = a.B + (long)(j0 + s) * a.ldb + a.i0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int r = 64 * g + lane;
+            if (r < a.bs) bc[r] = b[g][s];
+        }
+    }
+}
+
+template <int S, int R>
+hipError_t launch_block_real_t(const RealDiagArgs& a, hipStream_t s) {
+    constexpr int per_wg = (RNT / 64) * S;
+    hipLaunchKernelGGL((k_block_real<S, R>), dim3((a.n + per_wg - 1) / per_wg), dim3(RNT), 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_gemm_real(const RealGemmArgs& g, hipStream_t s) {
-    if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (g.K < 0) return hipErrorInvalidValue;
-    const int TM = (g.M + RBM - 1) / RBM, TN = (g.N + RBN - 1) / RBN;
-    hipLaunchKernelGGL(k_gemm_real, dim3(TM * TN), dim3(RNT), 0, s, g);
-    return hipGetLastError();
+    if (g.M <= 0 || g.N <= 0 || g.K == 0) return hipSuccess;
+    // The largest wavefront tile that still gives the chip enough wavefronts:
+    // 128 x 32 (16 products per 10 loads) for the deferred updates, 64 x 32 in
+    // between, 32 x 32 for thin updates. Two k-steps in flight for 128 x 32
+    // once there are two such wavefronts per SIMD, three below.
+    const long w8 = (long)((g.M + 127) / 128) * ((g.N + 31) / 32);
+    const long w4 = (long)((g.M + 63) / 64) * ((g.N + 31) / 32);
+    if (w8 >= 1536) return launch_gemm_real_t<8, 2, 2>(g, s);
+    if (w8 >= 768) return launch_gemm_real_t<8, 2, 3>(g, s);
+    if (w4 >= 1024) return launch_gemm_real_t<4, 2, 4>(g, s);
+    return launch_gemm_real_t<2, 2, 4>(g, s);
 }
 
 hipError_t launch_diag_real(const RealDiagArgs& a, hipStream_t s) {
@@ -221,6 +387,11 @@ hipError_t launch_diag_real(const RealDiagArgs& a, hipStream_t s) {
     if (a.bs <= 0 || a.bs > NB || a.n <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_diag_real<NB, SPW>), dim3((a.n + per_wg - 1) / per_wg), dim3(RNT), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_block_real(const RealDiagArgs& a, hipStream_t s) {
+    if (a.bs <= 0 || a.bs > 256 || a.n <= 0) return hipErrorInvalidValue;
+    return launch_block_real_t<4, 8>(a, s);
 }
 
 }  // namespace mst
