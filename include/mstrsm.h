@@ -139,16 +139,21 @@ mst_status mstrsm_op(int side, int uplo, int op, int m, int n, const void* A, in
                      const void* shifts, void* B, int ldb, const mst_opts* opt, void* stream);
 
 /*
- * mstrsm_real — real-arithmetic multi-shift solve (the paper's future work, in
- * its plainest form): U, the shifts and B real (float64),
+ * mstrsm_real — real-arithmetic multi-shift solve (named as future work in the
+ * paper's conclusion, Sec. 8; here in its plainest form): U, the shifts and B
+ * real (float64),
  *     (U - shifts[j] I) X(:,j) = B(:,j),
- * back substitution in diagonal blocks of 64 rows with the substitution on the
- * FP64 matrix cores (Alg 3 with real operands). Plain: no scaling, like mstrsm.
+ * Alg 3 with real operands: fused blocks of up to 256 rows (64-row diagonal
+ * blocks and the updates inside the block in one kernel), the substitution
+ * between blocks on the FP64 matrix cores. Plain: no scaling, like mstrsm.
  *   U, ldu     m x m upper triangular float64, read only (strict lower triangle not read)
  *   shifts     n float64
  *   B, ldb     m x n float64; on entry B, on exit X
- *   opt        nullable; outer_nb (a multiple of 64, default 256) is used, nb is not
- *              (the diagonal blocks are 64 rows); precision must be 0
+ *   opt        nullable; outer_nb (a multiple of 64, default 256) is used, nb is not;
+ *              precision must be 0 (else MST_EUNSUPPORTED)
+ * Errors: MST_EARG for m < 0, n < 0, a leading dimension below max(1, m), a
+ * null pointer with a non-empty operand, or outer_nb not a multiple of 64
+ * (mst_last_bad_arg names the argument); HIP errors as MST_EHIP.
  */
 mst_status mstrsm_real(int m, int n, const double* U, int ldu, const double* shifts, double* B,
                        int ldb, const mst_opts* opt, void* stream);

@@ -127,17 +127,15 @@ struct RealGemmArgs {
     double* C; long ldc;
 };
 hipError_t launch_gemm_real(const RealGemmArgs& g, hipStream_t s);
-// Diagonal block [i0, i0 + bs) (bs <= 64) of the real solve (U - lambda_j I) x = b,
-// all n shifts, in place in B.
+// Block [i0, i0 + bs) (bs <= 256) of the real solve (U - lambda_j I) x = b, all
+// n shifts, in place in B: the 64-row diagonal blocks and the updates inside
+// the block fused.
 struct RealDiagArgs {
     int m, n, i0, bs;
     const double* U; long ldu;
     const double* lam;
     double* B; long ldb;
 };
-hipError_t launch_diag_real(const RealDiagArgs& a, hipStream_t s);
-// Block [i0, i0 + bs) (bs <= 256) of the real solve, diagonal blocks and the
-// updates inside the block fused, all n shifts, in place in B.
 hipError_t launch_block_real(const RealDiagArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- auxiliary kernels

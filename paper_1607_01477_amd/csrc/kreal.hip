@@ -2,13 +2,15 @@
 // right-hand sides real (float64). The paper leaves real arithmetic to future
 // work; this is its plainest form, the blocked back substitution of Alg 3 with
 // real operands:
-//   k_diag_real - one nb x nb diagonal block for all shifts: the block in LDS,
-//                 lane r of a wavefront owns row r, the solution entry of
-//                 each step broadcast with v_readlane; several shifts per
-//                 wavefront interleaved to hide the step latency;
-//   k_gemm_real - the substitution C -= A B on the FP64 matrix cores
-//                 (one v_mfma_f64_16x16x4_f64 per 16 x 16 x 4 block), operands
-//                 streamed from L1/L2 into registers a few k-steps ahead.
+//   k_block_real - one block of up to 256 rows for all shifts: the 64-row
+//                  diagonal blocks and the updates inside the block fused,
+//                  lane r of a wavefront owning rows r + 64 g, the solution
+//                  entry of each step broadcast with v_readlane, several
+//                  shifts per wavefront interleaved;
+//   k_gemm_real  - the substitution C -= A B between blocks on the FP64
+//                  matrix cores (one v_mfma_f64_16x16x4_f64 per 16 x 16 x 4
+//                  block), operands streamed from L1/L2 into registers a few
+//                  k-steps ahead, the wavefront tile chosen by shape.
 #include "common.h"
 
 namespace mst {
@@ -205,61 +207,16 @@ __device__ inline double readlane_d(double v, int i) {
     return __hiloint2double(hi, lo);
 }
 
-// One diagonal block [i0, i0 + bs) of U for all shifts, in place in B. Lane r
-// of each wavefront owns row r (NB = 64); each wavefront solves SPW shifts at
-// once. Rows are scaled by their pivot reciprocals first: with
-// b'(r) = b(r) / d(r) and u'(r, i) = u(r, i) / d(r), step i is x(i) = b'(i)
-// (broadcast) and b'(r) -= u'(r, i) x(i).
-template <int NB, int SPW>
-__global__ __launch_bounds__(RNT) void k_diag_real(RealDiagArgs a) {
-    static_assert(NB == 64, "one row per lane");
-    __shared__ double Us[NB * NB];   // Us[i * NB + r] = U(i0 + r, i0 + i) for r < i, else 0
-    __shared__ double Ud[NB];
-    const int bs = a.bs, i0 = a.i0;
-    for (int t = threadIdx.x; t < NB * NB; t += RNT) {
-        const int c = t / NB, rr = t - c * NB;
-        const double v = (rr <= c && c < bs) ? a.U[(long)(i0 + c) * a.ldu + i0 + rr] : 0.0;
-        if (rr == c) Ud[rr] = v;
-        Us[t] = (rr < c) ? v : 0.0;
-    }
-    __syncthreads();
-    const int r = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int j0 = (blockIdx.x * (RNT / 64) + wave) * SPW;
-    if (j0 >= a.n) return;
-    double b[SPW], p[SPW];
-    bool jv[SPW];
-#pragma unroll
-    for (int s = 0; s < SPW; ++s) {
-        const int j = j0 + s;
-        jv[s] = j < a.n;
-        const bool on = jv[s] && r < bs;
-        const double d = on ? Ud[r] - a.lam[j] : 1.0;
-        p[s] = 1.0 / d;
-        b[s] = on ? a.B[(long)j * a.ldb + i0 + r] / d : 0.0;
-    }
-    double un = Us[(bs - 1) * NB + r];
-    for (int i = bs - 1; i >= 0; --i) {
-        const double u = un;
-        un = Us[(i > 0 ? i - 1 : 0) * NB + r];
-#pragma unroll
-        for (int s = 0; s < SPW; ++s) {
-            const double x = readlane_d(b[s], i);
-            b[s] = fma(-(u * p[s]), x, b[s]);
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < SPW; ++s)
-        if (jv[s] && r < bs) a.B[(long)(j0 + s) * a.ldb + i0 + r] = b[s];
-}
-
 // One block [i0, i0 + bs) of up to 256 rows for all shifts, in place in B.
 // Each wavefront owns S shifts and all rows of the block: lane r holds rows
 // r, r + 64, r + 128, r + 192 (row groups g = 0..3). The 64-row diagonal
 // blocks are taken bottom-up; inside diagonal block C, step i broadcasts the
 // finished x(64 C + i) with v_readlane and applies column 64 C + i of U both
-// to the rows of block C above it (pivot-scaled, as in k_diag_real) and to
-// all rows of the groups g < C (unscaled; they are scaled when their own
-// diagonal block starts). No LDS and no barriers: the columns of U are read
+// to the rows of block C above it and to all rows of the groups g < C. Rows
+// of block C are scaled by their pivot reciprocals when the block starts:
+// with b'(r) = b(r) / d(r) and u'(r, i) = u(r, i) / d(r), step i is
+// x(i) = b'(i) (broadcast) and b'(r) -= u'(r, i) x(i); rows of the groups
+// g < C take the unscaled update until their own diagonal block starts. No LDS and no barriers: the columns of U are read
 // straight from memory, R steps ahead of their use.
 template <int C, int S, int R>
 __device__ __forceinline__ void block_real_sub(const RealDiagArgs& a, double (&b)[4][S], const double (&lam)[S],
@@ -278,16 +235,18 @@ __device__ __forceinline__ void block_real_sub(const RealDiagArgs& a, double (&b
             b[C][s] *= p[s];
         }
     }
-    const int rcl = min(rc, bs - 1);                   // clamped row for the loads of group C
     // Steps ie + 1 .. T - 1 (T a multiple of R) only pad a partial block: lane
     // `step` then holds b = 0, so x = 0 and the step changes nothing; their
     // column is clamped into the block.
     const int T = (ie + R) / R * R;
     auto fetch = [&](int step, double (&u)[C + 1]) __attribute__((always_inline)) {
-        const double* col = Ub + (long)(64 * C + min(max(step, 0), ie)) * a.ldu;
+        const int cs = min(max(step, 0), ie);
+        const double* col = Ub + (long)(64 * C + cs) * a.ldu;
 #pragma unroll
         for (int g = 0; g < C; ++g) u[g] = col[64 * g + lane];
-        u[C] = col[rcl];
+        // rows on or below the diagonal read the diagonal entry instead (the
+        // value is discarded there): the strict lower triangle is never read
+        u[C] = col[64 * C + min(lane, cs)];
     };
     double uq[R][C + 1];
     // issue order = use order (the load counter is waited on in order)
@@ -296,30 +255,46 @@ __device__ __forceinline__ void block_real_sub(const RealDiagArgs& a, double (&b
         fetch(T - 1 - r, uq[r]);
         __builtin_amdgcn_sched_barrier(0);
     }
+    // Software-pipelined steps: the rows of the groups g < C take the update of
+    // step k + 1 while the readlane of step k and the pivot-block update of
+    // step k are in flight.
+    double xp[S], up[C > 0 ? C : 1];
+#pragma unroll
+    for (int s = 0; s < S; ++s) xp[s] = 0.0;
+#pragma unroll
+    for (int g = 0; g < (C > 0 ? C : 1); ++g) up[g] = 0.0;
+    auto lagged = [&](int h) __attribute__((always_inline)) {
+        // half h of the lagged update: shifts [h S / 2, (h + 1) S / 2)
+#pragma unroll
+        for (int s = h * S / 2; s < (h + 1) * S / 2; ++s)
+#pragma unroll
+            for (int g = 0; g < C; ++g) b[g][s] = fma(-up[g], xp[s], b[g][s]);
+    };
     for (int i = T - 1; i >= 0; i -= R) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int step = i - r;
             const double uc = (lane < step) ? uq[r][C] : 0.0;
             double x[S];
-            // the diagonal block first: its next pivot row is on the critical path
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                x[s] = readlane_d(b[C][s], step);
-                b[C][s] = fma(-(uc * p[s]), x[s], b[C][s]);
-            }
+            for (int s = 0; s < S; ++s) x[s] = readlane_d(b[C][s], step);
             __builtin_amdgcn_sched_barrier(0);
-            double ug[C > 0 ? C : 1];
+            lagged(0);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int g = 0; g < C; ++g) ug[g] = uq[r][g];
+            for (int s = 0; s < S; ++s) b[C][s] = fma(-(uc * p[s]), x[s], b[C][s]);
+            __builtin_amdgcn_sched_barrier(0);
+            lagged(1);
+#pragma unroll
+            for (int s = 0; s < S; ++s) xp[s] = x[s];
+#pragma unroll
+            for (int g = 0; g < C; ++g) up[g] = uq[r][g];
             fetch(step - R, uq[r]);
             __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int s = 0; s < S; ++s)
-#pragma unroll
-                for (int g = 0; g < C; ++g) b[g][s] = fma(-ug[g], x[s], b[g][s]);
         }
     }
+    lagged(0);
+    lagged(1);
 }
 
 template <int S, int R>
@@ -380,13 +355,6 @@ hipError_t launch_gemm_real(const RealGemmArgs& g, hipStream_t s) {
     if (w8 >= 768) return launch_gemm_real_t<8, 2, 3>(g, s);
     if (w4 >= 1024) return launch_gemm_real_t<4, 2, 4>(g, s);
     return launch_gemm_real_t<2, 2, 4>(g, s);
-}
-
-hipError_t launch_diag_real(const RealDiagArgs& a, hipStream_t s) {
-    constexpr int NB = 64, SPW = 4, per_wg = (RNT / 64) * SPW;
-    if (a.bs <= 0 || a.bs > NB || a.n <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_diag_real<NB, SPW>), dim3((a.n + per_wg - 1) / per_wg), dim3(RNT), 0, s, a);
-    return hipGetLastError();
 }
 
 hipError_t launch_block_real(const RealDiagArgs& a, hipStream_t s) {
