@@ -197,6 +197,15 @@ def other_workloads(P, W, torch, np) -> dict:
         var[uplo + op] = {"ms": round(msv, 3), "gflops": round(fl / (msv * 1e-3) / 1e9, 2)}
     out["variants_m4096_n2048"] = var
     log("variants m=4096 n=2048: %s" % ", ".join("%s %.3f ms" % (k, v["ms"]) for k, v in var.items()))
+    del Ud, Ld, Bv
+    # real arithmetic, m = n = 4096 (m^2 n flops), solved in place repeatedly
+    w = W.c10_real()
+    Ur, sr, Br = dev(w.U, torch), torch.from_numpy(w.shifts).cuda(), dev(w.B, torch)
+    msr = _time(lambda: P.mstrsm_real(Ur, sr, Br), torch, 5)
+    out["c10_real_m4096_n4096"] = {"ms": round(msr, 3),
+                                   "gflops": round(float(w.m) ** 2 * w.n / (msr * 1e-3) / 1e9, 2)}
+    log("real solve 4096 x 4096: %.3f ms" % msr)
+    del Ur, Br
     return out
 
 
