@@ -159,6 +159,28 @@ mst_status mstrsm_real(int m, int n, const double* U, int ldu, const double* shi
                        int ldb, const mst_opts* opt, void* stream);
 
 /*
+ * mstrsm_real_op — the variants of mstrsm_op (footnote to Sec. 2) in real
+ * arithmetic: side 'L': op(A - shifts[j] I) X(:,j) = B(:,j); side 'R':
+ * X(:,j)^T op(A - shifts[j] I) = B(:,j)^T; A upper ('U') or lower ('L'); op 'N',
+ * 'T' or 'C' ('C' = 'T' for real data). (U, 'N') on the left is mstrsm_real.
+ * Every other variant is reduced to the upper solve: a lower A transposed is
+ * upper, and a forward substitution is a back substitution in reversed order,
+ * (J E J)(J x) = J b with J the row reversal. The library forms that
+ * upper-triangular copy of A (m x m doubles of stream-ordered workspace; only
+ * A's own triangle is read) and, for the forward cases, reverses the rows of
+ * B before and after the solve.
+ *   side, uplo, op   the characters above (as int)
+ *   A, lda           m x m triangular float64, read only
+ *   shifts           n float64
+ *   B, ldb           m x n float64; on entry B, on exit X
+ *   opt              nullable; outer_nb (a multiple of 64, default 256); precision must be 0
+ * Errors as mstrsm_op (MST_EARG names the argument; MST_EUNSUPPORTED for
+ * precision 1; MST_ENOMEM when the copy of A cannot be allocated).
+ */
+mst_status mstrsm_real_op(int side, int uplo, int op, int m, int n, const double* A, int lda,
+                          const double* shifts, double* B, int ldb, const mst_opts* opt, void* stream);
+
+/*
  * Gradient pieces of a real loss L through X = solve(U, shifts, B), given
  * Y = adjoint solve of dL/dX (gradient convention dL/dRe z + i dL/dIm z).
  * The gradient of B is Y itself.

@@ -23,7 +23,7 @@ from ._lib import MstError, MstOpts
 
 __all__ = ["mstrsm", "mstrsm_safe", "mstrsm_adjoint", "grad_u", "grad_shift", "residual",
            "triang_eig", "lanczos_sigma_min", "mstrsm_gen", "mstrsm_safe_gen", "gen_triang_eig",
-           "eig_schur", "gen_eig_schur", "eig", "gen_eig", "mstrsm_op", "mstrsm_real",
+           "eig_schur", "gen_eig_schur", "eig", "gen_eig", "mstrsm_op", "mstrsm_real", "mstrsm_real_op",
            "solve", "MultiShiftSolve", "colmajor",
            "MstError", "version", "lib_path"]
 
@@ -186,7 +186,7 @@ def mstrsm_op(A, shifts, B, *, uplo="U", op="N", side="L", nb=0, outer_nb=0, fus
 def mstrsm_real(U, shifts, B, *, outer_nb=0):
     """Real arithmetic: X with (U - shifts[j] I) X[:, j] = B[:, j] for real U,
     shifts and B (float64; B overwritten when it is already column-major
-    float64). Diagonal blocks of 64 rows."""
+    float64). Fused blocks of up to 256 rows."""
     for t, name in ((U, "U"), (B, "B")):
         if t.dim() != 2:
             raise ValueError("%s must be a matrix" % name)
@@ -200,6 +200,29 @@ def mstrsm_real(U, shifts, B, *, outer_nb=0):
     o = _opts(outer_nb=outer_nb)
     rc = _lib.load().mstrsm_real(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), ctypes.byref(o), _stream())
     _lib.check("mstrsm_real", rc)
+    return X
+
+
+def mstrsm_real_op(A, shifts, B, *, uplo="U", op="N", side="L", outer_nb=0):
+    """The variants of `mstrsm_op` in real arithmetic (float64): X with
+    op(A - shifts[j] I) X[:, j] = B[:, j] (side "L") or
+    X[:, j]^T op(A - shifts[j] I) = B[:, j]^T (side "R"), A upper ("U") or lower
+    ("L"), op "N", "T" or "C" (the same as "T" for real data). B is overwritten
+    when it is already column-major float64."""
+    for t, name in ((A, "A"), (B, "B")):
+        if t.dim() != 2:
+            raise ValueError("%s must be a matrix" % name)
+        _dev(t, name)
+    A = colmajor(A, torch.float64)
+    X = colmajor(B, torch.float64)
+    m, n = X.shape
+    if A.shape != (m, m):
+        raise ValueError("A must be %d x %d" % (m, m))
+    s = _vec(shifts, n, "shifts", torch.float64)
+    o = _opts(outer_nb=outer_nb)
+    rc = _lib.load().mstrsm_real_op(ord(side), ord(uplo), ord(op), m, n, _p(A), _ld(A), _p(s), _p(X), _ld(X),
+                                    ctypes.byref(o), _stream())
+    _lib.check("mstrsm_real_op", rc)
     return X
 
 

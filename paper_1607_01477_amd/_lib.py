@@ -18,7 +18,7 @@ MST_OK, MST_EARG, MST_EHIP, MST_ENOMEM, MST_EUNSUPPORTED = 0, -1, -2, -3, -4
 EXPORTS = ["mstrsm", "mstrsm_safe", "mstrsm_adjoint", "mst_grad_u", "mst_grad_shift",
            "mst_residual", "mst_triang_eig", "mst_lanczos_sigma_min", "mstrsm_gen",
            "mstrsm_safe_gen", "mst_gen_triang_eig", "mst_eig_schur", "mst_gen_eig_schur", "mstrsm_op",
-           "mstrsm_real",
+           "mstrsm_real", "mstrsm_real_op",
            "mst_status_string",
            "mst_last_bad_arg", "mst_last_error", "mst_version", "mst_profile_start",
            "mst_profile_stop"]
@@ -65,6 +65,7 @@ def load():
                 "mst_gen_eig_schur": [I, P, I, P, I, P, I, P, I, P, P, OP, P],
                 "mstrsm_op": [I, I, I, I, I, P, I, P, P, I, OP, P],
                 "mstrsm_real": [I, I, P, I, P, P, I, OP, P],
+                "mstrsm_real_op": [I, I, I, I, I, P, I, P, P, I, OP, P],
             }
             for name, args in sig.items():
                 f = getattr(lib, name)

@@ -711,6 +711,47 @@ mst_status mstrsm_real(int m, int n, const double* U, int ldu, const double* shi
     return MST_OK;
 }
 
+mst_status mstrsm_real_op(int side, int uplo, int op, int m, int n, const double* A, int lda,
+                          const double* shifts, double* B, int ldb, const mst_opts* opt, void* stream) {
+    t_bad_arg = 0;
+    if (side != 'L' && side != 'R') return bad(1);
+    if (uplo != 'U' && uplo != 'L') return bad(2);
+    if (op != 'N' && op != 'T' && op != 'C') return bad(3);
+    if (m < 0) return bad(4);
+    if (n < 0) return bad(5);
+    mst_status st;
+    if ((st = check_mat(A, lda, m, n > 0 ? m : 0, 6, 7)) != MST_OK) return st;
+    if (n > 0 && m > 0 && !shifts) return bad(8);
+    if ((st = check_mat(B, ldb, m, n, 9, 10)) != MST_OK) return st;
+    Opts o;
+    if ((st = read_opts(opt, o, 11)) != MST_OK) return st;
+    if (o.precision != 0) return MST_EUNSUPPORTED;
+    const int outer = (opt && opt->outer_nb) ? opt->outer_nb : 256;
+    if (outer < 64 || outer % 64) return bad(11);
+    // real data: the conjugate transpose is the transpose; the right side
+    // x op(A - l I) = b is op(A - l I)^T x^T = b^T
+    const bool tr = (op != 'N') != (side == 'R');
+    if (m == 0 || n == 0) return MST_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (uplo == 'U' && !tr) {
+        HIPCHK(real_loop(m, n, A, lda, shifts, B, ldb, outer, s));
+        return MST_OK;
+    }
+    // Lower or transposed: an upper-triangular copy. A lower A transposed is
+    // upper; a forward substitution becomes a back substitution on the
+    // reversed order, (J E J)(J x) = J b with J the reversal permutation.
+    const int mode = (uplo == 'L' && tr) ? REAL_T : (uplo == 'L') ? REAL_JJ : REAL_JTJ;
+    const bool rev = mode != REAL_T;
+    Workspace ws(s);
+    double* Uh;
+    HIPCHK(ws_get(ws, (size_t)m * m, &Uh));
+    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_real_upper_copy(m, A, lda, mode, Uh, s); }));
+    if (rev) HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_reverse_rows(m, n, B, ldb, s); }));
+    HIPCHK(real_loop(m, n, Uh, m, shifts, B, ldb, outer, s));
+    if (rev) HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_reverse_rows(m, n, B, ldb, s); }));
+    return MST_OK;
+}
+
 mst_status mst_grad_u(int m, int n, const void* Y, int ldy, const void* X, int ldx, void* gU, int ldgu,
                       void* stream) {
     t_bad_arg = 0;

@@ -137,6 +137,16 @@ struct RealDiagArgs {
     double* B; long ldb;
 };
 hipError_t launch_block_real(const RealDiagArgs& a, hipStream_t s);
+// Upper-triangular copy Uh (m x m, leading dimension m; only the upper triangle
+// is written) of a triangular A whose variant reduces to an upper solve:
+//   REAL_T    Uh(i,j) = A(j,i)                  (A lower, transposed solve)
+//   REAL_JJ   Uh(i,j) = A(m-1-i, m-1-j)         (A lower, forward solve)
+//   REAL_JTJ  Uh(i,j) = A(m-1-j, m-1-i)         (A upper, transposed solve)
+// Only A's own triangle is read.
+enum RealCopyMode { REAL_T = 0, REAL_JJ = 1, REAL_JTJ = 2 };
+hipError_t launch_real_upper_copy(int m, const double* A, long lda, int mode, double* Uh, hipStream_t s);
+// Rows of B (m x n) in reverse order, in place.
+hipError_t launch_reverse_rows(int m, int n, double* B, long ldb, hipStream_t s);
 
 // ---------------------------------------------------------------- auxiliary kernels
 hipError_t launch_norms(int m, const zd* U, long ldu, int nb, double* cn_in, double* above,

@@ -340,7 +340,78 @@ hipError_t launch_block_real_t(const RealDiagArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// One 32 x 32 tile of Uh: the matching tile of A is read along its columns
+// (coalesced), parked in LDS under Uh's coordinates, and written along Uh's
+// columns. Elements outside A's own triangle or outside the matrix are never
+// touched; Uh's strict lower triangle is left unwritten.
+__global__ __launch_bounds__(256) void k_real_upper_copy(int m, const double* __restrict__ A, long lda, int mode,
+                                                         double* __restrict__ Uh) {
+    __shared__ double sh[32][33];
+    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    if (i0 > j0 + 31) return;   // tile entirely below the diagonal
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    // origin of the source tile and the map (rl, cl) -> (il, jl)
+    int p0, q0;
+    if (mode == REAL_T) { p0 = j0; q0 = i0; }
+    else if (mode == REAL_JJ) { p0 = m - 32 - i0; q0 = m - 32 - j0; }
+    else { p0 = m - 32 - j0; q0 = m - 32 - i0; }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int rl = tx, cl = ty + 8 * k;
+        int il, jl;
+        if (mode == REAL_T) { il = cl; jl = rl; }
+        else if (mode == REAL_JJ) { il = 31 - rl; jl = 31 - cl; }
+        else { il = 31 - cl; jl = 31 - rl; }
+        const int p = p0 + rl, q = q0 + cl, i = i0 + il, j = j0 + jl;
+        double v = 0.0;
+        if (p >= 0 && p < m && q >= 0 && q < m && i <= j) v = A[(long)q * lda + p];
+        sh[il][jl] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int il = tx, jl = ty + 8 * k;
+        const int i = i0 + il, j = j0 + jl;
+        if (i < m && j < m && i <= j) Uh[(long)j * m + i] = sh[il][jl];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reverse_rows(int m, int n, double* __restrict__ B, long ldb) {
+    const int half = m / 2;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (t >= half || j >= n) return;
+    double* col = B + (long)j * ldb;
+    const int i = (int)t, k = m - 1 - (int)t;
+    const double a = col[i], b = col[k];
+    col[i] = b;
+    col[k] = a;
+}
+
 }  // namespace
+
+hipError_t launch_real_upper_copy(int m, const double* A, long lda, int mode, double* Uh, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    if (mode < REAL_T || mode > REAL_JTJ) return hipErrorInvalidValue;
+    const int T = (m + 31) / 32;
+    hipLaunchKernelGGL(k_real_upper_copy, dim3(T, T), dim3(256), 0, s, m, A, lda, mode, Uh);
+    return hipGetLastError();
+}
+
+hipError_t launch_reverse_rows(int m, int n, double* B, long ldb, hipStream_t s) {
+    if (m < 2 || n <= 0) return hipSuccess;
+    if (n > 65535) {
+        // grid.y limit: columns in chunks
+        for (int j0 = 0; j0 < n; j0 += 65535) {
+            hipError_t e = launch_reverse_rows(m, (n - j0 < 65535 ? n - j0 : 65535), B + (long)j0 * ldb, ldb, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    const int half = m / 2;
+    hipLaunchKernelGGL(k_reverse_rows, dim3((half + 255) / 256, n), dim3(256), 0, s, m, n, B, ldb);
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm_real(const RealGemmArgs& g, hipStream_t s) {
     if (g.K < 0) return hipErrorInvalidValue;

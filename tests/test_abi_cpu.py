@@ -102,3 +102,30 @@ def test_real_argument_errors_without_gpu():
     assert lib.mstrsm_real(3, 2, fake, 3, fake, fake, 3, ctypes.byref(o), None) == _lib.MST_EARG
     assert lib.mst_last_bad_arg() == 8
     assert lib.mstrsm_real(0, 4, None, 1, None, None, 1, None, None) == _lib.MST_OK
+
+
+def test_real_op_argument_errors_without_gpu():
+    from paper_1607_01477_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(4096)
+    c = ord
+    assert lib.mstrsm_real_op(c("X"), c("U"), c("N"), 3, 2, fake, 3, fake, fake, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 1
+    assert lib.mstrsm_real_op(c("L"), c("Q"), c("N"), 3, 2, fake, 3, fake, fake, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 2
+    assert lib.mstrsm_real_op(c("L"), c("L"), c("Z"), 3, 2, fake, 3, fake, fake, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 3
+    assert lib.mstrsm_real_op(c("L"), c("L"), c("N"), 3, 2, fake, 2, fake, fake, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 7
+    assert lib.mstrsm_real_op(c("L"), c("L"), c("N"), 3, 2, fake, 3, None, fake, 3, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 8
+    o = _lib.MstOpts()
+    o.outer_nb = 96
+    assert lib.mstrsm_real_op(c("R"), c("L"), c("T"), 3, 2, fake, 3, fake, fake, 3, ctypes.byref(o), None) == \
+        _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 11
+    o = _lib.MstOpts()
+    o.precision = 1
+    assert lib.mstrsm_real_op(c("L"), c("L"), c("N"), 3, 2, fake, 3, fake, fake, 3, ctypes.byref(o), None) == \
+        _lib.MST_EUNSUPPORTED
+    assert lib.mstrsm_real_op(c("L"), c("L"), c("C"), 0, 4, None, 1, None, None, 1, None, None) == _lib.MST_OK

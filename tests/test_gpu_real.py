@@ -77,3 +77,98 @@ def test_real_matches_complex_path(P):
     Xc = P.mstrsm(Uc, cd(w.shifts), Bc).cpu().numpy()
     assert np.all(Xc.imag == 0)
     assert colerr(Xr, Xc.real).max() <= 1e-12
+
+
+def test_real_empty_problems(P):
+    # m = 0 or n = 0: nothing to do, no launch, B returned as is
+    for m, n in [(0, 0), (0, 5), (7, 0)]:
+        U = torch.zeros((m, m), dtype=torch.float64, device="cuda").t()
+        B = torch.zeros((m, n), dtype=torch.float64, device="cuda").t().contiguous().t()
+        s = torch.zeros(n, dtype=torch.float64, device="cuda")
+        X = P.mstrsm_real(U, s, B)
+        assert X.shape == (m, n)
+
+
+def test_real_deterministic_side_stream_and_padding(P):
+    # bitwise equal across calls, also on a non-default stream; rows of a padded
+    # leading dimension stay untouched
+    w = W.c10_real(seed=1003, m=777, n=301)
+    X1 = P.mstrsm_real(rdev(w.U), rdev(w.shifts), rdev(w.B)).cpu().numpy()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        X2 = P.mstrsm_real(rdev(w.U), rdev(w.shifts), rdev(w.B))
+    st.synchronize()
+    assert np.array_equal(X1, X2.cpu().numpy())
+    ld = 800
+    Bp = torch.full((301, ld), 7.25, dtype=torch.float64, device="cuda").t()   # ld x n, column-major
+    Bp[:777].copy_(torch.from_numpy(w.B))
+    Xp = P.mstrsm_real(rdev(w.U), rdev(w.shifts), Bp[:777])
+    torch.cuda.synchronize()
+    assert Xp.data_ptr() == Bp.data_ptr()
+    assert np.array_equal(Xp.cpu().numpy(), X1)
+    assert torch.all(Bp[777:] == 7.25)
+
+
+def _real_operator(A, lam, uplo, op):
+    T = np.triu(A) if uplo == "U" else np.tril(A)
+    E = T - lam * np.eye(A.shape[0])
+    return E if op == "N" else E.T
+
+
+@pytest.mark.parametrize("uplo,op", [(u, o) for u in "UL" for o in "NTC"])
+@pytest.mark.parametrize("m,n,outer", [(1, 2, 256), (33, 17, 64), (65, 33, 256), (257, 70, 128), (600, 96, 256)])
+def test_real_variants(P, oracle_mod, uplo, op, m, n, outer):
+    announce("real variant %s%s m=%d n=%d outer=%d" % (uplo, op, m, n, outer))
+    w = W.c10_real(seed=1100 + m + n + ord(uplo) + ord(op), m=m, n=n)
+    A = w.U if uplo == "U" else np.asfortranarray(w.U.T.copy())
+    An = A.copy(order="F")
+    if uplo == "U":
+        An[np.tril_indices(m, -1)] = np.nan   # the triangle the variant must not read
+    else:
+        An[np.triu_indices(m, 1)] = np.nan
+    X = P.mstrsm_real_op(rdev(An), rdev(w.shifts), rdev(w.B), uplo=uplo, op=op, outer_nb=outer).cpu().numpy()
+    assert np.all(np.isfinite(X))
+    # the complex oracle on the same real data (for real data 'C' is 'T')
+    Xo = oracle_mod.solve_op(A.astype(np.complex128), w.shifts.astype(np.complex128),
+                             w.B.astype(np.complex128), uplo, op)
+    assert np.all(Xo.imag == 0)
+    err = colerr(X, Xo.real)
+    for j in range(n):
+        E = _real_operator(A, w.shifts[j], uplo, op)
+        r = np.abs(E @ X[:, j] - w.B[:, j]).max()
+        assert r <= 1e-13 * np.abs(E).sum(1).max() * np.abs(X[:, j]).max(), j
+        if j < 16:
+            kap = np.linalg.norm(E, np.inf) * np.linalg.norm(np.linalg.inv(E), np.inf)
+            assert err[j] <= 64 * EPS * kap, (j, err[j] / (EPS * kap))
+
+
+@pytest.mark.parametrize("uplo", "UL")
+@pytest.mark.parametrize("op", "NT")
+def test_real_right_side(P, oracle_mod, uplo, op):
+    # x op(A - l_j I) = b_j  <=>  op(A - l_j I)^T x_j^T = b_j^T
+    w = W.c10_real(seed=1200 + ord(uplo) + ord(op), m=300, n=40)
+    A = w.U if uplo == "U" else np.asfortranarray(w.U.T.copy())
+    X = P.mstrsm_real_op(rdev(A), rdev(w.shifts), rdev(w.B), uplo=uplo, op=op, side="R").cpu().numpy()
+    Xo = oracle_mod.solve_op(A.astype(np.complex128), w.shifts.astype(np.complex128),
+                             w.B.astype(np.complex128), uplo, "T" if op == "N" else "N")
+    assert colerr(X, Xo.real).max() <= 1e-12
+    for j in range(40):
+        E = _real_operator(A, w.shifts[j], uplo, op)
+        r = np.abs(X[:, j] @ E - w.B[:, j]).max()
+        assert r <= 1e-13 * np.abs(E).sum(0).max() * np.abs(X[:, j]).max()
+
+
+def test_real_upper_n_is_mstrsm_real_and_full_size_lower(P, oracle_mod):
+    w = W.c10_real(seed=1300, m=333, n=50)
+    a = P.mstrsm_real_op(rdev(w.U), rdev(w.shifts), rdev(w.B), uplo="U", op="N").cpu().numpy()
+    b = P.mstrsm_real(rdev(w.U), rdev(w.shifts), rdev(w.B)).cpu().numpy()
+    assert np.array_equal(a, b)
+    # 4096 x 4096 lower forward solve, sampled columns against the oracle
+    w = W.c10_real()
+    L = np.asfortranarray(w.U.T.copy())
+    X = P.mstrsm_real_op(rdev(L), rdev(w.shifts), rdev(w.B), uplo="L", op="N").cpu().numpy()
+    assert np.all(np.isfinite(X))
+    cols = [0, 1, 63, 64, 2048, 4095]
+    Xo = oracle_mod.solve_op(L.astype(np.complex128), w.shifts[cols].astype(np.complex128),
+                             w.B[:, cols].astype(np.complex128), "L", "N")
+    assert colerr(X[:, cols], Xo.real).max() <= 1e-12
