@@ -796,7 +796,7 @@ mst_status mst_residual(int m, int n, const void* U, int ldu, const void* shifts
     if ((st = check_mat(X, ldx, m, n, 6, 7)) != MST_OK) return st;
     if ((st = check_mat(B0, ldb0, m, n, 8, 9)) != MST_OK) return st;
     if ((st = check_mat(R, ldr, m, n, 10, 11)) != MST_OK) return st;
-    if (R == X && m * n > 0) return bad(10);
+    if (R == X && (long)m * n > 0) return bad(10);
     if (R == B0 && ldr != ldb0) return bad(11);
     if (m == 0 || n == 0) return MST_OK;
     HIPCHK(residual(m, n, (const zd*)U, ldu, (const zd*)shifts, (const zd*)X, ldx, (const zd*)B0, ldb0,

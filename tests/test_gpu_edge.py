@@ -119,3 +119,38 @@ def test_side_stream_and_determinism(P):
     g1 = host(P.mstrsm_gen(U, V, lam, dev(w.B)))
     g2 = host(P.mstrsm_gen(U, V, lam, dev(w.B)))
     assert np.array_equal(g1, g2)
+
+
+def test_offsets_beyond_two_gib(P, oracle_mod):
+    # U and B of 2.4 GB each (complex, m = n = 12288): element offsets times 16
+    # bytes pass 2^31, so any 32-bit index arithmetic would show here
+    import torch
+    m = n = 12288
+    announce("complex m = n = %d (sampled columns)" % m)
+    w = W.c3_mixed(seed=31, m=m, n=n)
+    Ud, ld, Bd = dev(w.U), dev(w.shifts), dev(w.B)
+    X = P.mstrsm(Ud, ld, Bd)
+    torch.cuda.synchronize()
+    cols = [0, 1, 6143, n - 2, n - 1]
+    Xs = X[:, cols].cpu().numpy()
+    del Ud, Bd, X
+    Xo = oracle_mod.solve(w.U, w.shifts[cols], w.B[:, cols])
+    assert colerr(Xs, Xo).max() <= 1e-12
+    rows = np.abs(w.U).sum(1)
+    for k, j in enumerate(cols):
+        r = w.U @ Xs[:, k] - w.shifts[j] * Xs[:, k] - w.B[:, j]
+        nrm = (rows + np.abs(np.diag(w.U) - w.shifts[j]) - np.abs(np.diag(w.U))).max()
+        assert np.abs(r).max() <= 1e-13 * nrm * np.abs(Xs[:, k]).max()
+    del w
+    # real, m = n = 16384 (2 GB each)
+    m = n = 16384
+    announce("real m = n = %d (sampled columns)" % m)
+    w = W.c10_real(seed=32, m=m, n=n)
+    Ur = torch.from_numpy(w.U).cuda()   # Fortran-ordered: column-major on the device
+    Br = torch.from_numpy(w.B).cuda()
+    Xr = P.mstrsm_real(Ur, torch.from_numpy(w.shifts).cuda(), Br)
+    torch.cuda.synchronize()
+    Xs = Xr[:, cols].cpu().numpy()
+    del Ur, Br, Xr
+    Xo = oracle_mod.solve_real(w.U, w.shifts[cols], w.B[:, cols])
+    assert colerr(Xs, Xo).max() <= 1e-12
