@@ -154,3 +154,41 @@ def test_offsets_beyond_two_gib(P, oracle_mod):
     del Ur, Br, Xr
     Xo = oracle_mod.solve_real(w.U, w.shifts[cols], w.B[:, cols])
     assert colerr(Xs, Xo).max() <= 1e-12
+
+
+def test_nonfinite_columns_stay_isolated(P):
+    # NaN and Inf in single columns of B and an exactly zero pivot for one
+    # shift: those columns turn non-finite, every other column is bit-identical
+    # to the solve of the clean data (the plain solve, like xTRSM, reports
+    # nothing; shifts never mix)
+    import torch
+    m, n = 600, 70
+    bad = (3, 40, 55)
+    w = W.c3_mixed(seed=41, m=m, n=n)
+    clean = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B)))
+    B = w.B.copy(order="F")
+    B[100, 3] = np.nan
+    B[5, 40] = np.inf
+    lam = w.shifts.copy()
+    lam[55] = w.U[300, 300]
+    X = host(P.mstrsm(dev(w.U), dev(lam), dev(B)))
+    for j in range(n):
+        if j in bad:
+            assert not np.all(np.isfinite(X[:, j])), j
+        else:
+            assert np.array_equal(X[:, j], clean[:, j]), j
+    # the same for the real path
+    w = W.c10_real(seed=42, m=m, n=n)
+    rd = lambda a: torch.from_numpy(np.asfortranarray(a)).cuda()
+    clean = P.mstrsm_real(rd(w.U), rd(w.shifts), rd(w.B)).cpu().numpy()
+    B = w.B.copy(order="F")
+    B[100, 3] = np.nan
+    B[5, 40] = np.inf
+    lam = w.shifts.copy()
+    lam[55] = w.U[300, 300]
+    X = P.mstrsm_real(rd(w.U), rd(lam), rd(B)).cpu().numpy()
+    for j in range(n):
+        if j in bad:
+            assert not np.all(np.isfinite(X[:, j])), j
+        else:
+            assert np.array_equal(X[:, j], clean[:, j]), j
