@@ -43,6 +43,11 @@ GEMM_TRAFFIC = {"kgemm_sha1": "8a4e7752b13cd971", "bytes_per_launch": 295.4e6, "
                 "nb": 16, "outer_nb": 256,
                 # the pencil substitution (profiles/k_gemm_direct_pencil_m4096_n4096.md)
                 "pencil_bytes_per_launch": 470.9e6}
+# The same for the real substitution GEMM (all its tile variants, averaged over
+# the 15 launches of a solve; profiles/real_solve_m4096_n4096.md), valid for the
+# source it was measured on (sha1 prefix of csrc/kreal.hip).
+REAL_GEMM_TRAFFIC = {"kreal_sha1": "9ce80911bf2d5dbd", "bytes_per_launch": 119.7e6, "m": 4096, "n": 4096,
+                     "outer_nb": 256}
 PEAK_FP32_MFMA_TF = 157.3
 METRIC = "complex128 multi-shift solve GFLOP/s at m=n=4096 and % of MFMA peak vs plain FP64"
 METRIC_PENCIL = "complex128 generalized multi-shift solve GFLOP/s (8 m^2 n) at m=n=4096"
@@ -75,6 +80,19 @@ def gemm_traffic(m, n, nb, outer_nb, pencil=False):
     if h != t["kgemm_sha1"] or (m, n, nb, outer_nb) != (t["m"], t["n"], t["nb"], t["outer_nb"]):
         return None
     return t["pencil_bytes_per_launch"] if pencil else t["bytes_per_launch"]
+
+
+def real_gemm_traffic(m, n, outer_nb):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1607_01477_amd", "csrc", "kreal.hip")
+    try:
+        h = hashlib.sha1(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    t = REAL_GEMM_TRAFFIC
+    if h != t["kreal_sha1"] or (m, n, outer_nb) != (t["m"], t["n"], t["outer_nb"]):
+        return None
+    return t["bytes_per_launch"]
 
 
 def _time(fn, torch, reps):
@@ -364,7 +382,8 @@ def main() -> int:
         "peak": PEAK_FP64_MFMA_TF,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP64_MFMA_TF, 4),
-        "traffic": None if real else gemm_traffic(m, n, args.nb, args.outer_nb, pencil),
+        "traffic": (real_gemm_traffic(m, n, args.outer_nb) if real
+                    else gemm_traffic(m, n, args.nb, args.outer_nb, pencil)),
         "kernel": ("k_gemm_direct, pencil substitution C -= U X - V (lambda X) (FP64 MFMA 16x16x4)"
                    if pencil else "k_gemm_real (real substitution GEMM, FP64 MFMA 16x16x4)" if real
                    else "k_gemm_direct (substitution GEMM, FP64 MFMA 16x16x4)"),
