@@ -555,6 +555,37 @@ def main() -> int:
                                 "one_thread": {"value": round(oflops(n1) / t1 / 1e9, 3),
                                                "sample": "%d shifts (%.1f s)" % (n1, t1)}}
         log("cpu oracle: %d cols in %.1fs = %.2f GFLOP/s on %d threads" % (ncols, tc, cg, cores))
+        if not (pencil or safe or real or teig or args.no_secondary):
+            # the oracle on the other workloads of the path, beside their GPU
+            # times under "workloads": C1, C2 and the C5 forward solve in full, C4
+            # on every 100th grid point (extrapolated to the whole grid)
+            oc = {}
+
+            def tm(f):
+                t0 = time.perf_counter()
+                f()
+                return time.perf_counter() - t0
+            w1 = W.c1_plain()
+            t = tm(lambda: oracle.solve(w1.U, w1.shifts, w1.B))
+            oc["c1_m256_n256"] = {"s": round(t, 4), "sample": "full",
+                                  "gflops": round(W.nominal_flops(w1.m, w1.n) / t / 1e9, 2)}
+            w2 = W.c2_triang_eig()
+            t = tm(lambda: oracle.triang_eig(w2.U, nb=64))
+            oc["c2_triang_eig_m2048"] = {"s": round(t, 3), "sample": "full (safe, nb = 64)",
+                                         "gflops": round(W.nominal_flops(w2.m, w2.m, w2.col_len) / t / 1e9, 2)}
+            w4 = W.c4_pseudospectra()
+            sel = np.arange(0, w4.shifts.shape[0], 100)
+            t = tm(lambda: oracle.lanczos_sigma_min(w4.U, w4.shifts[sel], w4.B[:, sel], iters=15))
+            oc["c4_lanczos_m2000_N10000"] = {"s_subset": round(t, 3),
+                                             "s_extrapolated": round(t * w4.shifts.shape[0] / sel.size, 2),
+                                             "sample": "%d of %d shifts (every 100th), extrapolated"
+                                                       % (sel.size, w4.shifts.shape[0])}
+            w5 = W.c5_adjoint()
+            t = tm(lambda: oracle.solve(w5.U, w5.shifts, w5.B))
+            oc["c5_fwd_m4096_n2048"] = {"s": round(t, 3), "sample": "full",
+                                        "gflops": round(W.nominal_flops(w5.m, w5.n) / t / 1e9, 2)}
+            line["cpu_baseline"]["other_configs"] = oc
+            log("cpu oracle, other configs:", oc)
 
     print(json.dumps(line), flush=True)
     return 0
