@@ -11,6 +11,8 @@
 //                  matrix cores (one v_mfma_f64_16x16x4_f64 per 16 x 16 x 4
 //                  block), operands streamed from L1/L2 into registers a few
 //                  k-steps ahead, the wavefront tile chosen by shape.
+#include <cstdint>
+
 #include "common.h"
 
 namespace mst {
@@ -44,8 +46,9 @@ __device__ inline void real_tile(int TM, int TN, int& tm, int& tn) {
 // i + 16 k, B(k, j) at lane j + 16 k. The first k-step takes C as its
 // accumulator input, one column subtile at a time, so that C never occupies
 // more than TI x 4 registers outside the accumulators.
-template <int TI, int TJ, int DEPTH>
+template <int TI, int TJ, int DEPTH, bool PAIR = false>
 __global__ __launch_bounds__(RNT) void k_gemm_real(RealGemmArgs g) {
+    static_assert(!PAIR || TI % 2 == 0, "row pairs: even number of row subtiles");
     constexpr int WM = 16 * TI, WN = 16 * TJ, BM = 2 * WM, BN = 2 * WN;
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
     int tm, tn;
@@ -58,6 +61,12 @@ __global__ __launch_bounds__(RNT) void k_gemm_real(RealGemmArgs g) {
     const double* __restrict__ B = g.B;
     double* __restrict__ C = g.C;
     const int nks = (g.K + 3) / 4;
+    // row r16 (0..15) of row subtile i: consecutive 16-row blocks, or with
+    // PAIR the subtiles 2p and 2p + 1 interleaved over 32 rows (even and odd
+    // rows), so that one 16-byte load gives a lane its rows of both
+    auto rowmap = [&](int i, int r16) __attribute__((always_inline)) {
+        return PAIR ? rw + 32 * (i >> 1) + 2 * r16 + (i & 1) : rw + 16 * i + r16;
+    };
 
     v4d acc[TI][TJ];
     // acc -= a b: the negation is the MFMA's source modifier on A
@@ -78,7 +87,7 @@ __global__ __launch_bounds__(RNT) void k_gemm_real(RealGemmArgs g) {
             for (int i = 0; i < TI; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int row = rw + i * 16 + lq + 4 * v;
+                    const int row = rowmap(i, lq + 4 * v);
                     c[i][v] = (col < g.N && row < g.M) ? C[(long)col * g.ldc + row] : 0.0;
                 }
 #pragma unroll
@@ -89,7 +98,7 @@ __global__ __launch_bounds__(RNT) void k_gemm_real(RealGemmArgs g) {
     };
     int ra[TI], cb[TJ];
 #pragma unroll
-    for (int i = 0; i < TI; ++i) ra[i] = min(rw + 16 * i + lr, g.M - 1);
+    for (int i = 0; i < TI; ++i) ra[i] = min(rowmap(i, lr), g.M - 1);
 #pragma unroll
     for (int j = 0; j < TJ; ++j) cb[j] = min(cw + 16 * j + lr, g.N - 1);
     double pa[DEPTH][TI], pb[DEPTH][TJ];
@@ -133,8 +142,19 @@ __global__ __launch_bounds__(RNT) void k_gemm_real(RealGemmArgs g) {
 #pragma unroll
         for (int j = 0; j < TJ; ++j) qb[j] = B + (long)cb[j] * g.ldb + lq;
         auto next = [&](int, double (&a)[TI], double (&b)[TJ]) __attribute__((always_inline)) {
+            if constexpr (PAIR) {
+                // rows rw + 32 p + 2 lr and + 1: one 16-byte load (16-byte
+                // alignment checked by the launcher)
 #pragma unroll
-            for (int i = 0; i < TI; ++i) a[i] = qa[16 * i];
+                for (int p = 0; p < TI / 2; ++p) {
+                    const double2 v = *(const double2*)(qa + 32 * p);
+                    a[2 * p] = v.x;
+                    a[2 * p + 1] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < TI; ++i) a[i] = qa[16 * i];
+            }
 #pragma unroll
             for (int j = 0; j < TJ; ++j) { b[j] = *qb[j]; qb[j] += 4; }
             qa += sA;
@@ -147,7 +167,7 @@ __global__ __launch_bounds__(RNT) void k_gemm_real(RealGemmArgs g) {
         // edge tile: clamped unconditional loads, values outside zeroed at use
         bool oka[TI], okb[TJ];
 #pragma unroll
-        for (int i = 0; i < TI; ++i) oka[i] = rw + 16 * i + lr < g.M;
+        for (int i = 0; i < TI; ++i) oka[i] = rowmap(i, lr) < g.M;
 #pragma unroll
         for (int j = 0; j < TJ; ++j) okb[j] = cw + 16 * j + lr < g.N;
         auto load = [&](int ks, double (&a)[TI], double (&b)[TJ]) __attribute__((always_inline)) {
@@ -186,17 +206,17 @@ __global__ __launch_bounds__(RNT) void k_gemm_real(RealGemmArgs g) {
         for (int i = 0; i < TI; ++i)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = rw + i * 16 + lq + 4 * v;
+                const int row = rowmap(i, lq + 4 * v);
                 if (row < g.M) C[(long)col * g.ldc + row] = acc[i][j][v];
             }
     }
 }
 
-template <int TI, int TJ, int DEPTH>
+template <int TI, int TJ, int DEPTH, bool PAIR = false>
 hipError_t launch_gemm_real_t(const RealGemmArgs& g, hipStream_t s) {
     constexpr int BM = 32 * TI, BN = 32 * TJ;
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
-    hipLaunchKernelGGL((k_gemm_real<TI, TJ, DEPTH>), dim3(TM * TN), dim3(RNT), 0, s, g);
+    hipLaunchKernelGGL((k_gemm_real<TI, TJ, DEPTH, PAIR>), dim3(TM * TN), dim3(RNT), 0, s, g);
     return hipGetLastError();
 }
 
@@ -417,14 +437,17 @@ hipError_t launch_gemm_real(const RealGemmArgs& g, hipStream_t s) {
     if (g.K < 0) return hipErrorInvalidValue;
     if (g.M <= 0 || g.N <= 0 || g.K == 0) return hipSuccess;
     // The largest wavefront tile that still gives the chip enough wavefronts:
-    // 128 x 32 (16 products per 10 loads) for the deferred updates, 64 x 32 in
-    // between, 32 x 32 for thin updates. Two k-steps in flight for 128 x 32
-    // once there are two such wavefronts per SIMD, three below.
+    // 128 x 32 (16 products per 10 loads, or per 6 with row pairs) for the
+    // deferred updates, 64 x 32 in between, 32 x 32 for thin updates. Two
+    // k-steps in flight for 128 x 32 once there are two such wavefronts per
+    // SIMD, more below. Row pairs (one 16-byte load for two rows of A) need A
+    // 16-byte aligned with an even leading dimension.
     const long w8 = (long)((g.M + 127) / 128) * ((g.N + 31) / 32);
     const long w4 = (long)((g.M + 63) / 64) * ((g.N + 31) / 32);
-    if (w8 >= 1536) return launch_gemm_real_t<8, 2, 2>(g, s);
-    if (w8 >= 768) return launch_gemm_real_t<8, 2, 3>(g, s);
-    if (w4 >= 1024) return launch_gemm_real_t<4, 2, 4>(g, s);
+    const bool pair = ((uintptr_t)g.A & 15) == 0 && (g.lda & 1) == 0;
+    if (w8 >= 1536) return pair ? launch_gemm_real_t<8, 2, 2, true>(g, s) : launch_gemm_real_t<8, 2, 2>(g, s);
+    if (w8 >= 768) return pair ? launch_gemm_real_t<8, 2, 4, true>(g, s) : launch_gemm_real_t<8, 2, 3>(g, s);
+    if (w4 >= 1024) return pair ? launch_gemm_real_t<4, 2, 4, true>(g, s) : launch_gemm_real_t<4, 2, 4>(g, s);
     return launch_gemm_real_t<2, 2, 4>(g, s);
 }
 

@@ -172,3 +172,20 @@ def test_real_upper_n_is_mstrsm_real_and_full_size_lower(P, oracle_mod):
     Xo = oracle_mod.solve_op(L.astype(np.complex128), w.shifts[cols].astype(np.complex128),
                              w.B[:, cols].astype(np.complex128), "L", "N")
     assert colerr(X[:, cols], Xo.real).max() <= 1e-12
+
+
+@pytest.mark.parametrize("m,n", [(3002, 2500), (3001, 2499)])
+def test_real_large_ragged_tiles(P, oracle_mod, m, n):
+    # even m: the 16-byte row-pair loads of the GEMM, with ragged edge tiles;
+    # odd m (odd leading dimension): the single-row loads
+    announce("real ragged m=%d n=%d" % (m, n))
+    w = W.c10_real(seed=1400 + m, m=m, n=n)
+    X = P.mstrsm_real(rdev(w.U), rdev(w.shifts), rdev(w.B)).cpu().numpy()
+    assert np.all(np.isfinite(X))
+    cols = [0, 1, 31, 32, n // 2, n - 2, n - 1]
+    Xo = oracle_mod.solve_real(w.U, w.shifts[cols], w.B[:, cols])
+    assert colerr(X[:, cols], Xo).max() <= 1e-12
+    for k, j in enumerate(cols):
+        A = np.triu(w.U) - w.shifts[j] * np.eye(m)
+        r = np.abs(A @ X[:, j] - w.B[:, j]).max()
+        assert r <= 1e-13 * np.abs(A).sum(1).max() * np.abs(X[:, j]).max(), j
