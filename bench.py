@@ -46,7 +46,7 @@ GEMM_TRAFFIC = {"kgemm_sha1": "8a4e7752b13cd971", "bytes_per_launch": 295.4e6, "
 # The same for the real substitution GEMM (all its tile variants, averaged over
 # the 15 launches of a solve; profiles/real_solve_m4096_n4096.md), valid for the
 # source it was measured on (sha1 prefix of csrc/kreal.hip).
-REAL_GEMM_TRAFFIC = {"kreal_sha1": "7aab2e5b99bc95b8", "bytes_per_launch": 119.4e6, "m": 4096, "n": 4096,
+REAL_GEMM_TRAFFIC = {"kreal_sha1": "e7be9309582c3d97", "bytes_per_launch": 119.4e6, "m": 4096, "n": 4096,
                      "outer_nb": 256}
 PEAK_FP32_MFMA_TF = 157.3
 METRIC = "complex128 multi-shift solve GFLOP/s at m=n=4096 and % of MFMA peak vs plain FP64"

@@ -10,7 +10,10 @@
 //   k_gemm_real  - the substitution C -= A B between blocks on the FP64
 //                  matrix cores (one v_mfma_f64_16x16x4_f64 per 16 x 16 x 4
 //                  block), operands streamed from L1/L2 into registers a few
-//                  k-steps ahead, the wavefront tile chosen by shape.
+//                  k-steps ahead, the wavefront tile chosen by shape;
+//   k_real_upper_copy, k_reverse_rows - the lower, transposed and right-side
+//                  variants (footnote to Sec. 2) as this upper solve: an
+//                  upper-triangular copy of A and the rows of B reversed.
 #include <cstdint>
 
 #include "common.h"
@@ -236,8 +239,9 @@ __device__ inline double readlane_d(double v, int i) {
 // of block C are scaled by their pivot reciprocals when the block starts:
 // with b'(r) = b(r) / d(r) and u'(r, i) = u(r, i) / d(r), step i is
 // x(i) = b'(i) (broadcast) and b'(r) -= u'(r, i) x(i); rows of the groups
-// g < C take the unscaled update until their own diagonal block starts. No LDS and no barriers: the columns of U are read
-// straight from memory, R steps ahead of their use.
+// g < C take the unscaled update until their own diagonal block starts. No
+// LDS and no barriers: the columns of U are read straight from memory, R
+// steps ahead of their use.
 template <int C, int S, int R>
 __device__ __forceinline__ void block_real_sub(const RealDiagArgs& a, double (&b)[4][S], const double (&lam)[S],
                                                const bool (&jv)[S], int lane) {
