@@ -189,3 +189,14 @@ def test_real_large_ragged_tiles(P, oracle_mod, m, n):
         A = np.triu(w.U) - w.shifts[j] * np.eye(m)
         r = np.abs(A @ X[:, j] - w.B[:, j]).max()
         assert r <= 1e-13 * np.abs(A).sum(1).max() * np.abs(X[:, j]).max(), j
+
+
+@pytest.mark.parametrize("outer", [128, 192, 320, 512, 1024])
+def test_real_outer_block_sizes(P, oracle_mod, outer):
+    # fused blocks of 128 or 192 rows (outer 128, 192), 64 (outer 320), and
+    # several fused blocks per outer block (outer 512, 1024)
+    m, n = 1100, 300
+    announce("real outer=%d m=%d n=%d" % (outer, m, n))
+    w = W.c10_real(seed=1500 + outer, m=m, n=n)
+    X = P.mstrsm_real(rdev(w.U), rdev(w.shifts), rdev(w.B), outer_nb=outer).cpu().numpy()
+    check(oracle_mod, w.U, w.shifts, w.B, X, cols=range(0, n, 23))
