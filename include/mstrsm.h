@@ -24,6 +24,9 @@
  *    offending argument. m == 0 or n == 0 returns MST_OK with nothing enqueued.
  *  - Calls from several host threads are allowed; the error state
  *    (mst_last_bad_arg, mst_last_error) is per thread.
+ *  - With the environment variable MSTRSM_LOG set (to anything but "0") each
+ *    call is reported on stderr with its sizes, and so is each argument or HIP
+ *    error with the name of the call; nothing is synchronised for it.
  */
 #ifndef MSTRSM_H
 #define MSTRSM_H

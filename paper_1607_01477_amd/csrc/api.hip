@@ -18,6 +18,7 @@
 // pass rescales each solved block to the final exponent, so scaling never
 // costs an extra sweep over B while no rescaling happens.
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <vector>
@@ -32,13 +33,32 @@ namespace {
 thread_local int t_bad_arg = 0;
 thread_local char t_err[256] = "";
 
+// MSTRSM_LOG set (and not "0"): every call and every error is reported on
+// stderr (the call's name and sizes; nothing is synchronised)
+bool log_on() {
+    static const bool on = [] {
+        const char* e = getenv("MSTRSM_LOG");
+        return e != nullptr && *e != 0 && strcmp(e, "0") != 0;
+    }();
+    return on;
+}
+thread_local const char* t_entry = "";
+
+void entry(const char* name, int m, int n) {
+    t_bad_arg = 0;
+    t_entry = name;
+    if (log_on()) fprintf(stderr, "[mstrsm] %s m=%d n=%d\n", name, m, n);
+}
+
 mst_status bad(int pos) {
     t_bad_arg = pos;
+    if (log_on()) fprintf(stderr, "[mstrsm] %s: invalid argument %d\n", t_entry, pos);
     return MST_EARG;
 }
 
 mst_status fail_hip(hipError_t e, const char* what) {
     snprintf(t_err, sizeof(t_err), "%s: %s", what, hipGetErrorString(e));
+    if (log_on()) fprintf(stderr, "[mstrsm] %s: %s\n", t_entry, t_err);
     return (e == hipErrorOutOfMemory) ? MST_ENOMEM : MST_EHIP;
 }
 
@@ -587,7 +607,7 @@ extern "C" {
 
 mst_status mstrsm(int m, int n, const void* U, int ldu, const void* shifts, void* B, int ldb,
                   const mst_opts* opt, void* stream) {
-    t_bad_arg = 0;
+    entry("mstrsm", m, n);
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
@@ -605,7 +625,7 @@ mst_status mstrsm(int m, int n, const void* U, int ldu, const void* shifts, void
 mst_status mstrsm_safe(int m, int n, const void* U, int ldu, const void* shifts, void* B, int ldb,
                        const int* col_len, double* scale, int* scale_log2, const mst_opts* opt,
                        void* stream) {
-    t_bad_arg = 0;
+    entry("mstrsm_safe", m, n);
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
@@ -635,7 +655,7 @@ mst_status mstrsm_safe(int m, int n, const void* U, int ldu, const void* shifts,
 
 mst_status mstrsm_adjoint(int m, int n, const void* U, int ldu, const void* shifts, void* G, int ldg,
                           const mst_opts* opt, void* stream) {
-    t_bad_arg = 0;
+    entry("mstrsm_adjoint", m, n);
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
@@ -652,7 +672,7 @@ mst_status mstrsm_adjoint(int m, int n, const void* U, int ldu, const void* shif
 
 mst_status mstrsm_op(int side, int uplo, int op, int m, int n, const void* A, int lda, const void* shifts,
                      void* B, int ldb, const mst_opts* opt, void* stream) {
-    t_bad_arg = 0;
+    entry("mstrsm_op", m, n);
     if (side != 'L' && side != 'R') return bad(1);
     if (uplo != 'U' && uplo != 'L') return bad(2);
     if (op != 'N' && op != 'T' && op != 'C') return bad(3);
@@ -694,7 +714,7 @@ mst_status mstrsm_op(int side, int uplo, int op, int m, int n, const void* A, in
 
 mst_status mstrsm_real(int m, int n, const double* U, int ldu, const double* shifts, double* B, int ldb,
                        const mst_opts* opt, void* stream) {
-    t_bad_arg = 0;
+    entry("mstrsm_real", m, n);
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
@@ -713,7 +733,7 @@ mst_status mstrsm_real(int m, int n, const double* U, int ldu, const double* shi
 
 mst_status mstrsm_real_op(int side, int uplo, int op, int m, int n, const double* A, int lda,
                           const double* shifts, double* B, int ldb, const mst_opts* opt, void* stream) {
-    t_bad_arg = 0;
+    entry("mstrsm_real_op", m, n);
     if (side != 'L' && side != 'R') return bad(1);
     if (uplo != 'U' && uplo != 'L') return bad(2);
     if (op != 'N' && op != 'T' && op != 'C') return bad(3);
@@ -754,7 +774,7 @@ mst_status mstrsm_real_op(int side, int uplo, int op, int m, int n, const double
 
 mst_status mst_grad_u(int m, int n, const void* Y, int ldy, const void* X, int ldx, void* gU, int ldgu,
                       void* stream) {
-    t_bad_arg = 0;
+    entry("mst_grad_u", m, n);
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
@@ -773,7 +793,7 @@ mst_status mst_grad_u(int m, int n, const void* Y, int ldy, const void* X, int l
 
 mst_status mst_grad_shift(int m, int n, const void* X, int ldx, const void* Y, int ldy, void* gshift,
                           void* stream) {
-    t_bad_arg = 0;
+    entry("mst_grad_shift", m, n);
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
@@ -787,7 +807,7 @@ mst_status mst_grad_shift(int m, int n, const void* X, int ldx, const void* Y, i
 
 mst_status mst_residual(int m, int n, const void* U, int ldu, const void* shifts, const void* X, int ldx,
                         const void* B0, int ldb0, void* R, int ldr, void* stream) {
-    t_bad_arg = 0;
+    entry("mst_residual", m, n);
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
@@ -806,7 +826,7 @@ mst_status mst_residual(int m, int n, const void* U, int ldu, const void* shifts
 
 mst_status mst_triang_eig(int m, const void* T, int ldt, void* Z, int ldz, void* eigvals, int* scale_log2,
                           const mst_opts* opt, void* stream) {
-    t_bad_arg = 0;
+    entry("mst_triang_eig", m, m);
     if (m < 0) return bad(1);
     mst_status st;
     if ((st = check_mat(T, ldt, m, m, 2, 3)) != MST_OK) return st;
@@ -832,7 +852,7 @@ mst_status mst_triang_eig(int m, const void* T, int ldt, void* Z, int ldz, void*
 
 mst_status mstrsm_gen(int m, int n, const void* U, int ldu, const void* V, int ldv, const void* shifts,
                       void* B, int ldb, const mst_opts* opt, void* stream) {
-    t_bad_arg = 0;
+    entry("mstrsm_gen", m, n);
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
@@ -852,7 +872,7 @@ mst_status mstrsm_gen(int m, int n, const void* U, int ldu, const void* V, int l
 mst_status mstrsm_safe_gen(int m, int n, const void* U, int ldu, const void* V, int ldv,
                            const void* shifts, void* B, int ldb, const int* col_len, double* scale,
                            int* scale_log2, const mst_opts* opt, void* stream) {
-    t_bad_arg = 0;
+    entry("mstrsm_safe_gen", m, n);
     if (m < 0) return bad(1);
     if (n < 0) return bad(2);
     mst_status st;
@@ -882,7 +902,7 @@ mst_status mstrsm_safe_gen(int m, int n, const void* U, int ldu, const void* V, 
 
 mst_status mst_gen_triang_eig(int m, const void* T, int ldt, const void* S, int lds, void* Z, int ldz,
                               void* eigvals, int* scale_log2, const mst_opts* opt, void* stream) {
-    t_bad_arg = 0;
+    entry("mst_gen_triang_eig", m, m);
     if (m < 0) return bad(1);
     mst_status st;
     if ((st = check_mat(T, ldt, m, m, 2, 3)) != MST_OK) return st;
@@ -909,7 +929,7 @@ mst_status mst_gen_triang_eig(int m, const void* T, int ldt, const void* S, int 
 
 mst_status mst_eig_schur(int m, const void* T, int ldt, const void* Q, int ldq, void* X, int ldx,
                          void* eigvals, int* scale_log2, const mst_opts* opt, void* stream) {
-    t_bad_arg = 0;
+    entry("mst_eig_schur", m, m);
     if (m < 0) return bad(1);
     mst_status st;
     if ((st = check_mat(T, ldt, m, m, 2, 3)) != MST_OK) return st;
@@ -927,7 +947,7 @@ mst_status mst_eig_schur(int m, const void* T, int ldt, const void* Q, int ldq, 
 mst_status mst_gen_eig_schur(int m, const void* T, int ldt, const void* S, int lds, const void* P, int ldp,
                              void* X, int ldx, void* eigvals, int* scale_log2, const mst_opts* opt,
                              void* stream) {
-    t_bad_arg = 0;
+    entry("mst_gen_eig_schur", m, m);
     if (m < 0) return bad(1);
     mst_status st;
     if ((st = check_mat(T, ldt, m, m, 2, 3)) != MST_OK) return st;
@@ -946,7 +966,7 @@ mst_status mst_gen_eig_schur(int m, const void* T, int ldt, const void* S, int l
 mst_status mst_lanczos_sigma_min(int m, int N, const void* U, int ldu, const void* z, void* V, int ldv,
                                  int iters, double* sigma, double* alpha, double* beta, int* steps,
                                  const mst_opts* opt, void* stream) {
-    t_bad_arg = 0;
+    entry("mst_lanczos_sigma_min", m, N);
     if (m < 1) return bad(1);
     if (N < 0) return bad(2);
     mst_status st;

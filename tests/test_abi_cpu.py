@@ -129,3 +129,24 @@ def test_real_op_argument_errors_without_gpu():
     assert lib.mstrsm_real_op(c("L"), c("L"), c("N"), 3, 2, fake, 3, fake, fake, 3, ctypes.byref(o), None) == \
         _lib.MST_EUNSUPPORTED
     assert lib.mstrsm_real_op(c("L"), c("L"), c("C"), 0, 4, None, 1, None, None, 1, None, None) == _lib.MST_OK
+
+
+def test_log_env_reports_calls_and_errors():
+    # MSTRSM_LOG: each call and each argument error on stderr (no GPU call is made)
+    import os
+    import subprocess
+    import sys
+    code = ("import ctypes\n"
+            "from paper_1607_01477_amd import _lib\n"
+            "lib = _lib.load()\n"
+            "lib.mstrsm_real(0, 4, None, 1, None, None, 1, None, None)\n"
+            "lib.mstrsm_real(-1, 4, None, 1, None, None, 1, None, None)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, MSTRSM_LOG="1", PYTHONPATH=root)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "[mstrsm] mstrsm_real m=0 n=4" in r.stderr
+    assert "[mstrsm] mstrsm_real: invalid argument 1" in r.stderr
+    env["MSTRSM_LOG"] = "0"
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+    assert "[mstrsm]" not in r.stderr
