@@ -550,7 +550,7 @@ def main() -> int:
         t1 = time.perf_counter() - t0
         oracle.set_num_threads(cores)
         line["cpu_baseline"] = {"value": round(cg, 3), "unit": "GFLOP/s", "cores": used,
-                                "kind": "oracle",
+                                "kind": "oracle", "cpu_model": cpu_model(),
                                 "sample": "%d of %d shifts of the m=%d workload (%.1f s)" % (ncols, n, m, tc),
                                 "one_thread": {"value": round(oflops(n1) / t1 / 1e9, 3),
                                                "sample": "%d shifts (%.1f s)" % (n1, t1)}}
@@ -589,6 +589,26 @@ def main() -> int:
 
     print(json.dumps(line), flush=True)
     return 0
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.strip().lower().startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.lower().startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":

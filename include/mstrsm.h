@@ -56,8 +56,13 @@ typedef struct {
     int omega_log2;    /* overflow threshold Omega = 2^omega_log2 for the safe solve;
                           default 960 (leaves 2^64 of headroom below DBL_MAX). Smaller
                           values force rescaling at small sizes (testing). Range 8..1000. */
-    int force_phase2;  /* accepted for interface compatibility: the GPU safe solve always
-                          runs the checked back substitution, which gives the same result */
+    int force_phase2;  /* safe solves: 0 (default) or 1. Alg 4 has a fast path (phase 1)
+                          that only decides whether the checked back substitution (phase 2)
+                          can be skipped. Here each diagonal block first runs a speculative
+                          pass with the checks of phase 2 evaluated beside the substitution
+                          and runs the checked steps only when a check fires; 1 skips the
+                          speculative pass so that every block runs the checked steps.
+                          Results are the same bit for bit (tested). */
     int fuse_blocks;   /* 0 (default): an outer block of at most 256 rows is solved by one
                           fused kernel (diagonal blocks plus the substitution between them);
                           -1: one kernel per diagonal block plus separate GEMMs (same
@@ -71,8 +76,13 @@ typedef struct {
                           a second stream of the library, together with that block's
                           diagonal solve, while the GEMM for all rows further up runs on
                           the caller's stream (ordered by events; the call stays
-                          asynchronous on the caller's stream). Results are identical bit
-                          for bit; on MI355X it pays off for nb = 32 only. */
+                          asynchronous on the caller's stream). The rows above each
+                          outer block then receive one product with K = outer_nb per
+                          outer block, where the default path groups four outer blocks
+                          into one deeper product: the same arithmetic in another
+                          summation order, so results agree to rounding, not bit for
+                          bit (safe exponents are the same). On MI355X it pays off
+                          for nb = 32 only. */
     int reserved[1];
 } mst_opts;
 
@@ -338,7 +348,8 @@ mst_status mst_profile_stop(double* ms, double* flops, long long* launches);
 const char* mst_status_string(mst_status s);
 /* 1-based position of the first bad argument of this thread's last MST_EARG. */
 int mst_last_bad_arg(void);
-/* Text of this thread's last MST_EHIP / MST_ENOMEM failure (static storage per thread). */
+/* Text of this thread's last MST_EHIP / MST_ENOMEM / MST_EUNSUPPORTED failure (static
+   storage per thread); every call of the library clears it on entry. */
 const char* mst_last_error(void);
 /* Library version, e.g. "0.1.0". */
 const char* mst_version(void);

@@ -129,7 +129,7 @@ def mstrsm(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2, fuse=Tr
 
 
 def mstrsm_safe(U, shifts, B, col_len=None, *, nb=0, outer_nb=0, omega_log2=0, fuse=True,
-                staged=False, overlap=False):
+                staged=False, overlap=False, force_phase2=False):
     """Safe solve: returns (X, scale, scale_log2) with
     (U - shifts[j] I) X[:, j] = scale[j] B[:, j], scale[j] = 2^-scale_log2[j]."""
     U = _mat(U, "U")
@@ -142,7 +142,7 @@ def mstrsm_safe(U, shifts, B, col_len=None, *, nb=0, outer_nb=0, omega_log2=0, f
     scale = torch.empty(n, dtype=torch.float64, device=X.device)
     klog = torch.empty(n, dtype=torch.int32, device=X.device)
     o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2, fuse=fuse, staged=staged,
-              overlap=overlap)
+              overlap=overlap, force_phase2=force_phase2)
     rc = _lib.load().mstrsm_safe(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), _p(cl), _p(scale),
                                  _p(klog), ctypes.byref(o), _stream())
     _lib.check("mstrsm_safe", rc)
@@ -266,7 +266,7 @@ def residual(U, shifts, X, B0):
     return R
 
 
-def triang_eig(T, *, nb=0, outer_nb=0, omega_log2=0):
+def triang_eig(T, *, nb=0, outer_nb=0, omega_log2=0, force_phase2=False):
     """TriangEig (Alg 6): returns (eigvals, Z, scale_log2) with T Z[:, j] =
     eigvals[j] Z[:, j], Z upper triangular, Z[j, j] = 2^-scale_log2[j]."""
     T = _mat(T, "T")
@@ -276,7 +276,7 @@ def triang_eig(T, *, nb=0, outer_nb=0, omega_log2=0):
     Z = torch.empty_strided((m, m), (1, max(1, m)), dtype=torch.complex128, device=T.device)
     ev = torch.empty(m, dtype=torch.complex128, device=T.device)
     klog = torch.empty(m, dtype=torch.int32, device=T.device)
-    o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2)
+    o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2, force_phase2=force_phase2)
     rc = _lib.load().mst_triang_eig(m, _p(T), _ld(T), _p(Z), max(1, m), _p(ev), _p(klog),
                                     ctypes.byref(o), _stream())
     _lib.check("mst_triang_eig", rc)

@@ -90,6 +90,6 @@ def check(fn: str, rc: int) -> None:
     detail = lib.mst_status_string(rc).decode()
     if rc == MST_EARG:
         detail += " (argument %d)" % lib.mst_last_bad_arg()
-    elif rc in (MST_EHIP, MST_ENOMEM):
+    elif rc in (MST_EHIP, MST_ENOMEM, MST_EUNSUPPORTED):
         detail += " (%s)" % lib.mst_last_error().decode()
     raise MstError(fn, rc, detail)

@@ -46,6 +46,7 @@ thread_local const char* t_entry = "";
 
 void entry(const char* name, int m, int n) {
     t_bad_arg = 0;
+    t_err[0] = 0;
     t_entry = name;
     if (log_on()) fprintf(stderr, "[mstrsm] %s m=%d n=%d\n", name, m, n);
 }
@@ -54,6 +55,13 @@ mst_status bad(int pos) {
     t_bad_arg = pos;
     if (log_on()) fprintf(stderr, "[mstrsm] %s: invalid argument %d\n", t_entry, pos);
     return MST_EARG;
+}
+
+// a valid option combination this entry point does not offer
+mst_status unsupported(const char* why) {
+    snprintf(t_err, sizeof(t_err), "%s", why);
+    if (log_on()) fprintf(stderr, "[mstrsm] %s: unsupported: %s\n", t_entry, why);
+    return MST_EUNSUPPORTED;
 }
 
 mst_status fail_hip(hipError_t e, const char* what) {
@@ -110,6 +118,7 @@ struct Opts {
     bool fuse = true;
     int staged = 0;
     bool overlap = false;
+    bool force_checked = false;
 };
 
 // position of opt in the caller's argument list, for error reporting
@@ -133,6 +142,8 @@ mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
     r.staged = o->gemm_staged;
     if (o->overlap != 0 && o->overlap != 1) return bad(pos);
     r.overlap = o->overlap == 1;
+    if (o->force_phase2 != 0 && o->force_phase2 != 1) return bad(pos);
+    r.force_checked = o->force_phase2 == 1;
     return MST_OK;
 }
 
@@ -275,7 +286,10 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
         // X of outer block ob+1 into the rows of ob, then the solve of ob. The
         // caller's stream S carries the bulk: X of ob into all rows above ob-1.
         // Per element the updates keep their order (outer blocks bottom to
-        // top), so the result is that of the one-stream order bit for bit.
+        // top, one product of K = outer_nb each), so the result is that of a
+        // one-stream loop with one substitution per outer block; the default
+        // one-stream loop below groups outer blocks into deeper products and
+        // therefore differs from this one in summation order (rounding only).
         //   K, substitute(ob+1 -> rows of ob): after S's GEMM of ob+2, the last
         //      earlier writer of those rows;
         //   S, GEMM of ob: after K's solve of ob (it reads X of ob).
@@ -527,7 +541,7 @@ mst_status safe_solve(int m, int n, const zd* U, long ldu, const zd* lam, zd* B,
     HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_colinit(m, n, B, ldb, col_len, G, kcur, s); }));
     SafeState st{};
     st.G = G; st.kcur = kcur; st.kb = kb; st.cn_in = cn_in; st.above_sum = above_sum;
-    st.delta = delta; st.omega_log2 = o.omega_log2;
+    st.delta = delta; st.omega_log2 = o.omega_log2; st.force_checked = o.force_checked ? 1 : 0;
     if (V) {
         // the same sums and zero-pivot replacement for V (pencil bound of Alg 9)
         double *cn_v, *above_v, *colmax_v, *above_sum_v, *delta_v;
@@ -635,7 +649,7 @@ mst_status mstrsm_safe(int m, int n, const void* U, int ldu, const void* shifts,
     if (n > 0 && !scale) return bad(9);
     Opts o;
     if ((st = read_opts(opt, o, 11)) != MST_OK) return st;
-    if (o.precision != 0) return MST_EUNSUPPORTED;
+    if (o.precision != 0) return unsupported("precision 1 is offered by the plain upper solve only");
     if (n == 0) return MST_OK;
     hipStream_t s = (hipStream_t)stream;
     Workspace ws(s);
@@ -664,7 +678,7 @@ mst_status mstrsm_adjoint(int m, int n, const void* U, int ldu, const void* shif
     if ((st = check_mat(G, ldg, m, n, 6, 7)) != MST_OK) return st;
     Opts o;
     if ((st = read_opts(opt, o, 8)) != MST_OK) return st;
-    if (o.precision != 0) return MST_EUNSUPPORTED;
+    if (o.precision != 0) return unsupported("precision 1 is offered by the plain upper solve only");
     if (m == 0 || n == 0) return MST_OK;
     HIPCHK(adjoint_loop(m, n, (const zd*)U, ldu, (const zd*)shifts, (zd*)G, ldg, o, (hipStream_t)stream));
     return MST_OK;
@@ -687,10 +701,10 @@ mst_status mstrsm_op(int side, int uplo, int op, int m, int n, const void* A, in
     // right side: x op(A - l I) = b for the row vector x, i.e. op(A - l I)^T x^T = b^T
     int eop = op;
     if (side == 'R') {
-        if (op == 'C') return MST_EUNSUPPORTED;
+        if (op == 'C') return unsupported("right side with op C is not offered");
         eop = (op == 'N') ? 'T' : 'N';
     }
-    if (o.precision != 0 && !(uplo == 'U' && eop == 'N')) return MST_EUNSUPPORTED;
+    if (o.precision != 0 && !(uplo == 'U' && eop == 'N')) return unsupported("precision 1 is offered by the plain upper solve only");
     if (m == 0 || n == 0) return MST_OK;
     hipStream_t s = (hipStream_t)stream;
     const zd* Az = (const zd*)A;
@@ -723,7 +737,7 @@ mst_status mstrsm_real(int m, int n, const double* U, int ldu, const double* shi
     if ((st = check_mat(B, ldb, m, n, 6, 7)) != MST_OK) return st;
     Opts o;
     if ((st = read_opts(opt, o, 8)) != MST_OK) return st;
-    if (o.precision != 0) return MST_EUNSUPPORTED;
+    if (o.precision != 0) return unsupported("precision 1 is offered by the plain upper solve only");
     const int outer = (opt && opt->outer_nb) ? opt->outer_nb : 256;
     if (outer < 64 || outer % 64) return bad(8);
     if (m == 0 || n == 0) return MST_OK;
@@ -745,7 +759,7 @@ mst_status mstrsm_real_op(int side, int uplo, int op, int m, int n, const double
     if ((st = check_mat(B, ldb, m, n, 9, 10)) != MST_OK) return st;
     Opts o;
     if ((st = read_opts(opt, o, 11)) != MST_OK) return st;
-    if (o.precision != 0) return MST_EUNSUPPORTED;
+    if (o.precision != 0) return unsupported("precision 1 is offered by the plain upper solve only");
     const int outer = (opt && opt->outer_nb) ? opt->outer_nb : 256;
     if (outer < 64 || outer % 64) return bad(11);
     // real data: the conjugate transpose is the transpose; the right side
@@ -834,7 +848,7 @@ mst_status mst_triang_eig(int m, const void* T, int ldt, void* Z, int ldz, void*
     if (m > 0 && !eigvals) return bad(6);
     Opts o;
     if ((st = read_opts(opt, o, 8)) != MST_OK) return st;
-    if (o.precision != 0) return MST_EUNSUPPORTED;
+    if (o.precision != 0) return unsupported("precision 1 is offered by the plain upper solve only");
     if (m == 0) return MST_OK;
     hipStream_t s = (hipStream_t)stream;
     Workspace ws(s);
@@ -862,7 +876,7 @@ mst_status mstrsm_gen(int m, int n, const void* U, int ldu, const void* V, int l
     if ((st = check_mat(B, ldb, m, n, 8, 9)) != MST_OK) return st;
     Opts o;
     if ((st = read_opts(opt, o, 10)) != MST_OK) return st;
-    if (o.nb != 16 || o.precision != 0) return MST_EUNSUPPORTED;
+    if (o.nb != 16 || o.precision != 0) return unsupported("the pencil solves run with nb 16 and precision 0 only");
     if (m == 0 || n == 0) return MST_OK;
     HIPCHK(forward_loop(m, n, (const zd*)U, ldu, nullptr, 0, (const zd*)shifts, (zd*)B, ldb, nullptr, 0, o,
                         nullptr, nullptr, (hipStream_t)stream, (const zd*)V, ldv));
@@ -883,7 +897,7 @@ mst_status mstrsm_safe_gen(int m, int n, const void* U, int ldu, const void* V, 
     if (n > 0 && !scale) return bad(11);
     Opts o;
     if ((st = read_opts(opt, o, 13)) != MST_OK) return st;
-    if (o.nb != 16 || o.precision != 0) return MST_EUNSUPPORTED;
+    if (o.nb != 16 || o.precision != 0) return unsupported("the pencil solves run with nb 16 and precision 0 only");
     if (n == 0) return MST_OK;
     hipStream_t s = (hipStream_t)stream;
     Workspace ws(s);
@@ -911,7 +925,7 @@ mst_status mst_gen_triang_eig(int m, const void* T, int ldt, const void* S, int 
     if (m > 0 && !eigvals) return bad(8);
     Opts o;
     if ((st = read_opts(opt, o, 10)) != MST_OK) return st;
-    if (o.nb != 16 || o.precision != 0) return MST_EUNSUPPORTED;
+    if (o.nb != 16 || o.precision != 0) return unsupported("the pencil solves run with nb 16 and precision 0 only");
     if (m == 0) return MST_OK;
     hipStream_t s = (hipStream_t)stream;
     Workspace ws(s);
@@ -938,7 +952,7 @@ mst_status mst_eig_schur(int m, const void* T, int ldt, const void* Q, int ldq, 
     if (m > 0 && !eigvals) return bad(8);
     Opts o;
     if ((st = read_opts(opt, o, 10)) != MST_OK) return st;
-    if (o.precision != 0) return MST_EUNSUPPORTED;
+    if (o.precision != 0) return unsupported("precision 1 is offered by the plain upper solve only");
     if (m == 0) return MST_OK;
     return eig_from_schur(m, (const zd*)T, ldt, nullptr, 0, (const zd*)Q, ldq, (zd*)X, ldx, (zd*)eigvals,
                           scale_log2, o, (hipStream_t)stream);
@@ -957,7 +971,7 @@ mst_status mst_gen_eig_schur(int m, const void* T, int ldt, const void* S, int l
     if (m > 0 && !eigvals) return bad(10);
     Opts o;
     if ((st = read_opts(opt, o, 12)) != MST_OK) return st;
-    if (o.nb != 16 || o.precision != 0) return MST_EUNSUPPORTED;
+    if (o.nb != 16 || o.precision != 0) return unsupported("the pencil solves run with nb 16 and precision 0 only");
     if (m == 0) return MST_OK;
     return eig_from_schur(m, (const zd*)T, ldt, (const zd*)S, lds, (const zd*)P, ldp, (zd*)X, ldx,
                           (zd*)eigvals, scale_log2, o, (hipStream_t)stream);
@@ -977,7 +991,7 @@ mst_status mst_lanczos_sigma_min(int m, int N, const void* U, int ldu, const voi
     if (N > 0 && !sigma) return bad(9);
     Opts o;
     if ((st = read_opts(opt, o, 13)) != MST_OK) return st;
-    if (o.precision != 0) return MST_EUNSUPPORTED;
+    if (o.precision != 0) return unsupported("precision 1 is offered by the plain upper solve only");
     if (N == 0) return MST_OK;
     hipStream_t s = (hipStream_t)stream;
     Workspace ws(s);

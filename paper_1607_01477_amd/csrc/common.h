@@ -18,6 +18,7 @@ struct SafeState {
     const double* above_sum;  // nblk: sum over the block's columns of max cabs1 above the block
     const double* delta;      // 1: replacement for a zero pivot
     int omega_log2;
+    int force_checked;        // 1: no speculative pass; every diagonal block runs the checked steps
     // pencil (U - lambda V): the same sums and replacement for V; the bound adds
     // cabs1(lambda_j) * above_sum_v and the zero-pivot replacement is max(delta, delta_v)
     const double* above_sum_v;
@@ -85,6 +86,26 @@ struct BlockArgs {
 int block_rows_max();
 bool block_fusable(int nb);   // nb handled by the fused kernel (16 or 32)
 hipError_t launch_block(int ev, const BlockArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- tile order
+// Workgroup -> output tile (tm, tn) of a TM x TN grid, shared by the GEMM
+// kernels. The hardware deals workgroup w to XCD w % 8; when the tile count is
+// a multiple of 8 each XCD gets one contiguous range of the order below, so
+// the workgroups that run together on one XCD share operand panels in its L2.
+// Within the order, row tiles go in groups of GROUP, column by column.
+template <int GROUP = 8>
+__device__ inline void tile_coords(int TM, int TN, int& tm, int& tn) {
+    const int T = TM * TN;
+    int w = blockIdx.x;
+    if ((T & 7) == 0) w = (w & 7) * (T >> 3) + (w >> 3);   // one contiguous range per XCD
+    const int per_group = GROUP * TN;
+    const int gid = w / per_group;
+    const int first = gid * GROUP;
+    const int gsz = min(TM - first, GROUP);
+    const int in = w - gid * per_group;
+    tm = first + in % gsz;
+    tn = in / gsz;
+}
 
 // ---------------------------------------------------------------- MFMA GEMM
 // C(M x N) <- epilogue(acc), acc = A(M x K) * B(K x N), complex.

@@ -359,8 +359,11 @@ struct BlockSolve {
     // U(r,i) - lambda V(r,i) from the two staged blocks (Vs, shift lg), and in
     // the safe form the column norms of the shifted block (Alg 4 on U') are
     // formed here per shift instead of taken from cn_l.
+    // force (safe form): skip the speculative pass and run the checked steps
+    // of Alg 4 directly (the results are the same; kept to test that claim)
     __device__ __forceinline__ void run(const zd* Us, int bs, int r, int base, double cn_l, int w,
-                                        double omega, const zd* Vs = nullptr, zd lg = zd{0.0, 0.0}) {
+                                        double omega, const zd* Vs = nullptr, zd lg = zd{0.0, 0.0},
+                                        bool force = false) {
         auto coef = [&](int i) __attribute__((always_inline)) {
             if constexpr (GEN) return pencil(Us[i * NB + r], Vs[i * NB + r], lg);
             else return Us[i * NB + r];
@@ -409,8 +412,8 @@ struct BlockSolve {
                     b0i[s] = bi[s];
                     G0[s] = Gs[s];
                 }
-                bool flag = false;
-                run16spec<0>(uu, bs, r, cn_l, omega, flag);
+                bool flag = force;
+                if (!force) run16spec<0>(uu, bs, r, cn_l, omega, flag);
                 if (__any(flag)) {
 #pragma unroll
                     for (int s = 0; s < SPW; ++s) {
@@ -434,12 +437,14 @@ struct BlockSolve {
                     b0i[s] = bi[s];
                     G0[s] = Gs[s];
                 }
-                bool flag = false;
-                zd un = Us[(bs - 1) * NB + r];
-                for (int i = bs - 1; i >= 0; --i) {
-                    const zd u = un;
-                    un = Us[(i > 0 ? i - 1 : 0) * NB + r];
-                    step_spec(u, i, r, cn_l, omega, [&](double v) { return bcast<NB>(v, i, base); }, flag);
+                bool flag = force;
+                if (!force) {
+                    zd un = Us[(bs - 1) * NB + r];
+                    for (int i = bs - 1; i >= 0; --i) {
+                        const zd u = un;
+                        un = Us[(i > 0 ? i - 1 : 0) * NB + r];
+                        step_spec(u, i, r, cn_l, omega, [&](double v) { return bcast<NB>(v, i, base); }, flag);
+                    }
                 }
                 redo = __any(flag);
                 if (redo) {
@@ -552,7 +557,7 @@ __global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
         return;
     }
     S.pivots(Ud, r, bs, lam, jv, delta, Vd);
-    S.run(Us, bs, r, base, cn_l, w, omega, Vs, lam[0]);
+    S.run(Us, bs, r, base, cn_l, w, omega, Vs, lam[0], SAFE && a.safe.force_checked);
 
     if (SAFE) {
         const double asum0 = a.safe.above_sum[a.q];
@@ -957,7 +962,7 @@ __global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_bl
             }
             const double cn_l = (SAFE && !GEN && r < g.bs) ? a.safe.cn_in[i0 + r] : 0.0;
             S.pivots(Ud[buf], r, g.bs, lam, jv, delta, Vd[buf]);
-            S.run(Us[buf], g.bs, r, base, cn_l, w, omega, Vs[buf], lam[0]);
+            S.run(Us[buf], g.bs, r, base, cn_l, w, omega, Vs[buf], lam[0], SAFE && a.safe.force_checked);
             if (SAFE) {
                 const double asum0 = a.safe.above_sum[q];
                 const double asumv = GEN ? a.safe.above_sum_v[q] : 0.0;

@@ -52,20 +52,6 @@ template <> struct Traits<float> {
     }
 };
 
-__device__ inline void tile_coords(int TM, int TN, int& tm, int& tn) {
-    const int T = TM * TN;
-    int w = blockIdx.x;
-    if ((T & 7) == 0) w = (w & 7) * (T >> 3) + (w >> 3);   // one contiguous range per XCD
-    constexpr int GROUP = 8;
-    const int per_group = GROUP * TN;
-    const int gid = w / per_group;
-    const int first = gid * GROUP;
-    const int gsz = min(TM - first, GROUP);
-    const int in = w - gid * per_group;
-    tm = first + in % gsz;
-    tn = in / gsz;
-}
-
 // Tile order of -triu(A B^H) on a square grid of TM x TM tiles: the first
 // TM (TM + 1) / 2 workgroups take the tiles on and above the diagonal (row
 // major, dealt out to the XCDs in equal contiguous ranges, since the

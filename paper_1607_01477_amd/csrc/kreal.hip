@@ -25,22 +25,6 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int RNT = 256;            // threads per workgroup
 
-// Workgroup -> tile: groups of 8 row tiles, one contiguous range of tiles per
-// XCD (the hardware deals workgroup w to XCD w % 8).
-__device__ inline void real_tile(int TM, int TN, int& tm, int& tn) {
-    const int T = TM * TN;
-    int w = blockIdx.x;
-    if ((T & 7) == 0) w = (w & 7) * (T >> 3) + (w >> 3);
-    constexpr int GROUP = 8;
-    const int per_group = GROUP * TN;
-    const int gid = w / per_group;
-    const int first = gid * GROUP;
-    const int gsz = min(TM - first, GROUP);
-    const int in = w - gid * per_group;
-    tm = first + in % gsz;
-    tn = in / gsz;
-}
-
 // C(M x N) -= A(M x K) B(K x N), all column-major, K > 0. Four wavefronts in a
 // 2 x 2 arrangement, each with a (16 TI) x (16 TJ) tile of C: TI x TJ products
 // of 16 x 16 x 4 per k-step from TI + TJ operand loads, DEPTH k-steps of
@@ -55,7 +39,7 @@ __global__ __launch_bounds__(RNT) void k_gemm_real(RealGemmArgs g) {
     constexpr int WM = 16 * TI, WN = 16 * TJ, BM = 2 * WM, BN = 2 * WN;
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
     int tm, tn;
-    real_tile(TM, TN, tm, tn);
+    tile_coords(TM, TN, tm, tn);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lq = lane >> 4;
     const int rw = tm * BM + (wave >> 1) * WM, cw = tn * BN + (wave & 1) * WN;

@@ -140,13 +140,21 @@ def test_log_env_reports_calls_and_errors():
             "from paper_1607_01477_amd import _lib\n"
             "lib = _lib.load()\n"
             "lib.mstrsm_real(0, 4, None, 1, None, None, 1, None, None)\n"
-            "lib.mstrsm_real(-1, 4, None, 1, None, None, 1, None, None)\n")
+            "lib.mstrsm_real(-1, 4, None, 1, None, None, 1, None, None)\n"
+            "o = _lib.MstOpts(); o.precision = 1\n"
+            "rc = lib.mstrsm_real(0, 4, None, 1, None, None, 1, ctypes.byref(o), None)\n"
+            "assert rc == _lib.MST_EUNSUPPORTED, rc\n"
+            "assert b'precision 1' in lib.mst_last_error(), lib.mst_last_error()\n"
+            "assert lib.mstrsm_real(0, 4, None, 1, None, None, 1, None, None) == 0\n"
+            "assert lib.mst_last_error() == b'', lib.mst_last_error()\n")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     env = dict(os.environ, MSTRSM_LOG="1", PYTHONPATH=root)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
     assert r.returncode == 0, r.stderr
     assert "[mstrsm] mstrsm_real m=0 n=4" in r.stderr
     assert "[mstrsm] mstrsm_real: invalid argument 1" in r.stderr
+    assert "[mstrsm] mstrsm_real: unsupported: precision 1" in r.stderr
     env["MSTRSM_LOG"] = "0"
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
     assert "[mstrsm]" not in r.stderr
+

@@ -220,6 +220,55 @@ def test_safe_golden_examples(P):
                 assert np.array_equal(X[:, 0], exp.astype(np.complex128)), case["name"]
 
 
+def _bits(X):
+    return np.ascontiguousarray(X).view(np.uint64)
+
+
+@pytest.mark.parametrize("nb,fuse", [(16, True), (32, True), (16, False), (64, False)])
+def test_force_phase2_bit_identical(P, oracle_mod, nb, fuse):
+    """force_phase2 = 1 skips the speculative pass of the safe diagonal blocks
+    (every block runs the checked steps of Alg 4's phase 2); the default runs
+    the speculative pass and redoes a block with the checked steps only when a
+    check fires. Both must give the same X, scales and exponents bit for bit:
+    on inputs where nothing rescales (checked steps never taken by default)
+    and on growth problems that rescale, with and without variable row counts.
+    Fused outer blocks (nb 16, 32) and the per-block kernel (nb 16, 64)."""
+    import torch
+    w = W.c3_mixed(seed=71, m=700, n=150)
+    announce("force_phase2 nb=%d fuse=%s: no rescaling" % (nb, fuse))
+    a = [host(t) for t in P.mstrsm_safe(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, fuse=fuse)]
+    b = [host(t) for t in P.mstrsm_safe(dev(w.U), dev(w.shifts), dev(w.B), nb=nb, fuse=fuse,
+                                        force_phase2=True)]
+    assert np.all(a[2] == 0)
+    assert np.array_equal(_bits(a[0]), _bits(b[0])) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    U, lam, B = _growth(72 + nb, 600, 80)
+    L = W.rng(720 + nb).integers(0, 601, 80).astype(np.int32)
+    for cl in (None, L):
+        announce("force_phase2 nb=%d fuse=%s: growth, col_len=%s" % (nb, fuse, cl is not None))
+        cld = dev(cl, dtype=torch.int32) if cl is not None else None
+        a = [host(t) for t in P.mstrsm_safe(dev(U), dev(lam), dev(B), cld, nb=nb, fuse=fuse,
+                                            omega_log2=40)]
+        b = [host(t) for t in P.mstrsm_safe(dev(U), dev(lam), dev(B), cld, nb=nb, fuse=fuse,
+                                            omega_log2=40, force_phase2=True)]
+        assert np.any(a[2] > 0)
+        assert np.array_equal(_bits(a[0]), _bits(b[0]))
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+        Xo, so, ko = oracle_mod.solve_safe(U, lam, B, col_len=cl, nb=nb, omega_log2=40, force_phase2=True)
+        assert np.array_equal(b[2], ko)
+
+
+def test_force_phase2_triang_eig(P):
+    """TriangEig (Alg 6) on the c2 recipe at m = 600 with Omega = 2^200 (183
+    rescaled columns in the oracle, exact eigenvalue repeats): forced checked
+    steps equal the default bit for bit."""
+    w = W.c2_triang_eig(m=600)
+    announce("force_phase2 triang_eig m=600")
+    e0, Z0, k0 = (host(t) for t in P.triang_eig(dev(w.U), omega_log2=200))
+    e1, Z1, k1 = (host(t) for t in P.triang_eig(dev(w.U), omega_log2=200, force_phase2=True))
+    assert np.any(k0 > 0)
+    assert np.array_equal(_bits(Z0), _bits(Z1)) and np.array_equal(k0, k1)
+
+
 def test_safe_col_len(P, oracle_mod):
     U, lam, B = _growth(41, 260, 64)
     L = W.rng(410).integers(0, 261, 64).astype(np.int32)
