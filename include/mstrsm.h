@@ -122,6 +122,31 @@ mst_status mstrsm_safe(int m, int n, const void* U, int ldu, const void* shifts,
                        const mst_opts* opt, void* stream);
 
 /*
+ * mstrsm_safe_noalloc — mstrsm_safe for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, kernels and results as mstrsm_safe
+ * (bit for bit), but the workspace comes from a static device array of the
+ * library (MST_SCRATCH_LIMIT bytes on each device, held until the process
+ * ends) instead of stream-ordered allocations: the call makes no hipMalloc,
+ * hipMallocAsync or hipFree. The caller still provides U, shifts, B, col_len,
+ * scale and scale_log2.
+ *   Workspace needed, each piece rounded up to 256 bytes: n doubles, n int32,
+ *   ceil(m/nb) * n int32, three times m doubles, ceil(m/nb) doubles and one
+ *   double (about 4.2 MiB at m = n = 4096, nb = 16). A problem that needs more
+ *   than MST_SCRATCH_LIMIT returns MST_ENOMEM before anything is enqueued,
+ *   with the sizes in mst_last_error().
+ *   opt->overlap = 1 (a second stream) gives MST_EUNSUPPORTED.
+ * All calls on one device share that device's array: calls that overlap in
+ * time on one device (several streams or host threads) race and give wrong
+ * results; serialise them. No part of the array needs to start at zero (each
+ * call writes every entry before reading it).
+ */
+#define MST_SCRATCH_LIMIT (16u << 20)
+mst_status mstrsm_safe_noalloc(int m, int n, const void* U, int ldu, const void* shifts,
+                               void* B, int ldb, const int* col_len, double* scale,
+                               int* scale_log2, const mst_opts* opt, void* stream);
+
+/*
  * mstrsm_adjoint — conjugate-transposed multi-shift solve (the lower-triangular
  * forward-substitution variant noted in the footnote to Sec. 2):
  *     (U - shifts[j] I)^H Y(:,j) = G(:,j).

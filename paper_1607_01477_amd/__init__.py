@@ -21,7 +21,7 @@ import torch
 from . import _lib
 from ._lib import MstError, MstOpts
 
-__all__ = ["mstrsm", "mstrsm_safe", "mstrsm_adjoint", "grad_u", "grad_shift", "residual",
+__all__ = ["mstrsm", "mstrsm_safe", "mstrsm_safe_noalloc", "mstrsm_adjoint", "grad_u", "grad_shift", "residual",
            "triang_eig", "lanczos_sigma_min", "mstrsm_gen", "mstrsm_safe_gen", "gen_triang_eig",
            "eig_schur", "gen_eig_schur", "eig", "gen_eig", "mstrsm_op", "mstrsm_real", "mstrsm_real_op",
            "solve", "MultiShiftSolve", "colmajor",
@@ -146,6 +146,31 @@ def mstrsm_safe(U, shifts, B, col_len=None, *, nb=0, outer_nb=0, omega_log2=0, f
     rc = _lib.load().mstrsm_safe(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), _p(cl), _p(scale),
                                  _p(klog), ctypes.byref(o), _stream())
     _lib.check("mstrsm_safe", rc)
+    return X, scale, klog
+
+
+def mstrsm_safe_noalloc(U, shifts, B, col_len=None, *, scale=None, scale_log2=None, nb=0, outer_nb=0,
+                        omega_log2=0, fuse=True, staged=False):
+    """mstrsm_safe without device allocation inside the library: the workspace
+    is the library's static scratch (16 MiB per device; calls that overlap on
+    one device race). scale (float64) and scale_log2 (int32) may be given as
+    preallocated device vectors of n entries; otherwise they are created here.
+    Returns (X, scale, scale_log2)."""
+    U = _mat(U, "U")
+    X = _mat(B, "B")
+    m, n = X.shape
+    if U.shape != (m, m):
+        raise ValueError("U must be %d x %d" % (m, m))
+    s = _vec(shifts, n, "shifts")
+    cl = _vec(col_len, n, "col_len", torch.int32) if col_len is not None else None
+    scale = torch.empty(n, dtype=torch.float64, device=X.device) if scale is None else \
+        _vec(scale, n, "scale", torch.float64)
+    klog = torch.empty(n, dtype=torch.int32, device=X.device) if scale_log2 is None else \
+        _vec(scale_log2, n, "scale_log2", torch.int32)
+    o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2, fuse=fuse, staged=staged)
+    rc = _lib.load().mstrsm_safe_noalloc(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), _p(cl), _p(scale),
+                                         _p(klog), ctypes.byref(o), _stream())
+    _lib.check("mstrsm_safe_noalloc", rc)
     return X, scale, klog
 
 

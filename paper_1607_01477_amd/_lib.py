@@ -13,9 +13,10 @@ _lock = threading.Lock()
 _lib = None
 
 MST_OK, MST_EARG, MST_EHIP, MST_ENOMEM, MST_EUNSUPPORTED = 0, -1, -2, -3, -4
+SCRATCH_LIMIT = 16 << 20   # MST_SCRATCH_LIMIT: bytes of mstrsm_safe_noalloc's static scratch
 
 # every symbol include/mstrsm.h declares
-EXPORTS = ["mstrsm", "mstrsm_safe", "mstrsm_adjoint", "mst_grad_u", "mst_grad_shift",
+EXPORTS = ["mstrsm", "mstrsm_safe", "mstrsm_safe_noalloc", "mstrsm_adjoint", "mst_grad_u", "mst_grad_shift",
            "mst_residual", "mst_triang_eig", "mst_lanczos_sigma_min", "mstrsm_gen",
            "mstrsm_safe_gen", "mst_gen_triang_eig", "mst_eig_schur", "mst_gen_eig_schur", "mstrsm_op",
            "mstrsm_real", "mstrsm_real_op",
@@ -52,6 +53,7 @@ def load():
             sig = {
                 "mstrsm": [I, I, P, I, P, P, I, OP, P],
                 "mstrsm_safe": [I, I, P, I, P, P, I, P, P, P, OP, P],
+                "mstrsm_safe_noalloc": [I, I, P, I, P, P, I, P, P, P, OP, P],
                 "mstrsm_adjoint": [I, I, P, I, P, P, I, OP, P],
                 "mst_grad_u": [I, I, P, I, P, I, P, I, P],
                 "mst_grad_shift": [I, I, P, I, P, I, P, P],

@@ -21,12 +21,20 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "common.h"
 #include "mstrsm.h"
 
 using namespace mst;
+
+// Device memory of the entry point that allocates nothing (mstrsm_safe_noalloc):
+// one copy of this array per device, held until the process ends. Host code
+// never uses its name as an address: the device address comes from
+// hipGetSymbolAddress, once per device (scratch_ptr below).
+#define MST_SCRATCH_BYTES MST_SCRATCH_LIMIT
+static __device__ __align__(256) unsigned char scratch[MST_SCRATCH_BYTES];
 
 namespace {
 
@@ -148,14 +156,30 @@ mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
 }
 
 // Stream-ordered workspace, released on scope exit (also on error paths).
+// With an arena (the static scratch of mstrsm_safe_noalloc) the pieces are
+// carved from it in order, each aligned to 256 bytes, and nothing is
+// allocated or freed.
+constexpr size_t kWsAlign = 256;
+inline size_t ws_round(size_t bytes) { return ((bytes > 0 ? bytes : 16) + kWsAlign - 1) & ~(kWsAlign - 1); }
+
 struct Workspace {
     hipStream_t s;
     std::vector<void*> ptrs;
+    char* arena = nullptr;
+    size_t cap = 0, used = 0;
     explicit Workspace(hipStream_t st) : s(st) {}
+    Workspace(hipStream_t st, void* base, size_t bytes) : s(st), arena((char*)base), cap(bytes) {}
     ~Workspace() {
         for (void* p : ptrs) (void)hipFreeAsync(p, s);
     }
     hipError_t get(size_t bytes, void** out) {
+        if (arena) {
+            const size_t sz = ws_round(bytes);
+            if (used + sz > cap) return hipErrorOutOfMemory;
+            *out = arena + used;
+            used += sz;
+            return hipSuccess;
+        }
         void* p = nullptr;
         hipError_t e = hipMallocAsync(&p, bytes > 0 ? bytes : 16, s);
         if (e != hipSuccess) return e;
@@ -521,6 +545,14 @@ mst_status check_mat(const void* p, int ld, int rows, int cols, int ppos, int ld
     return MST_OK;
 }
 
+// Bytes safe_solve takes from its workspace (without V): the pieces it asks
+// for below, in the same order, each rounded as Workspace rounds them.
+size_t safe_ws_bytes(int m, int n, int nb) {
+    const size_t nblk = (size_t)((m + nb - 1) / nb);
+    return ws_round(n * sizeof(double)) + ws_round(n * sizeof(int)) + ws_round(nblk * n * sizeof(int)) +
+           3 * ws_round(m * sizeof(double)) + ws_round(nblk * sizeof(double)) + ws_round(sizeof(double));
+}
+
 // safe solve into an existing workspace scope
 mst_status safe_solve(int m, int n, const zd* U, long ldu, const zd* lam, zd* B, long ldb,
                       const int* col_len, double* scale, int* klog, const Opts& o, hipStream_t s,
@@ -615,6 +647,28 @@ mst_status eig_from_schur(int m, const zd* T, long ldt, const zd* S, long lds, c
     return MST_OK;
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device (each device holds its own copy of the array at its own address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_ptr(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -655,6 +709,47 @@ mst_status mstrsm_safe(int m, int n, const void* U, int ldu, const void* shifts,
     Workspace ws(s);
     if (m == 0) {
         // no rows: s_j = 1, k_j = 0
+        int* kcur;
+        int* kb;
+        HIPCHK(ws_get(ws, (size_t)n, &kcur));
+        HIPCHK(ws_get(ws, (size_t)n, &kb));
+        HIPCHK(launch_fill_int(n, 0, kcur, s));
+        HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_finalize(0, n, o.nb, (zd*)B, 1, nullptr, kcur, kb, scale, scale_log2, s); }));
+        return MST_OK;
+    }
+    return safe_solve(m, n, (const zd*)U, ldu, (const zd*)shifts, (zd*)B, ldb, col_len, scale,
+                      scale_log2, o, s, ws);
+}
+
+mst_status mstrsm_safe_noalloc(int m, int n, const void* U, int ldu, const void* shifts, void* B, int ldb,
+                               const int* col_len, double* scale, int* scale_log2, const mst_opts* opt,
+                               void* stream) {
+    entry("mstrsm_safe_noalloc", m, n);
+    if (m < 0) return bad(1);
+    if (n < 0) return bad(2);
+    mst_status st;
+    if ((st = check_mat(U, ldu, m, n > 0 ? m : 0, 3, 4)) != MST_OK) return st;
+    if (n > 0 && m > 0 && !shifts) return bad(5);
+    if ((st = check_mat(B, ldb, m, n, 6, 7)) != MST_OK) return st;
+    if (n > 0 && !scale) return bad(9);
+    Opts o;
+    if ((st = read_opts(opt, o, 11)) != MST_OK) return st;
+    if (o.precision != 0) return unsupported("precision 1 is offered by the plain upper solve only");
+    if (o.overlap) return unsupported("overlap = 1 needs a second stream; not offered without allocation");
+    if (n == 0) return MST_OK;
+    // m == 0 takes kcur and kb (n ints each) for the final pass
+    const size_t need = (m == 0) ? 2 * ws_round((size_t)n * sizeof(int)) : safe_ws_bytes(m, n, o.nb);
+    if (need > MST_SCRATCH_BYTES) {
+        snprintf(t_err, sizeof(t_err), "scratch of %zu bytes needed, the limit is %u bytes", need,
+                 (unsigned)MST_SCRATCH_BYTES);
+        if (log_on()) fprintf(stderr, "[mstrsm] %s: %s\n", t_entry, t_err);
+        return MST_ENOMEM;
+    }
+    void* base = nullptr;
+    HIPCHK(scratch_ptr(&base));
+    hipStream_t s = (hipStream_t)stream;
+    Workspace ws(s, base, MST_SCRATCH_BYTES);
+    if (m == 0) {
         int* kcur;
         int* kb;
         HIPCHK(ws_get(ws, (size_t)n, &kcur));

@@ -158,3 +158,29 @@ def test_log_env_reports_calls_and_errors():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
     assert "[mstrsm]" not in r.stderr
 
+
+def test_noalloc_rejections_without_gpu():
+    # mstrsm_safe_noalloc checks its arguments and the size of its static
+    # scratch on the host, before any HIP call
+    from paper_1607_01477_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(4096)   # never dereferenced: the calls return before any HIP call
+    f = lib.mstrsm_safe_noalloc
+    assert f(-1, 2, fake, 3, fake, fake, 3, None, fake, None, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 1
+    assert f(3, 2, fake, 3, fake, fake, 3, None, None, None, None, None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 9
+    o = _lib.MstOpts()
+    o.overlap = 1
+    assert f(3, 2, fake, 3, fake, fake, 3, None, fake, None, ctypes.byref(o), None) == _lib.MST_EUNSUPPORTED
+    o = _lib.MstOpts()
+    o.precision = 1
+    assert f(3, 2, fake, 3, fake, fake, 3, None, fake, None, ctypes.byref(o), None) == _lib.MST_EUNSUPPORTED
+    # m = n = 8192, nb = 16: the per-block exponent record alone is 512 x 8192 int32 = 16 MiB
+    assert f(8192, 8192, fake, 8192, fake, fake, 8192, None, fake, None, None, None) == _lib.MST_ENOMEM
+    msg = lib.mst_last_error().decode()
+    assert "scratch" in msg and str(_lib.SCRATCH_LIMIT) in msg, msg
+    # nb = 64 needs a quarter of that record and fits
+    nb64 = 128 * 8192 * 4 + 2 * 8192 * 8 + 3 * 8192 * 8 + 256 * 3
+    assert nb64 < _lib.SCRATCH_LIMIT
+    assert f(5, 0, fake, 5, fake, fake, 5, None, fake, None, None, None) == _lib.MST_OK
