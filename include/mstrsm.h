@@ -52,7 +52,8 @@ typedef struct {
                           1: substitution GEMMs in FP32 on MFMA (FP32 accumulation),
                              diagonal blocks in FP64, then FP64 iterative refinement
                              on the residual B - (U X - X diag(lambda)). mstrsm only. */
-    int max_sweeps;    /* refinement sweeps for precision 1: 1..3; default 2 */
+    int max_sweeps;    /* most refinement sweeps for precision 1: 1..3; default 2 (see
+                          refine_tol for stopping earlier) */
     int omega_log2;    /* overflow threshold Omega = 2^omega_log2 for the safe solve;
                           default 960 (leaves 2^64 of headroom below DBL_MAX). Smaller
                           values force rescaling at small sizes (testing). Range 8..1000. */
@@ -83,7 +84,20 @@ typedef struct {
                           summation order, so results agree to rounding, not bit for
                           bit (safe exponents are the same). On MI355X it pays off
                           for nb = 32 only. */
-    int reserved[1];
+    int reserved;      /* must be 0 */
+    double refine_tol; /* precision 1: before each sweep the relative residual of every
+                          column, ||(U - l_j I) x_j - b_j||_inf / (||U - l_j I||_inf
+                          ||x_j||_inf) (true modulus), is evaluated on the device; the
+                          remaining sweeps are skipped once the largest is <= refine_tol,
+                          and when a sweep did not lower the largest one, that sweep is
+                          undone and refinement stops. 0 = default 1e-14; negative: never
+                          stop early (but still undo a sweep that raised the residual). */
+    double* refine_report; /* precision 1, nullable device pointer to max_sweeps + 1
+                          doubles: entry t receives the largest relative residual after t
+                          sweeps (t = 0: the FP32-GEMM solve), -1 where not evaluated
+                          (after a stop). When given, the residual after the last sweep
+                          is evaluated too (one more FP64 residual product), so a last
+                          sweep that raised it is also undone. */
 } mst_opts;
 
 /*
@@ -95,9 +109,16 @@ typedef struct {
  *   B, ldb    m x n; on entry the right-hand sides, on exit X
  *   opt       nullable
  * Like xTRSM it does not detect singular or overflowing systems: a zero or
- * subnormal pivot gives Inf/NaN in X. With opt->precision = 1 the result has
- * FP64 accuracy after the refinement sweeps (max_sweeps) but the substitution
- * GEMMs run in FP32.
+ * subnormal pivot gives Inf/NaN in X. With opt->precision = 1 the substitution
+ * GEMMs run in FP32 and FP64 iterative refinement on the residual brings the
+ * result to FP64 accuracy (refine_tol, max_sweeps, refine_report). Each right-
+ * hand side (and each residual) is scaled by an exact power of two before it
+ * is rounded to FP32, so B of any magnitude is safe; U's entries must lie in
+ * FP32's range (|Re|, |Im| < 2^128; smaller entries than 2^-126 lose digits in
+ * the FP32 copy, which refinement makes up for). The refinement converges when
+ * the FP32 solve is accurate to better than one digit, roughly when
+ * cond(U - l_j I) < 10^6; otherwise it stops as described for refine_tol, and
+ * refine_report shows the residual reached.
  */
 mst_status mstrsm(int m, int n, const void* U, int ldu, const void* shifts,
                   void* B, int ldb, const mst_opts* opt, void* stream);

@@ -35,8 +35,10 @@ def version() -> str:
 
 
 def _opts(nb=0, outer_nb=0, precision=0, max_sweeps=0, omega_log2=0, force_phase2=0, fuse=True,
-          staged=False, overlap=False):
+          staged=False, overlap=False, refine_tol=0.0, refine_report=None):
     o = MstOpts()
+    o.refine_tol = float(refine_tol)
+    o.refine_report = refine_report.data_ptr() if refine_report is not None else None
     o.overlap = 1 if overlap else 0
     o.gemm_staged = 1 if staged else 0
     o.nb, o.outer_nb, o.precision = int(nb), int(outer_nb), int(precision)
@@ -111,18 +113,27 @@ def _mat(t: torch.Tensor, name: str) -> torch.Tensor:
 
 
 def mstrsm(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2, fuse=True, staged=False,
-           overlap=False):
+           overlap=False, refine_tol=0.0, refine_report=None):
     """X with (U - shifts[j] I) X[:, j] = B[:, j]; B is overwritten when it is
     already column-major complex128 (the result is returned either way).
-    precision=1: FP32 substitution GEMMs + FP64 refinement (max_sweeps)."""
+    precision=1: FP32 substitution GEMMs + FP64 refinement, at most max_sweeps
+    sweeps, stopping once the largest relative residual is <= refine_tol (0:
+    the library's default 1e-14; negative: never early). refine_report: an
+    optional float64 device tensor of max_sweeps + 1 entries that receives the
+    largest relative residual after each sweep (-1 where not evaluated)."""
     U = _mat(U, "U")
     X = _mat(B, "B")
     m, n = X.shape
     if U.shape != (m, m):
         raise ValueError("U must be %d x %d" % (m, m))
     s = _vec(shifts, n, "shifts")
+    if refine_report is not None:
+        if (refine_report.dtype != torch.float64 or not refine_report.is_contiguous()
+                or refine_report.numel() != max_sweeps + 1 or not refine_report.is_cuda):
+            raise ValueError("refine_report must be a contiguous float64 device tensor of %d entries"
+                             % (max_sweeps + 1))
     o = _opts(nb=nb, outer_nb=outer_nb, precision=precision, max_sweeps=max_sweeps, fuse=fuse,
-              staged=staged, overlap=overlap)
+              staged=staged, overlap=overlap, refine_tol=refine_tol, refine_report=refine_report)
     rc = _lib.load().mstrsm(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), ctypes.byref(o), _stream())
     _lib.check("mstrsm", rc)
     return X

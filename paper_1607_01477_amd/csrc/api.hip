@@ -127,6 +127,9 @@ struct Opts {
     int staged = 0;
     bool overlap = false;
     bool force_checked = false;
+    double refine_tol = 1e-14;
+    double* report = nullptr;
+    const int* skip = nullptr;   // set internally: the refinement loop's stop flag
 };
 
 // position of opt in the caller's argument list, for error reporting
@@ -152,6 +155,10 @@ mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
     r.overlap = o->overlap == 1;
     if (o->force_phase2 != 0 && o->force_phase2 != 1) return bad(pos);
     r.force_checked = o->force_phase2 == 1;
+    if (o->reserved != 0) return bad(pos);
+    if (o->refine_tol != 0.0) r.refine_tol = o->refine_tol;
+    if (r.refine_tol != r.refine_tol) return bad(pos);   // NaN
+    r.report = o->refine_report;
     return MST_OK;
 }
 
@@ -280,6 +287,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
         g.A = U32 + (long)x0 * ldu32 + r0; g.lda = ldu32;
         g.B = W32 + x0; g.ldb = ldw;
         g.C = W32 + r0; g.ldc = ldw;
+        g.skip = o.skip;
         return timed(MST_PROF_GEMM_F32, gemm_flops(g), st, [&] { return launch_gemm_f32(g, st); });
     };
     auto substitute = [&](int ob, int r0, int r1, hipStream_t st) -> hipError_t {
@@ -294,6 +302,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
         b.U = U; b.ldu = ldu; b.lam = lam; b.B = B; b.ldb = ldb;
         b.V = V; b.ldv = ldv;
         b.b32 = mixed ? W32 : nullptr; b.ldb32 = ldw;
+        b.skip = mixed ? o.skip : nullptr;
         b.col_len = col_len;
         if (safe) {
             b.safe = *safe;
@@ -356,6 +365,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             d.U = U; d.ldu = ldu; d.lam = lam; d.B = B; d.ldb = ldb;
             d.V = V; d.ldv = ldv;
             d.b32 = mixed ? W32 : nullptr; d.ldb32 = ldw;
+            d.skip = mixed ? o.skip : nullptr;
             d.col_len = col_len;
             if (safe) {
                 d.safe = *safe;
@@ -387,6 +397,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
                     g.A = U32 + (long)i0 * ldu32 + qa * nb; g.lda = ldu32;
                     g.B = W32 + i0; g.ldb = ldw;
                     g.C = W32 + qa * nb; g.ldc = ldw;
+                    g.skip = o.skip;
                     e = timed(MST_PROF_GEMM_F32, gemm_flops(g), s, [&] { return launch_gemm_f32(g, s); });
                 }
                 if (e != hipSuccess) return e;
@@ -479,8 +490,10 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
 }
 
 hipError_t residual(int m, int n, const zd* U, long ldu, const zd* lam, const zd* X, long ldx,
-                    const zd* B0, long ldb0, zd* R, long ldr, hipStream_t s, int staged = 0) {
+                    const zd* B0, long ldb0, zd* R, long ldr, hipStream_t s, int staged = 0,
+                    const int* skip = nullptr) {
     GemmArgs g{};
+    g.skip = skip;
     g.M = m; g.N = n; g.K = m; g.op = GOP_RESID; g.staged = staged;
     g.A = U; g.lda = ldu;
     g.B = X; g.ldb = ldx;
@@ -597,23 +610,69 @@ mst_status plain_solve(int m, int n, const zd* U, long ldu, const zd* lam, zd* B
         HIPCHK(forward_loop(m, n, U, ldu, nullptr, 0, lam, B, ldb, nullptr, 0, o, nullptr, nullptr, s));
         return MST_OK;
     }
-    // FP32 substitution GEMMs, FP64 diagonal blocks, FP64 refinement
+    // FP32 substitution GEMMs, FP64 diagonal blocks, FP64 iterative refinement.
+    // Every right-hand side is brought near 1 by an exact power of two per
+    // column before it is rounded to FP32 (the solve is linear: the solution
+    // carries the same factor, removed when it is added to X). The stop test
+    // and the undo of a sweep that raised the residual run on the device
+    // (RefineCtl), so the call stays asynchronous; the undo restores a copy of
+    // the iterate taken before the sweep.
+    const int S = o.sweeps;
+    const int nch = (m + kRowChunk - 1) / kRowChunk;
     zf *U32, *W32;
-    zd *B0, *R;
+    zd *B0, *R, *Xp, *udiag;
+    double *part, *rowoff, *rel;
+    int *einit, *ebuf;
+    RefineCtl* ctl;
     HIPCHK(ws_get(ws, (size_t)m * m, &U32));
     HIPCHK(ws_get(ws, (size_t)m * n, &W32));
     HIPCHK(ws_get(ws, (size_t)m * n, &B0));
     HIPCHK(ws_get(ws, (size_t)m * n, &R));
-    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_to_f32(m, m, U, ldu, U32, m, true, s); }));
-    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_copy(m, n, B, ldb, B0, m, s); }));
-    HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_to_f32(m, n, B, ldb, W32, m, false, s); }));
+    HIPCHK(ws_get(ws, (size_t)m * n, &Xp));
+    HIPCHK(ws_get(ws, (size_t)m, &udiag));
+    HIPCHK(ws_get(ws, (size_t)nch * m, &part));
+    HIPCHK(ws_get(ws, (size_t)m, &rowoff));
+    HIPCHK(ws_get(ws, (size_t)n, &rel));
+    HIPCHK(ws_get(ws, (size_t)n, &einit));
+    HIPCHK(ws_get(ws, (size_t)2 * n, &ebuf));
+    HIPCHK(ws_get(ws, (size_t)1, &ctl));
+    Opts om = o;
+    om.skip = &ctl->stop;
+    const int* stop = &ctl->stop;
+    auto aux = [&](auto&& f) { return timed(MST_PROF_AUX, 0.0, s, f); };
+    HIPCHK(aux([&] { return launch_refine_init(ctl, o.report, S + 1, s); }));
+    HIPCHK(aux([&] { return launch_to_f32(m, m, U, ldu, U32, m, true, s); }));
+    HIPCHK(aux([&] { return launch_rowabs(m, U, ldu, part, rowoff, udiag, s); }));
+    HIPCHK(aux([&] { return launch_copy(m, n, B, ldb, B0, m, s); }));
+    // X0: the FP32-GEMM solve of 2^-e B, then X0 = 2^e (that solution)
+    HIPCHK(aux([&] { return launch_colstats(m, n, B, ldb, nullptr, 0, rowoff, udiag, lam, einit, rel, nullptr, s); }));
+    HIPCHK(aux([&] { return launch_to_f32_cols(m, n, B, ldb, einit, W32, m, nullptr, s); }));
     HIPCHK(forward_loop(m, n, U, ldu, U32, m, lam, B, ldb, W32, m, o, nullptr, nullptr, s));
-    for (int sw = 0; sw < o.sweeps; ++sw) {
-        HIPCHK(residual(m, n, U, ldu, lam, B, ldb, B0, m, R, m, s, o.staged));
-        HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_to_f32(m, n, R, m, W32, m, false, s); }));
-        HIPCHK(forward_loop(m, n, U, ldu, U32, m, lam, R, m, W32, m, o, nullptr, nullptr, s));
-        HIPCHK(timed(MST_PROF_AUX, 0.0, s, [&] { return launch_axpy_inplace(m, n, R, m, B, ldb, s); }));
+    HIPCHK(aux([&] { return launch_scale_cols(m, n, B, ldb, einit, s); }));
+    // The residual of iterate t into R, its test, and the undo of sweep t when
+    // it raised the residual. The exponents for the next correction go to the
+    // half of ebuf that sweep t did not use.
+    auto check = [&](int t) -> hipError_t {
+        hipError_t e = residual(m, n, U, ldu, lam, B, ldb, B0, m, R, m, s, o.staged, stop);
+        if (e != hipSuccess) return e;
+        int* et = ebuf + (size_t)((t + 1) & 1) * n;
+        if ((e = aux([&] { return launch_colstats(m, n, R, m, B, ldb, rowoff, udiag, lam, et, rel, stop, s); })) != hipSuccess)
+            return e;
+        if ((e = aux([&] { return launch_refine_ctl(n, t, rel, o.refine_tol, ctl, o.report, s); })) != hipSuccess)
+            return e;
+        if (t == 0) return hipSuccess;
+        return aux([&] { return launch_copy_cond(m, n, Xp, m, B, ldb, nullptr, &ctl->rb[t], s); });
+    };
+    for (int sw = 1; sw <= S; ++sw) {
+        HIPCHK(check(sw - 1));
+        // correction: solve (U - lam I) D = R with 2^-e R in FP32 (D into R), X += 2^e D
+        const int* es = ebuf + (size_t)(sw & 1) * n;
+        HIPCHK(aux([&] { return launch_to_f32_cols(m, n, R, m, es, W32, m, stop, s); }));
+        HIPCHK(forward_loop(m, n, U, ldu, U32, m, lam, R, m, W32, m, om, nullptr, nullptr, s));
+        HIPCHK(aux([&] { return launch_copy_cond(m, n, B, ldb, Xp, m, stop, nullptr, s); }));
+        HIPCHK(aux([&] { return launch_axpy_cols(m, n, R, m, es, 1.0, B, ldb, stop, nullptr, s); }));
     }
+    if (o.report) HIPCHK(check(S));
     return MST_OK;
 }
 

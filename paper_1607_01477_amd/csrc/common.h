@@ -65,6 +65,7 @@ struct DiagArgs {
     const int* col_len;
     SafeState safe;
     int use_safe;
+    const int* skip;   // mixed precision: nothing is done when *skip != 0 (nullable)
 };
 hipError_t launch_diag(int nb, int ev, const DiagArgs& a, hipStream_t s);
 
@@ -82,6 +83,7 @@ struct BlockArgs {
     const int* col_len;
     SafeState safe;
     int use_safe;
+    const int* skip;   // mixed precision: nothing is done when *skip != 0 (nullable)
 };
 int block_rows_max();
 bool block_fusable(int nb);   // nb handled by the fused kernel (16 or 32)
@@ -135,6 +137,8 @@ struct GemmArgs {
     int staged;
     // GOP_GEN_SUB: second A operand (plain, same shape as A) and the shift of each column
     const void* A2; long lda2; const zd* glam;
+    // FP32 substitution and FP64 residual (refinement): nothing is done when *skip != 0
+    const int* skip;
 };
 hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s);
 hipError_t launch_gemm_f32(const GemmArgs& g, hipStream_t s);
@@ -195,6 +199,51 @@ hipError_t launch_lanczos_step(int m, int n, int it, int iters, const zd* V, lon
                                zd* W, long ldw, const zd* Vprev, long ldp,
                                double* alpha, double* beta, int* steps, hipStream_t s);
 hipError_t launch_fill_int(int n, int v, int* p, hipStream_t s);
+
+// ---------------------------------------------------------------- iterative refinement
+// State of the refinement loop of the mixed-precision solve, kept on the device
+// so that the stop test and the undo of a sweep run as kernels (the call stays
+// asynchronous). stop: later sweeps do nothing; rb[t]: sweep t raised the
+// residual and is undone; prev: residual of the last iterate tested.
+constexpr int kMaxSweeps = 3;
+struct RefineCtl {
+    int stop;
+    int rb[kMaxSweeps + 1];
+    double prev;
+};
+constexpr int kRowChunk = 128;   // columns per partial row sum
+// rowoff[i] = sum_{k > i} |U(i,k)| (true modulus; fixed order: chunks of kRowChunk
+// columns, then the chunks in order); udiag[i] = U(i,i). part: ceil(m/kRowChunk) * m doubles.
+hipError_t launch_rowabs(int m, const zd* U, long ldu, double* part, double* rowoff, zd* udiag,
+                         hipStream_t s);
+// Per column j of R (m x n): e[j] = ilogb(max_i |R(i,j)|_1) (0 for a zero or non-finite
+// column), so that 2^-e[j] R(:,j) has entries below 2 in each part; with X given also
+//   rel[j] = max_i |R(i,j)| / (max_i (rowoff[i] + |udiag[i] - lam_j|) max_i |X(i,j)|)
+// (true modulus; the absolute residual where X(:,j) = 0; +inf where R or X holds a
+// non-finite value). Nothing is done when skip && *skip.
+hipError_t launch_colstats(int m, int n, const zd* R, long ldr, const zd* X, long ldx,
+                           const double* rowoff, const zd* udiag, const zd* lam, int* e, double* rel,
+                           const int* skip, hipStream_t s);
+// dst(r, c) = fp32(2^-e[c] src(r, c)), unless skip && *skip
+hipError_t launch_to_f32_cols(int rows, int cols, const zd* src, long lds, const int* e, zf* dst,
+                              long ldd, const int* skip, hipStream_t s);
+// X(r, c) += sign 2^e[c] D(r, c); nothing is done when skip && *skip, or when
+// cond && *cond != 1
+hipError_t launch_axpy_cols(int rows, int cols, const zd* D, long ldd, const int* e, double sign,
+                            zd* X, long ldx, const int* skip, const int* cond, hipStream_t s);
+// dst = src, unless skip && *skip, or cond && *cond != 1
+hipError_t launch_copy_cond(int rows, int cols, const zd* src, long lds, zd* dst, long ldd,
+                            const int* skip, const int* cond, hipStream_t s);
+// X(r, c) = 2^e[c] X(r, c)
+hipError_t launch_scale_cols(int rows, int cols, zd* X, long ldx, const int* e, hipStream_t s);
+// ctl: stop = 0, rb = 0, prev = +inf; report[0..nrep) = -1 (report nullable)
+hipError_t launch_refine_init(RefineCtl* ctl, double* report, int nrep, hipStream_t s);
+// After the residual of iterate t (t = 0: the FP32 solve; rel from launch_colstats):
+// res = max_j rel[j]; report[t] = res; stop when res <= tol; when t > 0 and res is
+// not below the previous iterate's, stop and set rb[t] (undo sweep t). Nothing is
+// done once stop is set.
+hipError_t launch_refine_ctl(int n, int t, const double* rel, double tol, RefineCtl* ctl,
+                             double* report, hipStream_t s);
 hipError_t launch_zero(long count, zd* p, hipStream_t s);
 hipError_t launch_tridiag_max(int n, int iters, const double* alpha, const double* beta,
                               const int* steps, double* sigma, hipStream_t s);

@@ -321,6 +321,150 @@ __global__ __launch_bounds__(256) void k_zero(long count, zd* p) {
         p[e] = zd{0.0, 0.0};
 }
 
+// ---------------------------------------------------------------- iterative refinement
+
+__device__ inline double cmod(zd z) { return hypot(z.re, z.im); }
+
+// partial row sums of |U(i,k)|, k > i, over the column chunk blockIdx.y
+__global__ __launch_bounds__(256) void k_rowabs_part(int m, const zd* U, long ldu, double* part) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int c0 = blockIdx.y * kRowChunk, c1 = min(m, c0 + kRowChunk);
+    double acc = 0.0;
+    for (int c = max(c0, i + 1); c < c1; ++c) acc += cmod(U[(long)c * ldu + i]);
+    part[(long)blockIdx.y * m + i] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_rowabs_sum(int m, int nch, const zd* U, long ldu,
+                                                    const double* part, double* rowoff, zd* udiag) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    double acc = 0.0;
+    for (int ch = 0; ch < nch; ++ch) acc += part[(long)ch * m + i];
+    rowoff[i] = acc;
+    udiag[i] = U[(long)i * ldu + i];
+}
+
+__global__ __launch_bounds__(256) void k_colstats(int m, const zd* R, long ldr, const zd* X, long ldx,
+                                                  const double* rowoff, const zd* udiag, const zd* lam,
+                                                  int* e, double* rel, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double sh[8];
+    const int j = blockIdx.x;
+    const zd* rc = R + (long)j * ldr;
+    double c1 = 0.0, rm = 0.0, xm = 0.0, am = 0.0;
+    bool bad = false;
+    const zd lj = X ? lam[j] : zd{0.0, 0.0};
+    for (int r = threadIdx.x; r < m; r += 256) {
+        const zd v = rc[r];
+        const double a = cabs1(v);
+        bad = bad || !isfinite(a);
+        c1 = fmax(c1, a);
+        if (X) {
+            const zd x = X[(long)j * ldx + r];
+            bad = bad || !isfinite(cabs1(x));
+            rm = fmax(rm, cmod(v));
+            xm = fmax(xm, cmod(x));
+            const zd d = udiag[r];
+            am = fmax(am, rowoff[r] + cmod(zd{d.re - lj.re, d.im - lj.im}));
+        }
+    }
+    c1 = block_max<256>(c1, sh);
+    const double fb = block_max<256>(bad ? 1.0 : 0.0, sh);
+    if (X) {
+        rm = block_max<256>(rm, sh);
+        xm = block_max<256>(xm, sh);
+        am = block_max<256>(am, sh);
+    }
+    if (threadIdx.x == 0) {
+        const bool ok = fb == 0.0;
+        e[j] = (ok && c1 > 0.0) ? ilogb(c1) : 0;
+        if (X) {
+            double q = xm > 0.0 ? rm / (am * xm) : rm;
+            if (!ok || !(q >= 0.0) || !isfinite(am)) q = INFINITY;
+            rel[j] = q;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_to_f32_cols(int rows, int cols, const zd* src, long lds,
+                                                     const int* e, zf* dst, long ldd, const int* skip) {
+    if (skip && *skip) return;
+    const long total = (long)rows * cols;
+    for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+        const int c = (int)(t / rows), r = (int)(t - (long)c * rows);
+        const zd v = src[(long)c * lds + r];
+        const int k = e[c];
+        dst[(long)c * ldd + r] = zf{(float)ldexp(v.re, -k), (float)ldexp(v.im, -k)};
+    }
+}
+
+__global__ __launch_bounds__(256) void k_axpy_cols(int rows, int cols, const zd* D, long ldd,
+                                                   const int* e, double sign, zd* X, long ldx,
+                                                   const int* skip, const int* cond) {
+    if (skip && *skip) return;
+    if (cond && *cond != 1) return;
+    const long total = (long)rows * cols;
+    for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+        const int c = (int)(t / rows), r = (int)(t - (long)c * rows);
+        const zd d = D[(long)c * ldd + r];
+        const int k = e[c];
+        zd* p = &X[(long)c * ldx + r];
+        const zd x = *p;
+        *p = zd{x.re + sign * ldexp(d.re, k), x.im + sign * ldexp(d.im, k)};
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy_cond(int rows, int cols, const zd* src, long lds, zd* dst,
+                                                   long ldd, const int* skip, const int* cond) {
+    if (skip && *skip) return;
+    if (cond && *cond != 1) return;
+    const long total = (long)rows * cols;
+    for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+        const int c = (int)(t / rows), r = (int)(t - (long)c * rows);
+        dst[(long)c * ldd + r] = src[(long)c * lds + r];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scale_cols(int rows, int cols, zd* X, long ldx, const int* e) {
+    const long total = (long)rows * cols;
+    for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+        const int c = (int)(t / rows), r = (int)(t - (long)c * rows);
+        zd* p = &X[(long)c * ldx + r];
+        const zd x = *p;
+        *p = zd{ldexp(x.re, e[c]), ldexp(x.im, e[c])};
+    }
+}
+
+__global__ __launch_bounds__(64) void k_refine_init(RefineCtl* ctl, double* report, int nrep) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        ctl->stop = 0;
+        for (int i = 0; i <= kMaxSweeps; ++i) ctl->rb[i] = 0;
+        ctl->prev = INFINITY;
+    }
+    if (report && t < nrep) report[t] = -1.0;
+}
+
+__global__ __launch_bounds__(256) void k_refine_ctl(int n, int t, const double* rel, double tol,
+                                                    RefineCtl* ctl, double* report) {
+    __shared__ double sh[8];
+    if (ctl->stop) return;
+    double v = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) v = fmax(v, rel[j]);
+    const double res = block_max<256>(v, sh);
+    if (threadIdx.x == 0) {
+        if (report) report[t] = res;
+        if (res <= tol) {
+            ctl->stop = 1;
+        } else if (t > 0 && !(res < ctl->prev)) {
+            ctl->stop = 1;
+            ctl->rb[t] = 1;
+        }
+        ctl->prev = res;
+    }
+}
+
 inline int grid_for(long total) {
     long g = (total + 255) / 256;
     return (int)(g > 65536 ? 65536 : (g < 1 ? 1 : g));
@@ -335,6 +479,61 @@ hipError_t launch_fill_int(int n, int v, int* p, hipStream_t s) {
 
 hipError_t launch_zero(long count, zd* p, hipStream_t s) {
     hipLaunchKernelGGL(k_zero, dim3(grid_for(count)), dim3(256), 0, s, count, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowabs(int m, const zd* U, long ldu, double* part, double* rowoff, zd* udiag,
+                         hipStream_t s) {
+    const int nch = (m + kRowChunk - 1) / kRowChunk;
+    hipLaunchKernelGGL(k_rowabs_part, dim3((m + 255) / 256, nch), dim3(256), 0, s, m, U, ldu, part);
+    hipLaunchKernelGGL(k_rowabs_sum, dim3((m + 255) / 256), dim3(256), 0, s, m, nch, U, ldu, part, rowoff,
+                       udiag);
+    return hipGetLastError();
+}
+
+hipError_t launch_colstats(int m, int n, const zd* R, long ldr, const zd* X, long ldx,
+                           const double* rowoff, const zd* udiag, const zd* lam, int* e, double* rel,
+                           const int* skip, hipStream_t s) {
+    hipLaunchKernelGGL(k_colstats, dim3(n), dim3(256), 0, s, m, R, ldr, X, ldx, rowoff, udiag, lam, e, rel,
+                       skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32_cols(int rows, int cols, const zd* src, long lds, const int* e, zf* dst,
+                              long ldd, const int* skip, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_f32_cols, dim3(grid_for((long)rows * cols)), dim3(256), 0, s, rows, cols, src,
+                       lds, e, dst, ldd, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_cols(int rows, int cols, const zd* D, long ldd, const int* e, double sign,
+                            zd* X, long ldx, const int* skip, const int* cond, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_cols, dim3(grid_for((long)rows * cols)), dim3(256), 0, s, rows, cols, D, ldd,
+                       e, sign, X, ldx, skip, cond);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_cond(int rows, int cols, const zd* src, long lds, zd* dst, long ldd,
+                            const int* skip, const int* cond, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_cond, dim3(grid_for((long)rows * cols)), dim3(256), 0, s, rows, cols, src, lds,
+                       dst, ldd, skip, cond);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_cols(int rows, int cols, zd* X, long ldx, const int* e, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_cols, dim3(grid_for((long)rows * cols)), dim3(256), 0, s, rows, cols, X, ldx,
+                       e);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_init(RefineCtl* ctl, double* report, int nrep, hipStream_t s) {
+    hipLaunchKernelGGL(k_refine_init, dim3(1), dim3(64), 0, s, ctl, report, nrep);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_ctl(int n, int t, const double* rel, double tol, RefineCtl* ctl,
+                             double* report, hipStream_t s) {
+    hipLaunchKernelGGL(k_refine_ctl, dim3(1), dim3(256), 0, s, n, t, rel, tol, ctl, report);
     return hipGetLastError();
 }
 

@@ -495,6 +495,7 @@ struct BlockSolve {
 template <int NB, int SPW, int EV, bool SAFE, bool MIXED, bool VARLEN, bool GEN = false>
 __global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
     static_assert(!GEN || (NB == 16 && EV == 0 && !MIXED), "pencil: nb 16, upper, op N, FP64");
+    if (MIXED && a.skip && *a.skip) return;   // refinement stopped
     __shared__ zd Us[NB * NB];
     __shared__ zd Ud[NB];
     __shared__ zd Vs[GEN ? NB * NB : 1];
@@ -660,6 +661,7 @@ __global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_bl
     __shared__ int kcl[kCols], dkl[2][kCols], Ll[kCols];
     __shared__ int tctr[2];        // next update tile to claim, per pass parity
 
+    if (MIXED && a.skip && *a.skip) return;   // refinement stopped
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col0 = blockIdx.x * kCols;
     const int iS = a.iS, rows = a.rows;

@@ -94,6 +94,7 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(GemmArgs g) {
     __shared__ CT As[2][BK][BM + PAD];
     __shared__ CT Bs[2][BK][BN + PAD];
 
+    if ((sizeof(T) == 4 || OP == GOP_RESID) && g.skip && *g.skip) return;   // refinement stopped
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
     int tm, tn;
     tile_coords(TM, TN, tm, tn);
@@ -350,6 +351,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
     using Tr = Traits<T>;
     using CT = typename Tr::C;
     using V = typename Tr::V;
+    if ((sizeof(T) == 4 || RES) && g.skip && *g.skip) return;   // refinement stopped
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
     int tm, tn;
     if (TRI) {

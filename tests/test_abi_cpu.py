@@ -48,6 +48,25 @@ def test_argument_errors_without_gpu():
     assert lib.mst_status_string(_lib.MST_EARG).decode().startswith("MST_EARG")
 
 
+def test_option_errors_without_gpu():
+    # mst_opts.reserved must be 0 and refine_tol must not be NaN (checked on the host)
+    from paper_1607_01477_amd import _lib
+    lib = _lib.load()
+    o = _lib.MstOpts()
+    o.reserved = 1
+    assert lib.mstrsm(0, 7, None, 1, None, None, 1, ctypes.byref(o), None) == _lib.MST_EARG
+    assert lib.mst_last_bad_arg() == 8
+    o = _lib.MstOpts()
+    o.refine_tol = float("nan")
+    assert lib.mstrsm(0, 7, None, 1, None, None, 1, ctypes.byref(o), None) == _lib.MST_EARG
+    o = _lib.MstOpts()
+    o.refine_tol = -1.0
+    o.max_sweeps = 3
+    assert lib.mstrsm(0, 7, None, 1, None, None, 1, ctypes.byref(o), None) == _lib.MST_OK
+    o.max_sweeps = 4
+    assert lib.mstrsm(0, 7, None, 1, None, None, 1, ctypes.byref(o), None) == _lib.MST_EARG
+
+
 def test_generalized_argument_errors_without_gpu():
     from paper_1607_01477_amd import _lib
     lib = _lib.load()
