@@ -371,6 +371,39 @@ mst_status mst_lanczos_sigma_min(int m, int N, const void* U, int ldu, const voi
                                  const mst_opts* opt, void* stream);
 
 /*
+ * mst_lanczos_restart_sigma_min — the second stage of Alg 7 (Sec. 5) with a
+ * restarted Krylov method and a per-shift tolerance (the paper's runs used
+ * implicitly restarted Arnoldi; on the Hermitian positive definite operator
+ * A_j = (U - z_j I)^{-H} (U - z_j I)^{-1} that is thick-restart Lanczos).
+ * For every shift: cycles of Lanczos steps with full reorthogonalisation
+ * (classical Gram-Schmidt, two passes) build a basis of kdim vectors, each
+ * step one mstrsm and one mstrsm_adjoint over the shifts still running;
+ * Rayleigh-Ritz on the kdim x kdim projection gives the largest Ritz value
+ * theta and the residual norm of its Ritz vector, |beta S(kdim-1, 0)|. A shift
+ * stops when that is <= tol * theta, or after max_restarts restarts;
+ * otherwise the next cycle keeps its keep largest Ritz vectors and the last
+ * Lanczos vector (thick restart). sigma[j] = theta^{-1/2}.
+ *   V, ldv        m x N start vectors, read only (normalised copies are used)
+ *   kdim          basis vectors per cycle, 2..32
+ *   keep          Ritz vectors kept at a restart, 1..min(kdim - 1, 16)
+ *   max_restarts  0..100000 (0: one cycle of kdim plain Lanczos steps)
+ *   tol           >= 0: relative residual at which a shift stops
+ *   sigma         device, N doubles: the estimate of sigma_min(U - z_j I)
+ *   resid         nullable, device, N doubles: |beta S(kdim-1, 0)| / theta
+ *   steps         nullable, device, N int32: Lanczos steps taken
+ *   converged     nullable, device, N int32: 1 when resid <= tol
+ * Unlike the other entry points this call synchronises `stream` once per
+ * restart cycle (it reads the number of shifts still running, which sizes the
+ * next cycle's solves), so it cannot be captured into a graph. Workspace:
+ * (kdim + 1) m N + m N complex128 plus O(N kdim^2) doubles.
+ */
+mst_status mst_lanczos_restart_sigma_min(int m, int N, const void* U, int ldu, const void* z,
+                                         const void* V, int ldv, int kdim, int keep,
+                                         int max_restarts, double tol, double* sigma,
+                                         double* resid, int* steps, int* converged,
+                                         const mst_opts* opt, void* stream);
+
+/*
  * Kernel timing (diagnostics). Between mst_profile_start() and
  * mst_profile_stop(), every kernel launch made by this thread is bracketed by
  * a pair of HIP events on its stream and attributed to one family. stop()

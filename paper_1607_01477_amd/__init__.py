@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import MstError, MstOpts
 
 __all__ = ["mstrsm", "mstrsm_safe", "mstrsm_safe_noalloc", "mstrsm_adjoint", "grad_u", "grad_shift", "residual",
-           "triang_eig", "lanczos_sigma_min", "mstrsm_gen", "mstrsm_safe_gen", "gen_triang_eig",
+           "triang_eig", "lanczos_sigma_min", "lanczos_restarted_sigma_min", "mstrsm_gen", "mstrsm_safe_gen", "gen_triang_eig",
            "eig_schur", "gen_eig_schur", "eig", "gen_eig", "mstrsm_op", "mstrsm_real", "mstrsm_real_op",
            "solve", "MultiShiftSolve", "colmajor",
            "MstError", "version", "lib_path"]
@@ -442,6 +442,30 @@ def gen_eig(A, B, *, outer_nb=0):
     ev, X, _ = gen_eig_schur(torch.from_numpy(T).to(dev), torch.from_numpy(S).to(dev),
                              torch.from_numpy(P).to(dev), outer_nb=outer_nb)
     return ev, X
+
+
+def lanczos_restarted_sigma_min(U, z, V0, *, kdim=20, keep=6, max_restarts=30, tol=1e-10, nb=0,
+                                outer_nb=0):
+    """Thick-restart Lanczos estimate of sigma_min(U - z_j I) for every shift
+    (Alg 7 with restarts and a per-shift tolerance). V0 (m x N start vectors)
+    is not modified. Returns (sigma, resid, steps, converged). Synchronises
+    the current stream once per restart cycle."""
+    U = _mat(U, "U")
+    V = _mat(V0, "V0")
+    m, N = V.shape
+    if U.shape != (m, m):
+        raise ValueError("U must be %d x %d" % (m, m))
+    zz = _vec(z, N, "z")
+    sigma = torch.empty(N, dtype=torch.float64, device=V.device)
+    resid = torch.empty(N, dtype=torch.float64, device=V.device)
+    steps = torch.empty(N, dtype=torch.int32, device=V.device)
+    conv = torch.empty(N, dtype=torch.int32, device=V.device)
+    o = _opts(nb=nb, outer_nb=outer_nb)
+    rc = _lib.load().mst_lanczos_restart_sigma_min(m, N, _p(U), _ld(U), _p(zz), _p(V), _ld(V), int(kdim),
+                                                   int(keep), int(max_restarts), float(tol), _p(sigma),
+                                                   _p(resid), _p(steps), _p(conv), ctypes.byref(o), _stream())
+    _lib.check("mst_lanczos_restart_sigma_min", rc)
+    return sigma, resid, steps, conv
 
 
 def lanczos_sigma_min(U, z, V0, iters=15, *, nb=0, outer_nb=0):

@@ -17,7 +17,8 @@ SCRATCH_LIMIT = 16 << 20   # MST_SCRATCH_LIMIT: bytes of mstrsm_safe_noalloc's s
 
 # every symbol include/mstrsm.h declares
 EXPORTS = ["mstrsm", "mstrsm_safe", "mstrsm_safe_noalloc", "mstrsm_adjoint", "mst_grad_u", "mst_grad_shift",
-           "mst_residual", "mst_triang_eig", "mst_lanczos_sigma_min", "mstrsm_gen",
+           "mst_residual", "mst_triang_eig", "mst_lanczos_sigma_min", "mst_lanczos_restart_sigma_min",
+           "mstrsm_gen",
            "mstrsm_safe_gen", "mst_gen_triang_eig", "mst_eig_schur", "mst_gen_eig_schur", "mstrsm_op",
            "mstrsm_real", "mstrsm_real_op",
            "mst_status_string",
@@ -61,6 +62,8 @@ def load():
                 "mst_residual": [I, I, P, I, P, P, I, P, I, P, I, P],
                 "mst_triang_eig": [I, P, I, P, I, P, P, OP, P],
                 "mst_lanczos_sigma_min": [I, I, P, I, P, P, I, I, P, P, P, P, OP, P],
+                "mst_lanczos_restart_sigma_min": [I, I, P, I, P, P, I, I, I, I, ctypes.c_double, P, P, P,
+                                                  P, OP, P],
                 "mstrsm_gen": [I, I, P, I, P, I, P, P, I, OP, P],
                 "mstrsm_safe_gen": [I, I, P, I, P, I, P, P, I, P, P, P, OP, P],
                 "mst_gen_triang_eig": [I, P, I, P, I, P, I, P, P, OP, P],

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmstrsm.so")
-SOURCES = ["api.hip", "kdiag.hip", "kgemm.hip", "kaux.hip", "kreal.hip"]
+SOURCES = ["api.hip", "kdiag.hip", "kgemm.hip", "kaux.hip", "kreal.hip", "klanczos.hip"]
 ARCH = "gfx950"
 
 

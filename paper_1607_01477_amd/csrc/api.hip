@@ -1182,6 +1182,75 @@ mst_status mst_lanczos_sigma_min(int m, int N, const void* U, int ldu, const voi
     return MST_OK;
 }
 
+mst_status mst_lanczos_restart_sigma_min(int m, int N, const void* U, int ldu, const void* z, const void* V,
+                                         int ldv, int kdim, int keep, int max_restarts, double tol,
+                                         double* sigma, double* resid, int* steps, int* converged,
+                                         const mst_opts* opt, void* stream) {
+    entry("mst_lanczos_restart_sigma_min", m, N);
+    if (m < 1) return bad(1);
+    if (N < 0) return bad(2);
+    mst_status st;
+    if ((st = check_mat(U, ldu, m, N > 0 ? m : 0, 3, 4)) != MST_OK) return st;
+    if (N > 0 && !z) return bad(5);
+    if ((st = check_mat(V, ldv, m, N, 6, 7)) != MST_OK) return st;
+    if (kdim < 2 || kdim > trl_max_kdim()) return bad(8);
+    if (keep < 1 || keep >= kdim || keep > trl_max_keep()) return bad(9);
+    if (max_restarts < 0 || max_restarts > 100000) return bad(10);
+    if (!(tol >= 0.0)) return bad(11);
+    if (N > 0 && !sigma) return bad(12);
+    Opts o;
+    if ((st = read_opts(opt, o, 16)) != MST_OK) return st;
+    if (o.precision != 0) return unsupported("precision 1 is offered by the plain upper solve only");
+    if (N == 0) return MST_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace ws(s);
+    const long qs = (long)m * N;   // one basis block
+    zd *Q, *Wb, *zact;
+    double *H, *beta, *Sk, *res = resid;
+    int *idx, *go, *cnt, *stp = steps, *cv = converged;
+    HIPCHK(ws_get(ws, (size_t)(kdim + 1) * qs, &Q));
+    HIPCHK(ws_get(ws, (size_t)qs, &Wb));
+    HIPCHK(ws_get(ws, (size_t)N, &zact));
+    HIPCHK(ws_get(ws, (size_t)N * kdim * kdim, &H));
+    HIPCHK(ws_get(ws, (size_t)N, &beta));
+    HIPCHK(ws_get(ws, (size_t)N * kdim * keep, &Sk));
+    HIPCHK(ws_get(ws, (size_t)2 * N, &idx));
+    HIPCHK(ws_get(ws, (size_t)N, &go));
+    HIPCHK(ws_get(ws, (size_t)1, &cnt));
+    if (!res) HIPCHK(ws_get(ws, (size_t)N, &res));
+    if (!stp) HIPCHK(ws_get(ws, (size_t)N, &stp));
+    if (!cv) HIPCHK(ws_get(ws, (size_t)N, &cv));
+    const zd* Uz = (const zd*)U;
+    const zd* zz = (const zd*)z;
+    auto aux = [&](auto&& f) { return timed(MST_PROF_AUX, 0.0, s, f); };
+    HIPCHK(aux([&] { return launch_trl_init(m, N, kdim, (const zd*)V, ldv, Q, m, H, idx, stp, s); }));
+    int nact = N, cur = 0, k0 = 0;
+    for (int cycle = 0; cycle <= max_restarts; ++cycle) {
+        int* ic = idx + (size_t)cur * N;
+        for (int i = k0; i < kdim; ++i) {
+            // w = (U - z I)^{-H} (U - z I)^{-1} q_i for the running shifts, then the recurrence
+            HIPCHK(aux([&] { return launch_trl_gather(m, nact, ic, Q + (long)i * qs, m, Wb, m, zz, zact, s); }));
+            HIPCHK(forward_loop(m, nact, Uz, ldu, nullptr, 0, zact, Wb, m, nullptr, 0, o, nullptr, nullptr, s));
+            HIPCHK(adjoint_loop(m, nact, Uz, ldu, zact, Wb, m, o, s));
+            HIPCHK(aux([&] { return launch_trl_orth(m, nact, i, k0, kdim, ic, Wb, m, Q, m, qs, H, beta, stp, s); }));
+        }
+        const int last = cycle == max_restarts;
+        HIPCHK(aux([&] { return launch_trl_ritz(nact, kdim, keep, tol, last, ic, H, beta, Sk, sigma, res, cv, go, s); }));
+        if (last) break;
+        HIPCHK(aux([&] { return launch_trl_restart(m, nact, kdim, keep, ic, go, Q, m, qs, Sk, s); }));
+        HIPCHK(aux([&] { return launch_trl_compact(nact, ic, go, idx + (size_t)(1 - cur) * N, cnt, s); }));
+        // the number of shifts still running sizes the next cycle's solves
+        int h_cnt = 0;
+        HIPCHK(hipMemcpyAsync(&h_cnt, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        nact = h_cnt;
+        cur = 1 - cur;
+        k0 = keep;
+        if (nact == 0) break;
+    }
+    return MST_OK;
+}
+
 mst_status mst_profile_start(void) {
     for (auto& r : t_recs) {
         t_pool.push_back(r.a);

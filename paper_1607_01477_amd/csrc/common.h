@@ -248,4 +248,24 @@ hipError_t launch_zero(long count, zd* p, hipStream_t s);
 hipError_t launch_tridiag_max(int n, int iters, const double* alpha, const double* beta,
                               const int* steps, double* sigma, hipStream_t s);
 
+// ---------------------------------------------------------------- thick-restart Lanczos
+// Kernels of the restarted resolvent-norm driver (klanczos.hip). Q holds kdim + 1
+// basis blocks of m x N (block l at Q + l * qs, leading dimension ldq); H the
+// kdim x kdim projected matrix of each shift (row-major); idx the running shifts.
+int trl_max_kdim();
+int trl_max_keep();
+hipError_t launch_trl_init(int m, int N, int kdim, const zd* V, long ldv, zd* Q, long ldq, double* H, int* idx,
+                           int* steps, hipStream_t s);
+hipError_t launch_trl_gather(int m, int nact, const int* idx, const zd* Qi, long ldq, zd* W, long ldw,
+                             const zd* z, zd* zact, hipStream_t s);
+hipError_t launch_trl_orth(int m, int nact, int i, int k0, int kdim, const int* idx, zd* W, long ldw, zd* Q,
+                           long ldq, long qs, double* H, double* beta, int* steps, hipStream_t s);
+hipError_t launch_trl_ritz(int nact, int kdim, int keep, double tol, int last, const int* idx, double* H,
+                           const double* beta, double* Sk, double* sigma, double* resid, int* conv, int* go,
+                           hipStream_t s);
+hipError_t launch_trl_restart(int m, int nact, int kdim, int keep, const int* idx, const int* go, zd* Q,
+                              long ldq, long qs, const double* Sk, hipStream_t s);
+hipError_t launch_trl_compact(int nact, const int* idx, const int* go, int* idx_out, int* count,
+                              hipStream_t s);
+
 }  // namespace mst

@@ -5,8 +5,10 @@ chosen from the spectrum (a "portrait"), plus level-set segments for contour
 output.
 
 The GPU work is one call of `lanczos_sigma_min` (all grid points at once: one
-upper and one adjoint multi-shift solve per Lanczos step); the grid, the start
-vectors and the contour extraction are host-side set-up and post-processing.
+upper and one adjoint multi-shift solve per Lanczos step, a fixed number of
+steps), or, with a tolerance `tol`, of `lanczos_restarted_sigma_min` (thick
+restart with a per-shift stopping test); the grid, the start vectors and the
+contour extraction are host-side set-up and post-processing.
 
 Automatic window (the paper gives no rule): the square centred on the midpoint
 of the eigenvalues' bounding box, of side (1 + 2 pad) times the larger of its
@@ -17,7 +19,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import lanczos_sigma_min
+from . import lanczos_restarted_sigma_min, lanczos_sigma_min
 
 
 def window_grid(center: complex, width: float, height: float, nx: int, ny: int):
@@ -58,28 +60,37 @@ def _start_vectors(m: int, n: int, seed: int, device) -> torch.Tensor:
     return v.to(device)
 
 
-def spectral_cloud(U, shifts, *, iters: int = 15, seed: int = 0, V0=None):
+def spectral_cloud(U, shifts, *, iters: int = 15, seed: int = 0, V0=None, tol=None, kdim: int = 20,
+                   keep: int = 6, max_restarts: int = 30):
     """sigma_min(U - z I) estimates at arbitrary shifts z (U upper triangular,
-    device tensor). Returns a device tensor of len(shifts)."""
+    device tensor). tol None: `iters` plain Lanczos steps; otherwise thick-
+    restart Lanczos until the relative residual of each shift's top Ritz pair
+    is <= tol (basis kdim, keep Ritz vectors, at most max_restarts restarts).
+    Returns a device tensor of len(shifts)."""
     dev = U.device
     z = torch.as_tensor(np.asarray(shifts, dtype=np.complex128)).to(dev)
     if V0 is None:
         V0 = _start_vectors(U.shape[0], z.numel(), seed, dev)
+    if tol is not None:
+        sigma, _, _, _ = lanczos_restarted_sigma_min(U, z, V0, kdim=kdim, keep=keep,
+                                                     max_restarts=max_restarts, tol=tol)
+        return sigma
     sigma, _, _, _ = lanczos_sigma_min(U, z, V0, iters=iters)
     return sigma
 
 
 def spectral_window(U, center, width, height, nx: int = 100, ny: int = 100, *, iters: int = 15,
-                    seed: int = 0):
+                    seed: int = 0, tol=None):
     """Resolvent-norm data over a user window: (xs, ys, sigma) with
-    sigma[iy, ix] ~ sigma_min(U - (xs[ix] + i ys[iy]) I) on the host."""
+    sigma[iy, ix] ~ sigma_min(U - (xs[ix] + i ys[iy]) I) on the host (tol as
+    for spectral_cloud)."""
     xs, ys, z = window_grid(center, width, height, nx, ny)
-    sigma = spectral_cloud(U, z, iters=iters, seed=seed)
+    sigma = spectral_cloud(U, z, iters=iters, seed=seed, tol=tol)
     return xs, ys, sigma.cpu().numpy().reshape(ny, nx)
 
 
 def spectral_portrait(A, nx: int = 100, ny: int = 100, *, iters: int = 15, seed: int = 0,
-                      triangular: bool = False, pad: float = 0.2):
+                      triangular: bool = False, pad: float = 0.2, tol=None):
     """Spectral portrait of A: the Schur form on the host unless `triangular`,
     an automatic window around the eigenvalues, then the resolvent-norm grid on
     the GPU. Returns (xs, ys, sigma, eigs)."""
@@ -94,7 +105,7 @@ def spectral_portrait(A, nx: int = 100, ny: int = 100, *, iters: int = 15, seed:
         U = torch.as_tensor(T).to("cuda")
         eigs = np.diag(T).copy()
     center, w, h = portrait_window(eigs, pad=pad)
-    xs, ys, sigma = spectral_window(U, center, w, h, nx, ny, iters=iters, seed=seed)
+    xs, ys, sigma = spectral_window(U, center, w, h, nx, ny, iters=iters, seed=seed, tol=tol)
     return xs, ys, sigma, eigs
 
 

@@ -203,3 +203,20 @@ def test_noalloc_rejections_without_gpu():
     nb64 = 128 * 8192 * 4 + 2 * 8192 * 8 + 3 * 8192 * 8 + 256 * 3
     assert nb64 < _lib.SCRATCH_LIMIT
     assert f(5, 0, fake, 5, fake, fake, 5, None, fake, None, None, None) == _lib.MST_OK
+
+
+def test_restarted_lanczos_argument_errors_without_gpu():
+    from paper_1607_01477_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(4096)   # never dereferenced: the calls return before any HIP call
+    f = lib.mst_lanczos_restart_sigma_min
+    args = lambda kdim, keep, mr, tol: (5, 3, fake, 5, fake, fake, 5, kdim, keep, mr, tol, fake, None, None,
+                                        None, None, None)
+    assert f(*args(1, 1, 0, 0.0)) == _lib.MST_EARG and lib.mst_last_bad_arg() == 8
+    assert f(*args(33, 1, 0, 0.0)) == _lib.MST_EARG and lib.mst_last_bad_arg() == 8
+    assert f(*args(8, 8, 0, 0.0)) == _lib.MST_EARG and lib.mst_last_bad_arg() == 9
+    assert f(*args(32, 17, 0, 0.0)) == _lib.MST_EARG and lib.mst_last_bad_arg() == 9
+    assert f(*args(8, 3, -1, 0.0)) == _lib.MST_EARG and lib.mst_last_bad_arg() == 10
+    assert f(*args(8, 3, 0, float("nan"))) == _lib.MST_EARG and lib.mst_last_bad_arg() == 11
+    assert f(*args(8, 3, 0, -1.0)) == _lib.MST_EARG and lib.mst_last_bad_arg() == 11
+    assert f(5, 0, fake, 5, None, fake, 5, 8, 3, 0, 0.0, None, None, None, None, None, None) == _lib.MST_OK
