@@ -618,6 +618,10 @@ constexpr int block_threads(int nb, bool adj, bool safe, bool gen = false) {
     return (nb == 16 && !safe && !gen) ? 768 : 512;
 }
 constexpr int kAW = 4;                 // wavefronts that solve diagonal blocks; the others update
+// rounds of the matrix-core tiles a pass deals to the updating wavefronts (the
+// rest go to the solving ones): all of the at most 15 tiles with 8 updating
+// wavefronts; with 4, the solving ones take tiles 12 and beyond
+constexpr int upd_rounds(int nuw) { return nuw >= 8 ? 2 : 3; }
 
 // One outer block (rows [iS, iS+rows)) for kCols shifts, with the right-hand
 // sides resident in LDS. Diagonal blocks are solved one per pass with a
@@ -644,6 +648,7 @@ __global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_bl
     constexpr int kWGB = block_threads(NB, ADJ, SAFE, GEN);
     constexpr int NWAVE = kWGB / 64;
     constexpr int NUW = NWAVE - kAW;                     // updating wavefronts
+    constexpr int kUpdRounds = upd_rounds(NUW);
     constexpr int SPW = kCols / (kAW * G);               // interleaved shifts per lane group
     constexpr int NBB = NB * NB;
     constexpr int NST = GEN ? 4 : 2;                     // staged blocks per pass
@@ -659,7 +664,6 @@ __global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_bl
     __shared__ zd Vd[GEN ? 2 : 1][GEN ? NB : 1];
     __shared__ double Gl[kCols];
     __shared__ int kcl[kCols], dkl[2][kCols], Ll[kCols];
-    __shared__ int tctr[2];        // next update tile to claim, per pass parity
 
     if (MIXED && a.skip && *a.skip) return;   // refinement stopped
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -669,7 +673,6 @@ __global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_bl
     const double omega = ldexp(1.0, w);
     const double delta = SAFE ? (GEN ? fmax(*a.safe.delta, *a.safe.delta_v) : *a.safe.delta) : 0.0;
 
-    if (tid == 0) tctr[0] = NUW;
     if (tid < kCols) {
         const int j = col0 + tid;
         int L = 0;
@@ -993,17 +996,15 @@ __global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_bl
             }
         }
         // ---- rows beyond block q: C -= U_panel * x(block p) on the matrix cores.
-        // Tiles 0 .. NUW-1 go to the updating wavefronts (first fragment
-        // prefetched in the pass before); the rest are claimed from a counter
-        // by whichever wavefront is free, the solving ones after their solve.
+        // Static round-robin: updating wavefront u takes tiles u, u + NUW, ...
+        // below NUW * kUpdRounds (its first fragment prefetched in the pass
+        // before, each next one during the tile before); tiles from there on go
+        // to the solving wavefronts after their solve. (A shared claim counter
+        // would put an LDS atomic round trip, about a thousand cycles when the
+        // pass is busy, on both critical paths.)
         {
             const int ntile = (g.uend - g.ubeg + 15) / 16;
             const int dsh = (SAFE && g.bsp > 0) ? dkl[buf ^ 1][lr] : 0;
-            auto claim = [&]() __attribute__((always_inline)) {
-                int t = 0;
-                if (lane == 0) t = atomicAdd(&tctr[buf], 1);
-                return __builtin_amdgcn_readfirstlane(t);
-            };
             auto do_tile = [&](int tile, const zd (&af)[KS], const zd (&vf)[GEN ? KS : 1])
                 __attribute__((always_inline)) {
                 const int rb = g.ubeg + tile * 16;
@@ -1059,24 +1060,36 @@ __global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_bl
                     if (row < g.uend) Bl[lr * kSP + row] = zd{accR[v] + accR2[v], accI[v] + accI2[v]};
                 }
             };
-            int cur = (wave >= kAW) ? wave - kAW : claim();
-            if (wave < kAW && cur < ntile) aload(an, vn, g, cur);
+            const int nt_upd = min(ntile, NUW * kUpdRounds);
+            // wave-uniform tile indices (scalar loop control and addresses)
+            const int wv = __builtin_amdgcn_readfirstlane(wave);
+            int cur, stride, lim;
+            if (wv >= kAW) {
+                cur = wv - kAW;
+                stride = NUW;
+                lim = nt_upd;
+            } else {
+                cur = nt_upd + wv;
+                stride = kAW;
+                lim = ntile;
+                if (cur < lim) aload(an, vn, g, cur);
+            }
+            cur = __builtin_amdgcn_readfirstlane(cur);
+            lim = __builtin_amdgcn_readfirstlane(lim);
             zd af[KS];
             zd vf[GEN ? KS : 1];
-            while (cur < ntile) {
-                const int nxt = claim();
+            while (cur < lim) {
+                const int nxt = cur + stride;
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) af[ks] = an[ks];
                 if constexpr (GEN) {
 #pragma unroll
                     for (int ks = 0; ks < KS; ++ks) vf[ks] = vn[ks];
                 }
-                if (nxt < ntile) aload(an, vn, g, nxt);
+                if (nxt < lim) aload(an, vn, g, nxt);
                 do_tile(cur, af, vf);
                 cur = nxt;
             }
-            // counter of the next pass (its last use was before the barrier behind us)
-            if (tid == 0) tctr[buf ^ 1] = NUW;
         }
         if (stp + 1 < nsub) stage_store(buf ^ 1);
         // first fragment of the next pass, in flight across the barrier; issued
