@@ -106,20 +106,58 @@ __device__ inline double bcast(double v, int i, int base) {
     }
 }
 
+// 64-bit DPP moves: one v_mov_b64_dpp each (gfx950's DP ALU takes DPP64 with
+// row_newbcast). Plain functions with literal controls: inside a template the
+// builtin's result type is not resolved to its 64-bit operand's (it reads as
+// int), so the template below only dispatches.
+#define MST_BCAST64_FN(I, CTL)                                                           \
+    __device__ inline double bcast64_##I(double v) {                                     \
+        const long r = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(long, v), CTL, 0xF, 0xF, false); \
+        return __builtin_bit_cast(double, r);                                            \
+    }
+MST_BCAST64_FN(0, 0x150)
+MST_BCAST64_FN(1, 0x151)
+MST_BCAST64_FN(2, 0x152)
+MST_BCAST64_FN(3, 0x153)
+MST_BCAST64_FN(4, 0x154)
+MST_BCAST64_FN(5, 0x155)
+MST_BCAST64_FN(6, 0x156)
+MST_BCAST64_FN(7, 0x157)
+MST_BCAST64_FN(8, 0x158)
+MST_BCAST64_FN(9, 0x159)
+MST_BCAST64_FN(10, 0x15A)
+MST_BCAST64_FN(11, 0x15B)
+MST_BCAST64_FN(12, 0x15C)
+MST_BCAST64_FN(13, 0x15D)
+MST_BCAST64_FN(14, 0x15E)
+MST_BCAST64_FN(15, 0x15F)
+#undef MST_BCAST64_FN
+
+// Value of lane I of each row of 16 lanes, to every lane of that row
+// (DPP row_newbcast writes every lane, so no previous value is needed).
 template <int I>
 __device__ inline double bcast16(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + I, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + I, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
+    static_assert(I >= 0 && I < 16, "lane of a row");
+    if constexpr (I == 0) return bcast64_0(v);
+    else if constexpr (I == 1) return bcast64_1(v);
+    else if constexpr (I == 2) return bcast64_2(v);
+    else if constexpr (I == 3) return bcast64_3(v);
+    else if constexpr (I == 4) return bcast64_4(v);
+    else if constexpr (I == 5) return bcast64_5(v);
+    else if constexpr (I == 6) return bcast64_6(v);
+    else if constexpr (I == 7) return bcast64_7(v);
+    else if constexpr (I == 8) return bcast64_8(v);
+    else if constexpr (I == 9) return bcast64_9(v);
+    else if constexpr (I == 10) return bcast64_10(v);
+    else if constexpr (I == 11) return bcast64_11(v);
+    else if constexpr (I == 12) return bcast64_12(v);
+    else if constexpr (I == 13) return bcast64_13(v);
+    else if constexpr (I == 14) return bcast64_14(v);
+    else return bcast64_15(v);
 }
-
-// bcast16 without a previous-value operand: row_newbcast writes every lane,
-// so no register has to be initialised for lanes the move would skip
 template <int I>
 __device__ inline double bcast16m(double v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + I, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + I, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
+    return bcast16<I>(v);
 }
 
 template <int NB>

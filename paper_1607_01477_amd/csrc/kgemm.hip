@@ -615,8 +615,16 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
                 a0 = *qa0; a1 = *qa1; b0 = *qb0; b1 = *qb1;
                 qa0 += sA; qa1 += sA; qb0 += sB; qb1 += sB;
             };
+            // the prologue fills the ring in the loop body's order (fenced like
+            // it): the wait counts at the loop header merge both paths, and a
+            // prologue the scheduler reordered makes the first k-step of every
+            // ring round wait for loads of later slots
 #pragma unroll
-            for (int d = 0; d < DEPTH; ++d) next(pa0[d], pa1[d], pb0[d], pb1[d]);
+            for (int d = 0; d < DEPTH; ++d) {
+                __builtin_amdgcn_sched_barrier(0);
+                next(pa0[d], pa1[d], pb0[d], pb1[d]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
             int l0 = 0;
             for (; l0 + 2 * DEPTH <= nloc; l0 += DEPTH) {
 #pragma unroll
@@ -641,8 +649,11 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
         // k-step is loaded again, in bounds and unused), so the main loop is
         // straight-line code; only the last nloc % DEPTH steps are guarded.
 #pragma unroll
-        for (int d = 0; d < DEPTH; ++d)
+        for (int d = 0; d < DEPTH; ++d) {
+            __builtin_amdgcn_sched_barrier(0);
             load(kfirst + min(d, nloc - 1), pa0[d], pa1[d], pb0[d], pb1[d], qe0[d], qe1[d]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         int l0 = 0;
         for (; l0 + DEPTH <= nloc; l0 += DEPTH) {
 #pragma unroll
