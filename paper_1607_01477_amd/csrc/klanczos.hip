@@ -175,9 +175,12 @@ __global__ __launch_bounds__(kT) void k_trl_orth(int m, int i, int k0, int kdim,
     }
 }
 
-// One wavefront per running shift: cyclic Jacobi on the symmetric projected
-// matrix (kdim <= 32, in LDS), eigenvalues sorted descending with their
-// vectors; sigma = theta_0^-1/2, resid = |beta S(kdim-1, 0)| / theta_0, the
+// One wavefront per running shift: Jacobi eigensolver of the symmetric
+// projected matrix (kdim <= 32, in LDS) in the parallel (tournament) order:
+// each step rotates kdim/2 disjoint index pairs at once (the rows of all pairs,
+// then their columns and the eigenvector columns), so a sweep is kdim - 1
+// steps of two barriers; eigenvalues sorted descending with their vectors;
+// sigma = theta_0^-1/2, resid = |beta S(kdim-1, 0)| / theta_0, the
 // convergence test, and for a shift that goes on, the restart: H becomes
 // diag(theta_0..theta_{keep-1}) bordered by beta S(kdim-1, l) in row and
 // column keep, and S(:, 0:keep) is stored for k_trl_restart.
@@ -189,47 +192,84 @@ __global__ __launch_bounds__(64) void k_trl_ritz(int kdim, int keep, double tol,
     __shared__ double S[kMaxK * kMaxK];
     __shared__ double th[kMaxK];
     __shared__ int ord[kMaxK];
+    __shared__ double rc[kMaxK / 2], rs[kMaxK / 2];
+    __shared__ int rp[kMaxK / 2], rq[kMaxK / 2];
     const int c = blockIdx.x, j = idx[c], t = threadIdx.x;
     double* Hj = H + (long)j * kdim * kdim;
     for (int e = t; e < kdim * kdim; e += 64) {
         A[e] = Hj[e];
         S[e] = ((e / kdim) == (e % kdim)) ? 1.0 : 0.0;
     }
+    const int np = (kdim + 1) & ~1;   // players of the tournament (a dummy when kdim is odd)
+    const int npair = np / 2;
     __syncthreads();
     for (int sweep = 0; sweep < 60; ++sweep) {
+        // off-diagonal and diagonal mass (fixed-order wavefront sums)
         double off = 0.0, dia = 0.0;
-        for (int e = 0; e < kdim * kdim; ++e) {
-            const int p = e / kdim, q = e % kdim;
-            if (p != q) off += A[e] * A[e]; else dia += A[e] * A[e];
+        for (int e = t; e < kdim * kdim; e += 64) {
+            const double v = A[e] * A[e];
+            if ((e / kdim) != (e % kdim)) off += v; else dia += v;
+        }
+        for (int o = 32; o >= 1; o >>= 1) {
+            off += __shfl_xor(off, o, 64);
+            dia += __shfl_xor(dia, o, 64);
         }
         if (!(off > 1e-32 * dia)) break;
-        for (int p = 0; p < kdim - 1; ++p) {
-            for (int q = p + 1; q < kdim; ++q) {
-                const double apq = A[p * kdim + q];
-                if (apq == 0.0) continue;
-                // rotation zeroing A(p, q): tan 2phi = 2 apq / (aqq - app)
-                const double app = A[p * kdim + p], aqq = A[q * kdim + q];
-                const double tau = (aqq - app) / (2.0 * apq);
-                const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = tt * cs;
-                __syncthreads();
-                if (t < kdim) {
-                    // rows p and q, then columns p and q (A symmetric)
-                    const double a_p = A[p * kdim + t], a_q = A[q * kdim + t];
-                    A[p * kdim + t] = cs * a_p - sn * a_q;
-                    A[q * kdim + t] = sn * a_p + cs * a_q;
+        for (int step = 0; step < np - 1; ++step) {
+            // pairs of this step: player 0 against rotating player step + 1, and
+            // the others folded around the circle of players 1 .. np - 1
+            if (t < npair) {
+                int a, b;
+                if (t == 0) {
+                    a = 0;
+                    b = 1 + step % (np - 1);
+                } else {
+                    a = 1 + (step + t) % (np - 1);
+                    b = 1 + (step + np - 1 - t) % (np - 1);
                 }
-                __syncthreads();
-                if (t < kdim) {
-                    const double a_p = A[t * kdim + p], a_q = A[t * kdim + q];
-                    A[t * kdim + p] = cs * a_p - sn * a_q;
-                    A[t * kdim + q] = sn * a_p + cs * a_q;
-                    const double s_p = S[t * kdim + p], s_q = S[t * kdim + q];
-                    S[t * kdim + p] = cs * s_p - sn * s_q;
-                    S[t * kdim + q] = sn * s_p + cs * s_q;
+                const int p = a < b ? a : b, q = a < b ? b : a;
+                double cs = 1.0, sn = 0.0;
+                if (q < kdim) {
+                    const double apq = A[p * kdim + q];
+                    if (apq != 0.0) {
+                        const double app = A[p * kdim + p], aqq = A[q * kdim + q];
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        cs = 1.0 / sqrt(1.0 + tt * tt);
+                        sn = tt * cs;
+                    }
                 }
-                __syncthreads();
+                rp[t] = p;
+                rq[t] = q;
+                rc[t] = cs;
+                rs[t] = sn;
             }
+            __syncthreads();
+            // rows p and q of every pair (disjoint pairs: no element is touched twice)
+            for (int e = t; e < npair * kdim; e += 64) {
+                const int k = e / kdim, col = e - k * kdim;
+                const int p = rp[k], q = rq[k];
+                if (q >= kdim || rs[k] == 0.0) continue;
+                const double cs = rc[k], sn = rs[k];
+                const double a_p = A[p * kdim + col], a_q = A[q * kdim + col];
+                A[p * kdim + col] = cs * a_p - sn * a_q;
+                A[q * kdim + col] = sn * a_p + cs * a_q;
+            }
+            __syncthreads();
+            // columns p and q of every pair, and of the eigenvector matrix
+            for (int e = t; e < npair * kdim; e += 64) {
+                const int k = e / kdim, row = e - k * kdim;
+                const int p = rp[k], q = rq[k];
+                if (q >= kdim || rs[k] == 0.0) continue;
+                const double cs = rc[k], sn = rs[k];
+                const double a_p = A[row * kdim + p], a_q = A[row * kdim + q];
+                A[row * kdim + p] = cs * a_p - sn * a_q;
+                A[row * kdim + q] = sn * a_p + cs * a_q;
+                const double s_p = S[row * kdim + p], s_q = S[row * kdim + q];
+                S[row * kdim + p] = cs * s_p - sn * s_q;
+                S[row * kdim + q] = sn * s_p + cs * s_q;
+            }
+            __syncthreads();
         }
     }
     if (t < kdim) th[t] = A[t * kdim + t];
