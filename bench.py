@@ -39,14 +39,14 @@ PEAK_FP64_MFMA_TF = 78.6
 # HBM bytes per launch of the substitution GEMM at this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs scaled by a 512 MiB copy (profiles/k_gemm_direct_solve_m4096_n4096.md).
 # Valid only for the GEMM source it was measured on (sha1 prefix of csrc/kgemm.hip).
-GEMM_TRAFFIC = {"kgemm_sha1": "8a4e7752b13cd971", "bytes_per_launch": 295.4e6, "m": 4096, "n": 4096,
+GEMM_TRAFFIC = {"kgemm_sha1": "942127a8426db63f", "bytes_per_launch": 295.4e6, "m": 4096, "n": 4096,
                 "nb": 16, "outer_nb": 256,
                 # the pencil substitution (profiles/k_gemm_direct_pencil_m4096_n4096.md)
-                "pencil_bytes_per_launch": 470.9e6}
+                "pencil_bytes_per_launch": 471.0e6}
 # The same for the real substitution GEMM (all its tile variants, averaged over
 # the 15 launches of a solve; profiles/real_solve_m4096_n4096.md), valid for the
 # source it was measured on (sha1 prefix of csrc/kreal.hip).
-REAL_GEMM_TRAFFIC = {"kreal_sha1": "e7be9309582c3d97", "bytes_per_launch": 119.4e6, "m": 4096, "n": 4096,
+REAL_GEMM_TRAFFIC = {"kreal_sha1": "fe0f0182779df525", "bytes_per_launch": 119.4e6, "m": 4096, "n": 4096,
                      "outer_nb": 256}
 PEAK_FP32_MFMA_TF = 157.3
 METRIC = "complex128 multi-shift solve GFLOP/s at m=n=4096 and % of MFMA peak vs plain FP64"
