@@ -84,7 +84,14 @@ typedef struct {
                           summation order, so results agree to rounding, not bit for
                           bit (safe exponents are the same). On MI355X it pays off
                           for nb = 32 only. */
-    int reserved;      /* must be 0 */
+    int gemm_split;    /* 0 (default): the substitution and residual products split the K
+                          range of each 32 x 32 tile over 2 or 4 wavefronts of a workgroup
+                          when the launch has too few tiles to fill the device (decided per
+                          launch from its shape and the device's compute-unit count);
+                          1, 2 or 4 forces that split for every such product. Partial sums
+                          are added in a fixed order, so a given shape and split give the
+                          same bits on every call; different splits agree to rounding.
+                          Other values: MST_EINVAL. */
     double refine_tol; /* precision 1: before each sweep the relative residual of every
                           column, ||(U - l_j I) x_j - b_j||_inf / (||U - l_j I||_inf
                           ||x_j||_inf) (true modulus), is evaluated on the device; the

@@ -33,7 +33,7 @@ class MstOpts(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int), ("omega_log2", ctypes.c_int),
                 ("force_phase2", ctypes.c_int), ("fuse_blocks", ctypes.c_int),
                 ("gemm_staged", ctypes.c_int), ("overlap", ctypes.c_int),
-                ("reserved", ctypes.c_int), ("refine_tol", ctypes.c_double),
+                ("gemm_split", ctypes.c_int), ("refine_tol", ctypes.c_double),
                 ("refine_report", ctypes.c_void_p)]
 
 

@@ -125,6 +125,7 @@ struct Opts {
     int nb = 16, outer = 256, precision = 0, sweeps = 2, omega_log2 = 960;
     bool fuse = true;
     int staged = 0;
+    int split = 0;
     bool overlap = false;
     bool force_checked = false;
     double refine_tol = 1e-14;
@@ -155,7 +156,8 @@ mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
     r.overlap = o->overlap == 1;
     if (o->force_phase2 != 0 && o->force_phase2 != 1) return bad(pos);
     r.force_checked = o->force_phase2 == 1;
-    if (o->reserved != 0) return bad(pos);
+    if (o->gemm_split != 0 && o->gemm_split != 1 && o->gemm_split != 2 && o->gemm_split != 4) return bad(pos);
+    r.split = o->gemm_split;
     if (o->refine_tol != 0.0) r.refine_tol = o->refine_tol;
     if (r.refine_tol != r.refine_tol) return bad(pos);   // NaN
     r.report = o->refine_report;
@@ -269,7 +271,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
         const int x0 = qa * nb, x1 = row_end(ob_hi);
         GemmArgs g{};
         g.M = r1 - r0; g.N = n; g.K = x1 - x0;
-        g.op = GOP_SUB; g.staged = o.staged;
+        g.op = GOP_SUB; g.staged = o.staged; g.split = o.split;
         g.nb = nb; g.b_row0 = x0; g.c_row0 = r0; g.col_len = col_len;
         if (safe) {
             g.kb = safe->kb; g.n_kb = n; g.q_cur = qa; g.q_c = (qb + 1 < nblk) ? qb + 1 : -1;
@@ -378,7 +380,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             if (q > qa) {
                 GemmArgs g{};
                 g.M = i0 - qa * nb; g.N = n; g.K = bs;
-                g.op = GOP_SUB; g.staged = o.staged;
+                g.op = GOP_SUB; g.staged = o.staged; g.split = o.split;
                 g.nb = nb; g.b_row0 = i0; g.c_row0 = qa * nb; g.col_len = col_len;
                 if (safe) {
                     g.kb = safe->kb; g.n_kb = n; g.q_cur = q; g.q_c = (q + 1 < nblk) ? q + 1 : -1;
@@ -456,7 +458,7 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
             if (q < qb) {
                 // G(i1:end) -= E(i1:end, i0:i1) Y(i0:i1), E = U^H for the adjoint
                 GemmArgs g{};
-                g.M = end - i1; g.N = n; g.K = bs; g.op = GOP_SUB; g.staged = o.staged;
+                g.M = end - i1; g.N = n; g.K = bs; g.op = GOP_SUB; g.staged = o.staged; g.split = o.split;
                 g.A = etr ? U + (long)i1 * ldu + i0 : U + (long)i0 * ldu + i1; g.lda = ldu; g.a_ct = amode;
                 g.B = G + i0; g.ldb = ldg;
                 g.C = G + i1; g.ldc = ldg;
@@ -476,7 +478,7 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
         auto below = [&](int x0, int x1, int r1, int r2) -> hipError_t {
             if (r2 <= r1) return hipSuccess;
             GemmArgs g{};
-            g.M = r2 - r1; g.N = n; g.K = x1 - x0; g.op = GOP_SUB; g.staged = o.staged;
+            g.M = r2 - r1; g.N = n; g.K = x1 - x0; g.op = GOP_SUB; g.staged = o.staged; g.split = o.split;
             g.A = etr ? U + (long)r1 * ldu + x0 : U + (long)x0 * ldu + r1; g.lda = ldu; g.a_ct = amode;
             g.B = G + x0; g.ldb = ldg;
             g.C = G + r1; g.ldc = ldg;
@@ -491,9 +493,10 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
 
 hipError_t residual(int m, int n, const zd* U, long ldu, const zd* lam, const zd* X, long ldx,
                     const zd* B0, long ldb0, zd* R, long ldr, hipStream_t s, int staged = 0,
-                    const int* skip = nullptr) {
+                    const int* skip = nullptr, int split = 0) {
     GemmArgs g{};
     g.skip = skip;
+    g.split = split;
     g.M = m; g.N = n; g.K = m; g.op = GOP_RESID; g.staged = staged;
     g.A = U; g.lda = ldu;
     g.B = X; g.ldb = ldx;
@@ -653,7 +656,7 @@ mst_status plain_solve(int m, int n, const zd* U, long ldu, const zd* lam, zd* B
     // it raised the residual. The exponents for the next correction go to the
     // half of ebuf that sweep t did not use.
     auto check = [&](int t) -> hipError_t {
-        hipError_t e = residual(m, n, U, ldu, lam, B, ldb, B0, m, R, m, s, o.staged, stop);
+        hipError_t e = residual(m, n, U, ldu, lam, B, ldb, B0, m, R, m, s, o.staged, stop, o.split);
         if (e != hipSuccess) return e;
         int* et = ebuf + (size_t)((t + 1) & 1) * n;
         if ((e = aux([&] { return launch_colstats(m, n, R, m, B, ldb, rowoff, udiag, lam, et, rel, stop, s); })) != hipSuccess)

@@ -139,6 +139,9 @@ struct GemmArgs {
     const void* A2; long lda2; const zd* glam;
     // FP32 substitution and FP64 residual (refinement): nothing is done when *skip != 0
     const int* skip;
+    // GOP_SUB / GOP_RESID without staging: wavefronts per tile's K range (1, 2, 4),
+    // 0 = chosen from the launch shape
+    int split;
 };
 hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s);
 hipError_t launch_gemm_f32(const GemmArgs& g, hipStream_t s);

@@ -20,6 +20,7 @@
 // receives a contiguous range of tiles.
 #include "common.h"
 
+#include <atomic>
 #include <type_traits>
 
 namespace mst {
@@ -333,7 +334,12 @@ __global__ __launch_bounds__(NT, 2) void k_gemm(GemmArgs g) {
 // share A rows / B columns through L1.
 // AM: A operand access: 0 plain A(r,k) = a[k*lda + r]; 1 conjugate transpose
 // A(r,k) = conj(a[r*lda + k]); 2 transpose A(r,k) = a[r*lda + k].
-template <typename T, int DEPTH, int OP, int AM, bool SAFE, bool VARLEN>
+// KS: wavefronts per 32 x 32 tile. With KS = 1 the workgroup covers 64 x 64;
+// launches with too few tiles to give every SIMD work split each tile's K
+// range over KS = 2 (workgroup tile 64 x 32) or KS = 4 (32 x 32) wavefronts,
+// whose partial sums meet in LDS and are added in a fixed order, so the
+// result does not depend on timing.
+template <typename T, int DEPTH, int OP, int AM, bool SAFE, bool VARLEN, int KS>
 __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
     constexpr bool A_TR = AM != 0, A_CJ = AM == 1;
     static_assert(OP == GOP_SUB || OP == GOP_NEG_TRIU || OP == GOP_RESID || OP == GOP_GEN_SUB ||
@@ -344,6 +350,8 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
     static_assert(OP != GOP_GEN_SUB || (sizeof(T) == 8 && !A_TR), "pencil substitution: FP64, plain A");
     static_assert(sizeof(T) == 8 || (OP == GOP_SUB && !A_TR && !SAFE && !VARLEN),
                   "FP32: plain substitution only");
+    static_assert(KS == 1 || ((KS == 2 || KS == 4) && (OP == GOP_SUB || OP == GOP_RESID)),
+                  "K split: substitution and residual only");
     constexpr bool TRI = OP == GOP_NEG_TRIU;
     constexpr bool RES = OP == GOP_RESID;
     constexpr bool GEN = OP == GOP_GEN_SUB;
@@ -352,7 +360,8 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
     using CT = typename Tr::C;
     using V = typename Tr::V;
     if ((sizeof(T) == 4 || RES) && g.skip && *g.skip) return;   // refinement stopped
-    const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
+    constexpr int TBM = KS == 4 ? 32 : 64, TBN = KS == 1 ? 64 : 32;   // workgroup tile
+    const int TM = (g.M + TBM - 1) / TBM, TN = (g.N + TBN - 1) / TBN;
     int tm, tn;
     if (TRI) {
         tri_coords(TM, tm, tn);   // square: M = N
@@ -371,9 +380,12 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
         tile_coords(TM, TN, tm, tn);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
+    // wavefront tile (wr, wc) of the workgroup's and the K slice it computes
+    const int wr = KS == 1 ? wave >> 1 : (KS == 2 ? wave & 1 : 0);
+    const int wc = KS == 1 ? wave & 1 : 0;
+    const int ksl = KS == 1 ? 0 : (KS == 2 ? wave >> 1 : wave);
     const int lr = lane & 15, lq = lane >> 4;
-    const int rw = tm * BM + wr * 32, cw = tn * BN + wc * 32;
+    const int rw = tm * TBM + wr * 32, cw = tn * TBN + wc * 32;
     const CT* __restrict__ A = (const CT*)g.A;
     const CT* __restrict__ B = (const CT*)g.B;
     CT* __restrict__ C = (CT*)g.C;
@@ -403,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
     const bool full = (rw + 32 <= g.M) && (cw + 32 <= g.N);
 
     // ---- accumulators start from C (SUB), from B0 + lam B (RESID), from zero
-    // (TRI; GEN, whose C is added at the end)
+    // (TRI; GEN, whose C is added at the end; K slices after the first)
     V accR[2][2], accI[2][2];
     int clim0 = g.M, clim1 = g.M, blim0 = g.K, blim1 = g.K;
     int cshv[2] = {0, 0};
@@ -442,7 +454,7 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             for (int v = 0; v < 4; ++v) {
                 const int row = rw + i * 16 + Tr::out_row(lq, v);
                 CT c{0, 0};
-                if (!TRI && !GEN && !TRM && col < g.N && row < cl) {
+                if (!TRI && !GEN && !TRM && ksl == 0 && col < g.N && row < cl) {
                     if (RES) {
                         const zd b0 = g.B0[(long)col * g.ldb0 + row];
                         const CT x = B[(long)col * g.ldb + row];
@@ -607,10 +619,11 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             // instead of recomputing products; the main loop runs while every
             // refill lies inside K, a short guarded tail drains the ring.
             const long sA = A_TR ? 4 : 4L * lda, sB = TRI ? 4L * g.ldb : 4;
-            const CT* qa0 = A_TR ? A + (long)ra0 * lda + lq : A + (long)lq * lda + ra0;
-            const CT* qa1 = A_TR ? A + (long)ra1 * lda + lq : qa0 + 16;
-            const CT* qb0 = TRI ? B + (long)lq * g.ldb + cb0 : B + (long)cb0 * g.ldb + lq;
-            const CT* qb1 = TRI ? qb0 + 16 : B + (long)cb1 * g.ldb + lq;
+            const long k0 = 4L * kfirst + lq;
+            const CT* qa0 = A_TR ? A + (long)ra0 * lda + k0 : A + k0 * lda + ra0;
+            const CT* qa1 = A_TR ? A + (long)ra1 * lda + k0 : qa0 + 16;
+            const CT* qb0 = TRI ? B + k0 * g.ldb + cb0 : B + (long)cb0 * g.ldb + k0;
+            const CT* qb1 = TRI ? qb0 + 16 : B + (long)cb1 * g.ldb + k0;
             auto next = [&](CT& a0, CT& a1, CT& b0, CT& b1) __attribute__((always_inline)) {
                 a0 = *qa0; a1 = *qa1; b0 = *qb0; b1 = *qb1;
                 qa0 += sA; qa1 += sA; qb0 += sB; qb1 += sB;
@@ -705,10 +718,64 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
             done = nfree;
         }
         kloop(std::true_type{}, A, g.lda, done, nk - done);
-    } else if (unmasked) {
-        kloop(std::false_type{}, A, g.lda, kfirst0, nloc0);
+    } else if (KS == 1) {
+        if (unmasked)
+            kloop(std::false_type{}, A, g.lda, kfirst0, nloc0);
+        else
+            kloop(std::true_type{}, A, g.lda, kfirst0, nloc0);
     } else {
-        kloop(std::true_type{}, A, g.lda, kfirst0, nloc0);
+        // this wavefront's K slice: consecutive k-steps, the last slice shorter
+        const int per = (nloc0 + KS - 1) / KS;
+        const int kf = kfirst0 + ksl * per, nl = min(per, nloc0 - ksl * per);
+        if (full && (g.K & 3) == 0 && nl >= DEPTH && !RES && plain_ok)
+            kloop(std::false_type{}, A, g.lda, kf, nl);
+        else
+            kloop(std::true_type{}, A, g.lda, kf, nl);
+    }
+
+    if constexpr (KS > 1) {
+        // Partial sums through LDS, one 16 KB (FP64) slot per wavefront tile
+        // and round: KS = 2 adds s0 + s1, KS = 4 (s0 + s2) + (s1 + s3). Every
+        // wavefront reaches every barrier (the early returns above are taken
+        // by the whole workgroup or not at all: its wavefronts share columns).
+        __shared__ T red[2][32][64];
+        auto put = [&](int slot) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        red[slot][(i * 2 + j) * 4 + v][lane] = accR[i][j][v];
+                        red[slot][16 + (i * 2 + j) * 4 + v][lane] = accI[i][j][v];
+                    }
+        };
+        auto add = [&](int slot) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        accR[i][j][v] += red[slot][(i * 2 + j) * 4 + v][lane];
+                        accI[i][j][v] += red[slot][16 + (i * 2 + j) * 4 + v][lane];
+                    }
+        };
+        if (KS == 2) {
+            if (ksl == 1) put(wr);
+            __syncthreads();
+            if (ksl == 1) return;
+            add(wr);
+        } else {
+            if (ksl >= 2) put(ksl - 2);
+            __syncthreads();
+            if (ksl < 2) add(ksl);
+            __syncthreads();
+            if (ksl == 1) put(0);
+            __syncthreads();
+            if (ksl != 0) return;
+            add(0);
+        }
     }
 
     // ---- epilogue
@@ -749,10 +816,67 @@ hipError_t go(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Compute units of the current device, read once per device.
+int device_cus() {
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int c = cus[dev].load(std::memory_order_relaxed);
+    if (c <= 0) {
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+            c = 256;
+        cus[dev].store(c, std::memory_order_relaxed);
+    }
+    return c;
+}
+
+// K split of the direct GEMM for a launch shape (the measured cost of the
+// shapes of the blocked solve on MI355X, FP64 and FP32, N = 128 ... 4096):
+//  * a wavefront alone on its SIMD keeps the matrix pipe nearly as busy as
+//    two, so time follows the k-steps of the SIMD with the most wavefronts,
+//    ceil(waves / SIMDs) x k-steps per wavefront, plus about 16 k-steps for
+//    every round of resident workgroups (ring fill, C, the slices' sums);
+//  * a split-2 launch needing more than one round lost everywhere it was
+//    measured (the workgroups of the last round pile up on the CUs that
+//    free up first), so it is used within one round only.
+// A split must promise a tenth less than the best smaller one.
+int pick_split(const GemmArgs& g, int occupancy) {
+    const long simds = 4L * device_cus();
+    const long nks = (g.K + 3) / 4;
+    long best = 0;
+    int best_ks = 1;
+    for (int ks = 1; ks <= 4; ks *= 2) {
+        const int tbm = ks == 4 ? 32 : 64, tbn = ks == 1 ? 64 : 32;
+        const long waves = 4L * ((g.M + tbm - 1) / tbm) * ((g.N + tbn - 1) / tbn);
+        const long rounds = (waves + occupancy * simds - 1) / (occupancy * simds);
+        if (ks == 2 && rounds > 1) continue;
+        const long t = (waves + simds - 1) / simds * ((nks + ks - 1) / ks) + 16 * rounds;
+        if (ks == 1 || 10 * t < 9 * best) {
+            best = t;
+            best_ks = ks;
+        }
+    }
+    return best_ks;
+}
+
 template <typename T, int OP, int AM, bool SAFE, bool VARLEN>
 hipError_t go_direct(const GemmArgs& g, hipStream_t s) {
+    // wavefronts per tile: two per SIMD fit in FP64, three in FP32 (registers)
+    const int ks = (OP != GOP_SUB && OP != GOP_RESID) ? 1 : g.split ? g.split : pick_split(g, sizeof(T) == 8 ? 2 : 3);
+    if constexpr (OP == GOP_SUB || OP == GOP_RESID) {
+        if (ks == 2) {
+            const int TM = (g.M + 63) / 64, TN = (g.N + 31) / 32;
+            hipLaunchKernelGGL((k_gemm_direct<T, 4, OP, AM, SAFE, VARLEN, 2>), dim3(TM * TN), dim3(NT), 0, s, g);
+            return hipGetLastError();
+        }
+        if (ks == 4) {
+            const int TM = (g.M + 31) / 32, TN = (g.N + 31) / 32;
+            hipLaunchKernelGGL((k_gemm_direct<T, 4, OP, AM, SAFE, VARLEN, 4>), dim3(TM * TN), dim3(NT), 0, s, g);
+            return hipGetLastError();
+        }
+    }
     const int TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
-    hipLaunchKernelGGL((k_gemm_direct<T, 4, OP, AM, SAFE, VARLEN>), dim3(TM * TN), dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((k_gemm_direct<T, 4, OP, AM, SAFE, VARLEN, 1>), dim3(TM * TN), dim3(NT), 0, s, g);
     return hipGetLastError();
 }
 

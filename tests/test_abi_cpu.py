@@ -49,13 +49,19 @@ def test_argument_errors_without_gpu():
 
 
 def test_option_errors_without_gpu():
-    # mst_opts.reserved must be 0 and refine_tol must not be NaN (checked on the host)
+    # mst_opts.gemm_split must be 0, 1, 2 or 4 and refine_tol must not be NaN
+    # (checked on the host)
     from paper_1607_01477_amd import _lib
     lib = _lib.load()
-    o = _lib.MstOpts()
-    o.reserved = 1
-    assert lib.mstrsm(0, 7, None, 1, None, None, 1, ctypes.byref(o), None) == _lib.MST_EARG
-    assert lib.mst_last_bad_arg() == 8
+    for bad in (3, -1, 8):
+        o = _lib.MstOpts()
+        o.gemm_split = bad
+        assert lib.mstrsm(0, 7, None, 1, None, None, 1, ctypes.byref(o), None) == _lib.MST_EARG
+        assert lib.mst_last_bad_arg() == 8
+    for good in (0, 1, 2, 4):
+        o = _lib.MstOpts()
+        o.gemm_split = good
+        assert lib.mstrsm(0, 7, None, 1, None, None, 1, ctypes.byref(o), None) == _lib.MST_OK
     o = _lib.MstOpts()
     o.refine_tol = float("nan")
     assert lib.mstrsm(0, 7, None, 1, None, None, 1, ctypes.byref(o), None) == _lib.MST_EARG
