@@ -35,7 +35,7 @@ def version() -> str:
 
 
 def _opts(nb=0, outer_nb=0, precision=0, max_sweeps=0, omega_log2=0, force_phase2=0, fuse=True,
-          staged=False, overlap=False, refine_tol=0.0, refine_report=None, gemm_split=0):
+          staged=False, overlap=False, refine_tol=0.0, refine_report=None, gemm_split=0, fuse_width=0):
     o = MstOpts()
     o.gemm_split = int(gemm_split)
     o.refine_tol = float(refine_tol)
@@ -44,7 +44,9 @@ def _opts(nb=0, outer_nb=0, precision=0, max_sweeps=0, omega_log2=0, force_phase
     o.gemm_staged = 1 if staged else 0
     o.nb, o.outer_nb, o.precision = int(nb), int(outer_nb), int(precision)
     o.max_sweeps, o.omega_log2, o.force_phase2 = int(max_sweeps), int(omega_log2), int(force_phase2)
-    o.fuse_blocks = 0 if fuse else -1
+    if fuse_width not in (0, 4, 16):
+        raise ValueError("fuse_width must be 0 (automatic), 4 or 16")
+    o.fuse_blocks = {0: 0, 16: 1, 4: 2}[fuse_width] if fuse else -1
     return o
 
 
@@ -114,7 +116,7 @@ def _mat(t: torch.Tensor, name: str) -> torch.Tensor:
 
 
 def mstrsm(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2, fuse=True, staged=False,
-           overlap=False, refine_tol=0.0, refine_report=None, gemm_split=0):
+           overlap=False, refine_tol=0.0, refine_report=None, gemm_split=0, fuse_width=0):
     """X with (U - shifts[j] I) X[:, j] = B[:, j]; B is overwritten when it is
     already column-major complex128 (the result is returned either way).
     precision=1: FP32 substitution GEMMs + FP64 refinement, at most max_sweeps
@@ -135,14 +137,14 @@ def mstrsm(U, shifts, B, *, nb=0, outer_nb=0, precision=0, max_sweeps=2, fuse=Tr
                              % (max_sweeps + 1))
     o = _opts(nb=nb, outer_nb=outer_nb, precision=precision, max_sweeps=max_sweeps, fuse=fuse,
               staged=staged, overlap=overlap, refine_tol=refine_tol, refine_report=refine_report,
-              gemm_split=gemm_split)
+              gemm_split=gemm_split, fuse_width=fuse_width)
     rc = _lib.load().mstrsm(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), ctypes.byref(o), _stream())
     _lib.check("mstrsm", rc)
     return X
 
 
 def mstrsm_safe(U, shifts, B, col_len=None, *, nb=0, outer_nb=0, omega_log2=0, fuse=True,
-                staged=False, overlap=False, force_phase2=False, gemm_split=0):
+                staged=False, overlap=False, force_phase2=False, gemm_split=0, fuse_width=0):
     """Safe solve: returns (X, scale, scale_log2) with
     (U - shifts[j] I) X[:, j] = scale[j] B[:, j], scale[j] = 2^-scale_log2[j]."""
     U = _mat(U, "U")
@@ -155,7 +157,7 @@ def mstrsm_safe(U, shifts, B, col_len=None, *, nb=0, outer_nb=0, omega_log2=0, f
     scale = torch.empty(n, dtype=torch.float64, device=X.device)
     klog = torch.empty(n, dtype=torch.int32, device=X.device)
     o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2, fuse=fuse, staged=staged,
-              overlap=overlap, force_phase2=force_phase2, gemm_split=gemm_split)
+              overlap=overlap, force_phase2=force_phase2, gemm_split=gemm_split, fuse_width=fuse_width)
     rc = _lib.load().mstrsm_safe(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), _p(cl), _p(scale),
                                  _p(klog), ctypes.byref(o), _stream())
     _lib.check("mstrsm_safe", rc)
@@ -163,7 +165,7 @@ def mstrsm_safe(U, shifts, B, col_len=None, *, nb=0, outer_nb=0, omega_log2=0, f
 
 
 def mstrsm_safe_noalloc(U, shifts, B, col_len=None, *, scale=None, scale_log2=None, nb=0, outer_nb=0,
-                        omega_log2=0, fuse=True, staged=False, gemm_split=0):
+                        omega_log2=0, fuse=True, staged=False, gemm_split=0, fuse_width=0):
     """mstrsm_safe without device allocation inside the library: the workspace
     is the library's static scratch (16 MiB per device; calls that overlap on
     one device race). scale (float64) and scale_log2 (int32) may be given as
@@ -181,7 +183,7 @@ def mstrsm_safe_noalloc(U, shifts, B, col_len=None, *, scale=None, scale_log2=No
     klog = torch.empty(n, dtype=torch.int32, device=X.device) if scale_log2 is None else \
         _vec(scale_log2, n, "scale_log2", torch.int32)
     o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2, fuse=fuse, staged=staged,
-              gemm_split=gemm_split)
+              gemm_split=gemm_split, fuse_width=fuse_width)
     rc = _lib.load().mstrsm_safe_noalloc(m, n, _p(U), _ld(U), _p(s), _p(X), _ld(X), _p(cl), _p(scale),
                                          _p(klog), ctypes.byref(o), _stream())
     _lib.check("mstrsm_safe_noalloc", rc)
@@ -305,7 +307,7 @@ def residual(U, shifts, X, B0):
     return R
 
 
-def triang_eig(T, *, nb=0, outer_nb=0, omega_log2=0, force_phase2=False, gemm_split=0):
+def triang_eig(T, *, nb=0, outer_nb=0, omega_log2=0, force_phase2=False, gemm_split=0, fuse_width=0):
     """TriangEig (Alg 6): returns (eigvals, Z, scale_log2) with T Z[:, j] =
     eigvals[j] Z[:, j], Z upper triangular, Z[j, j] = 2^-scale_log2[j]."""
     T = _mat(T, "T")
@@ -316,7 +318,7 @@ def triang_eig(T, *, nb=0, outer_nb=0, omega_log2=0, force_phase2=False, gemm_sp
     ev = torch.empty(m, dtype=torch.complex128, device=T.device)
     klog = torch.empty(m, dtype=torch.int32, device=T.device)
     o = _opts(nb=nb, outer_nb=outer_nb, omega_log2=omega_log2, force_phase2=force_phase2,
-              gemm_split=gemm_split)
+              gemm_split=gemm_split, fuse_width=fuse_width)
     rc = _lib.load().mst_triang_eig(m, _p(T), _ld(T), _p(Z), max(1, m), _p(ev), _p(klog),
                                     ctypes.byref(o), _stream())
     _lib.check("mst_triang_eig", rc)

@@ -124,6 +124,7 @@ double gemm_flops(const GemmArgs& g) {
 struct Opts {
     int nb = 16, outer = 256, precision = 0, sweeps = 2, omega_log2 = 960;
     bool fuse = true;
+    int fuse_width = 0;
     int staged = 0;
     int split = 0;
     bool overlap = false;
@@ -148,8 +149,9 @@ mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
     if (r.sweeps < 1 || r.sweeps > 3) return bad(pos);
     if (o->omega_log2) r.omega_log2 = o->omega_log2;
     if (r.omega_log2 < 8 || r.omega_log2 > 1000) return bad(pos);
-    if (o->fuse_blocks != 0 && o->fuse_blocks != -1) return bad(pos);
-    r.fuse = o->fuse_blocks == 0;
+    if (o->fuse_blocks < -1 || o->fuse_blocks > 2) return bad(pos);
+    r.fuse = o->fuse_blocks >= 0;
+    r.fuse_width = o->fuse_blocks == 1 ? 16 : (o->fuse_blocks == 2 ? 4 : 0);
     if (o->gemm_staged != 0 && o->gemm_staged != 1) return bad(pos);
     r.staged = o->gemm_staged;
     if (o->overlap != 0 && o->overlap != 1) return bad(pos);
@@ -306,6 +308,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
         b.b32 = mixed ? W32 : nullptr; b.ldb32 = ldw;
         b.skip = mixed ? o.skip : nullptr;
         b.col_len = col_len;
+        b.width = o.fuse_width;
         if (safe) {
             b.safe = *safe;
             b.use_safe = 1;

@@ -29,6 +29,8 @@
 //             into one launch per outer block.
 #include "common.h"
 
+#include <atomic>
+
 namespace mst {
 namespace {
 
@@ -220,44 +222,74 @@ struct BlockSolve {
     double br[SPW], bi[SPW], pr[SPW], pi[SPW], cdl[SPW], Gs[SPW], Ms[SPW];
     int pe[SPW], kblk[SPW];
 
+    // The pivot of one row d = dr + i di (1 + 0i outside the block): cabs1(d)
+    // and its scaled reciprocal (safe: 1/d = 2^-e (pr + i pi); plain: pr + i pi
+    // = 1/d, e = 0).
+    static __device__ __forceinline__ void pivot_entry(double dr, double di, double& pr_, double& pi_,
+                                                       int& pe_, double& cd_) {
+        cd_ = cabs1(dr, di);
+        // scaled reciprocal: d = 2^e d', 1/d = 2^-e conj(d')/|d'|^2
+        const double am = fmax(fabs(dr), fabs(di));
+        const int e = (am > 0.0) ? ilogb(am) : 0;
+        const double sr = ldexp(dr, -e), si = ldexp(di, -e);
+        const double den = sr * sr + si * si;
+        if (SAFE) {
+            pr_ = sr / den;
+            pi_ = -si / den;
+            pe_ = e;
+        } else {
+            // plain solve: 1/d itself (overflows only for |d| < 2^-1022, a
+            // singular system for this solver)
+            pr_ = ldexp(sr / den, -e);
+            pi_ = ldexp(-si / den, -e);
+            pe_ = 0;
+        }
+    }
+
     // pivot d = U(r,r) - lambda (forward) or its conjugate (adjoint); exact
     // zeros replaced by delta in the safe variant
     // (GEN: d = U(r,r) - lambda V(r,r), V's diagonal in Vd)
+    static __device__ __forceinline__ void pivot_value(zd u, zd l, double delta, double& dr, double& di,
+                                                       const zd* vd = nullptr) {
+        if constexpr (GEN) {
+            const zd d = pencil(u, *vd, l);
+            dr = d.re;
+            di = d.im;
+        } else {
+            dr = u.re - l.re;
+            di = CJ ? (u.im + l.im) : (u.im - l.im);
+        }
+        if (SAFE && dr == 0.0 && di == 0.0) dr = delta;
+    }
+
     __device__ __forceinline__ void pivots(const zd* Ud, int r, int bs, const zd (&lam)[SPW],
                                            const bool (&jv)[SPW], double delta,
                                            const zd* Vd = nullptr) {
 #pragma unroll
         for (int s = 0; s < SPW; ++s) {
             double dr = 1.0, di = 0.0;
-            if (r < bs && jv[s]) {
-                const zd u = Ud[r];
-                if constexpr (GEN) {
-                    const zd d = pencil(u, Vd[r], lam[s]);
-                    dr = d.re;
-                    di = d.im;
-                } else {
-                    dr = u.re - lam[s].re;
-                    di = CJ ? (u.im + lam[s].im) : (u.im - lam[s].im);
-                }
-                if (SAFE && dr == 0.0 && di == 0.0) dr = delta;
-            }
-            cdl[s] = cabs1(dr, di);
-            // scaled reciprocal: d = 2^e d', 1/d = 2^-e conj(d')/|d'|^2
-            const double am = fmax(fabs(dr), fabs(di));
-            const int e = (am > 0.0) ? ilogb(am) : 0;
-            const double sr = ldexp(dr, -e), si = ldexp(di, -e);
-            const double den = sr * sr + si * si;
-            if (SAFE) {
-                pr[s] = sr / den;
-                pi[s] = -si / den;
-                pe[s] = e;
-            } else {
-                // plain solve: 1/d itself (overflows only for |d| < 2^-1022, a
-                // singular system for this solver)
-                pr[s] = ldexp(sr / den, -e);
-                pi[s] = ldexp(-si / den, -e);
-                pe[s] = 0;
-            }
+            if (r < bs && jv[s]) pivot_value(Ud[r], lam[s], delta, dr, di, GEN ? Vd + r : nullptr);
+            pivot_entry(dr, di, pr[s], pi[s], pe[s], cdl[s]);
+        }
+        reset();
+    }
+
+    // the pivots from values formed beforehand (pivot_entry)
+    __device__ __forceinline__ void pivots_given(const double (&pr_)[SPW], const double (&pi_)[SPW],
+                                                 const int (&pe_)[SPW], const double (&cd_)[SPW]) {
+#pragma unroll
+        for (int s = 0; s < SPW; ++s) {
+            pr[s] = pr_[s];
+            pi[s] = pi_[s];
+            pe[s] = pe_[s];
+            cdl[s] = cd_[s];
+        }
+        reset();
+    }
+
+    __device__ __forceinline__ void reset() {
+#pragma unroll
+        for (int s = 0; s < SPW; ++s) {
             kblk[s] = 0;
             Ms[s] = 0.0;
             Gs[s] = 0.0;
@@ -641,6 +673,19 @@ __device__ __forceinline__ void couple16(const zd (&uo)[16], const double (&xr)[
         ai[s][K & 1] = fma(uo[K].re, yi, fma(uo[K].im, yr, ai[s][K & 1]));
     }
     if constexpr (K < 15) couple16<SPW, K + 1>(uo, xr, xi, ar, ai);
+}
+
+// The same product for one shift with the Re u and Im u terms in separate
+// partial sums, so no step holds a dependent pair of FMAs (the narrow kernel).
+template <int K>
+__device__ __forceinline__ void couple16s(const zd (&uo)[16], double xr, double xi, double (&ar)[4],
+                                          double (&ai)[4]) {
+    const double yr = bcast16<K>(xr), yi = bcast16<K>(xi);
+    ar[K & 1] = fma(uo[K].re, yr, ar[K & 1]);
+    ar[2 + (K & 1)] = fma(-uo[K].im, yi, ar[2 + (K & 1)]);
+    ai[K & 1] = fma(uo[K].re, yi, ai[K & 1]);
+    ai[2 + (K & 1)] = fma(uo[K].im, yr, ai[2 + (K & 1)]);
+    if constexpr (K < 15) couple16s<K + 1>(uo, xr, xi, ar, ai);
 }
 
 // ---------------------------------------------------------------- fused outer block
@@ -1160,6 +1205,430 @@ __global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_bl
     }
 }
 
+// ---------------------------------------------------------------- narrow fused outer block
+// The outer block of k_block for 4 shifts per workgroup of 4 wavefronts, for
+// launches whose 16-shift workgroups would leave compute units idle (few
+// shifts, or few columns reaching an outer block in the triangular-eigenvector
+// solve). Wavefront 0 solves the diagonal blocks exactly as a solving
+// wavefront of k_block (one shift per lane group). Wavefronts 1-3 apply each
+// solved block to the rows above it with FP64 FMAs, one row per lane and all
+// four shifts: at four shifts a 16-column matrix-core tile would be three
+// quarters padding, and the substitution chain then shares its SIMD's FP64
+// pipeline with no matrix-core products (the four wavefronts of a workgroup
+// run on four different SIMDs). Rows of the update go in 64-row chunks:
+// wavefront u takes chunks u - 1 and u + 2, its first chunk's U entries
+// loaded during the pass before. Per element the updates keep the order of
+// the blocks, as in k_block.
+constexpr int kColsN = 4;     // shifts per narrow workgroup
+constexpr int kWGN = 256;     // threads per narrow workgroup
+template <bool SAFE, bool MIXED, bool VARLEN>
+__global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
+    constexpr int NB = 16, NBB = NB * NB;
+    constexpr int PERS = 2 * NBB / kWGN;
+    __shared__ zd Bl[kColsN * kSP];
+    __shared__ zd Us[2][NBB];
+    __shared__ zd Uo[2][NBB];
+    __shared__ zd Ud[2][NB];
+    __shared__ double Gl[kColsN];
+    __shared__ int kcl[kColsN], dkl[2][kColsN], Ll[kColsN];
+    // pivots of every row of the outer block and shift (formed in the prologue,
+    // off the substitution chain): reciprocal, exponent (safe), cabs1 (safe)
+    __shared__ double Ppr[kColsN][kRowsMax], Ppi[kColsN][kRowsMax];
+    __shared__ int Ppe[SAFE ? kColsN : 1][SAFE ? kRowsMax : 1];
+    __shared__ double Pcd[SAFE ? kColsN : 1][SAFE ? kRowsMax : 1];
+
+    if (MIXED && a.skip && *a.skip) return;   // refinement stopped
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col0 = blockIdx.x * kColsN;
+    const int iS = a.iS, rows = a.rows;
+    const int w = a.safe.omega_log2;
+    const double omega = ldexp(1.0, w);
+    const double delta = SAFE ? *a.safe.delta : 0.0;
+    const int nsub = (rows + NB - 1) / NB;
+
+    // column lengths of the workgroup's shifts
+    int Lmax = 0;
+#pragma unroll
+    for (int c = 0; c < kColsN; ++c) {
+        const int j = col0 + c;
+        int L = 0;
+        if (j < a.n) {
+            L = a.m;
+            if (VARLEN) {
+                L = a.col_len[j];
+                L = L < 0 ? 0 : (L > a.m ? a.m : L);
+            }
+        }
+        Lmax = max(Lmax, L);
+        if (tid == c) Ll[c] = L;
+    }
+    if (VARLEN && Lmax <= iS) {
+        // no column reaches the outer block: nothing to solve, the exponents
+        // after each of its diagonal blocks are the current ones
+        if (SAFE && tid < kColsN * nsub) {
+            const int c = tid % kColsN, q = a.qa + tid / kColsN;
+            if (col0 + c < a.n) a.safe.kb[(long)q * a.n + col0 + c] = a.safe.kcur[col0 + c];
+        }
+        return;
+    }
+    if (tid < kColsN) {
+        const int j = col0 + tid;
+        dkl[0][tid] = 0;
+        dkl[1][tid] = 0;
+        if (SAFE) {
+            Gl[tid] = (j < a.n) ? a.safe.G[j] : 0.0;
+            kcl[tid] = (j < a.n) ? a.safe.kcur[j] : 0;
+        }
+    }
+    // pivots: U(r, r) - lambda_j for every row of the outer block and shift
+    // (1 + 0i outside the block or past the shifts)
+    {
+        constexpr int PER = kColsN * kRowsMax / kWGN;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * kWGN;
+            const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
+            double dr = 1.0, di = 0.0;
+            if (rr < rows && col0 + c < a.n)
+                BlockSolve<NB, 1, EV_UPPER_N, SAFE>::pivot_value(a.U[(long)(iS + rr) * a.ldu + iS + rr],
+                                                                 a.lam[col0 + c], delta, dr, di);
+            double pr, pi, cd;
+            int pe;
+            BlockSolve<NB, 1, EV_UPPER_N, SAFE>::pivot_entry(dr, di, pr, pi, pe, cd);
+            Ppr[c][rr] = pr;
+            Ppi[c][rr] = pi;
+            if (SAFE) {
+                Ppe[c][rr] = pe;
+                Pcd[c][rr] = cd;
+            }
+        }
+    }
+    // right-hand sides of the outer block -> LDS (rows outside the column: 0)
+    {
+        constexpr int PER = kColsN * kRowsMax / kWGN;
+        zd st[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * kWGN;
+            const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
+            const int j = col0 + c;
+            int L = 0;
+            if (j < a.n) {
+                L = a.m;
+                if (VARLEN) {
+                    L = a.col_len[j];
+                    L = L < 0 ? 0 : (L > a.m ? a.m : L);
+                }
+            }
+            st[e] = zd{0.0, 0.0};
+            if (rr < rows && iS + rr < L) {
+                if (MIXED) {
+                    const zf v = a.b32[(long)j * a.ldb32 + iS + rr];
+                    st[e] = zd{v.re, v.im};
+                } else {
+                    st[e] = a.B[(long)j * a.ldb + iS + rr];
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * kWGN;
+            const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
+            Bl[c * kSP + rr] = st[e];
+        }
+    }
+
+    // pass stp solves block ql (from the bottom) and applies block qp = ql + 1
+    // (solved in the pass before) to the rows above ql
+    struct Pass {
+        int lr0, bs, p0, bsp;
+    };
+    auto pass_of = [&](int stp) __attribute__((always_inline)) {
+        Pass g;
+        const int ql = nsub - 1 - stp;
+        g.lr0 = ql * NB;
+        g.bs = min(NB, rows - g.lr0);
+        g.p0 = (ql + 1) * NB;
+        g.bsp = stp > 0 ? min(NB, rows - g.p0) : 0;
+        return g;
+    };
+
+    // staging of the diagonal and coupling blocks of a pass (as in k_block)
+    zd ust[PERS];
+    bool usv[PERS];
+    auto stage_load = [&](int stp) __attribute__((always_inline)) {
+        const Pass g = pass_of(stp);
+        const int i0 = iS + g.lr0, p0 = iS + g.p0;
+#pragma unroll
+        for (int e = 0; e < PERS; ++e) {
+            const int t = tid + e * kWGN;
+            long off = (long)i0 * a.ldu + i0;   // the block's first pivot: always valid
+            bool v;
+            if (t < NBB) {
+                const int c = t / NB, rr = t - c * NB;
+                v = rr <= c && c < g.bs;
+                off = v ? (long)(i0 + c) * a.ldu + i0 + rr : off;
+            } else {
+                const int t2 = t - NBB;
+                const int k = t2 / NB, r = t2 - k * NB;
+                v = r < g.bs && k < g.bsp;
+                off = v ? (long)(p0 + k) * a.ldu + i0 + r : off;
+            }
+            usv[e] = v;
+            ust[e] = a.U[off];
+        }
+    };
+    auto stage_store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int e = 0; e < PERS; ++e) {
+            const int t = tid + e * kWGN;
+            const zd v = usv[e] ? ust[e] : zd{0.0, 0.0};
+            if (t < NBB) {
+                const int c = t / NB, rr = t - c * NB;
+                if (rr == c) {
+                    Ud[buf][rr] = v;
+                    Us[buf][c * NB + rr] = zd{0.0, 0.0};
+                } else {
+                    Us[buf][c * NB + rr] = v;
+                }
+            } else {
+                const int t2 = t - NBB;
+                const int k = t2 / NB, r = t2 - k * NB;
+                Uo[buf][k * NB + r] = v;
+            }
+        }
+    };
+    stage_load(0);
+    stage_store(0);
+    __syncthreads();
+
+    // updating wavefronts: U(iS + row, iS + p0 + k), k < 16, of one 64-row
+    // chunk (row = chunk * 64 + lane), from clamped positions (in bounds; rows
+    // outside the update are never stored, entries past block p are zeroed)
+    auto uload = [&](zd (&u)[NB], const Pass& g, int chunk) __attribute__((always_inline)) {
+        const int row = min(chunk * 64 + lane, max(g.lr0 - 1, 0));
+        // one running pointer down the columns (one 64-bit add per step),
+        // held at the block's last column past it
+        const zd* up = a.U + (long)(iS + g.p0) * a.ldu + iS + row;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            u[k] = *up;
+            if (k + 1 < g.bsp) up += a.ldu;
+        }
+    };
+    // rows of the chunk -= U(rows, block p) x(block p), all four shifts per
+    // step k. The x of step k + 3 (four LDS broadcast reads) are issued with
+    // the FMAs of step k, and rows are stored after the last step. An empty
+    // asm statement after each step takes the accumulators as operands and
+    // clobbers memory: it keeps the step's FMAs before it and later reads
+    // after it, so the compiler neither sinks each read next to its FMAs (an
+    // LDS round trip on every step) nor hoists all of them to the top (every
+    // x live at once). Rows p0 + k for
+    // k >= bsp lie past the outer block, where Bl holds zeros (p0 + 15 <=
+    // 255), so no step needs a mask. Each component keeps two accumulators
+    // (the terms with Re u and with Im u), so a step's 16 FMAs are
+    // independent. In the safe form the rows first take the exponent change
+    // of block p.
+    auto uapply = [&](const zd (&u)[NB], const Pass& g, int chunk, int buf) __attribute__((always_inline)) {
+        const int row = chunk * 64 + lane;   // < 256: at most four chunks
+        const bool ok = row < g.lr0;
+        const zd* xb = Bl + g.p0;
+        double sr[kColsN], si[kColsN], tr[kColsN], ti[kColsN];
+        zd x0[kColsN], x1[kColsN], x2[kColsN], x3[kColsN];
+#pragma unroll
+        for (int c = 0; c < kColsN; ++c) {
+            zd v = Bl[c * kSP + row];
+            x0[c] = xb[c * kSP];
+            x1[c] = xb[c * kSP + 1];
+            x2[c] = xb[c * kSP + 2];
+            if (SAFE) {
+                const int dk = dkl[buf ^ 1][c];
+                v.re = ldexp(v.re, -dk);
+                v.im = ldexp(v.im, -dk);
+            }
+            sr[c] = v.re;
+            si[c] = v.im;
+            tr[c] = 0.0;
+            ti[c] = 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            if (k + 3 < NB) {
+#pragma unroll
+                for (int c = 0; c < kColsN; ++c) x3[c] = xb[c * kSP + k + 3];
+            }
+#pragma unroll
+            for (int c = 0; c < kColsN; ++c) {
+                sr[c] = fma(-u[k].re, x0[c].re, sr[c]);
+                si[c] = fma(-u[k].re, x0[c].im, si[c]);
+                tr[c] = fma(u[k].im, x0[c].im, tr[c]);
+                ti[c] = fma(-u[k].im, x0[c].re, ti[c]);
+            }
+            asm volatile(""
+                         : "+v"(sr[0]), "+v"(sr[1]), "+v"(sr[2]), "+v"(sr[3]), "+v"(si[0]), "+v"(si[1]),
+                           "+v"(si[2]), "+v"(si[3]), "+v"(tr[0]), "+v"(tr[1]), "+v"(tr[2]), "+v"(tr[3]),
+                           "+v"(ti[0]), "+v"(ti[1]), "+v"(ti[2]), "+v"(ti[3])
+                         :
+                         : "memory");
+#pragma unroll
+            for (int c = 0; c < kColsN; ++c) {
+                x0[c] = x1[c];
+                x1[c] = x2[c];
+                x2[c] = x3[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kColsN; ++c)
+            if (ok) Bl[c * kSP + row] = zd{sr[c] + tr[c], si[c] + ti[c]};
+    };
+
+    // The solving and the updating wavefronts run separate pass loops (the
+    // branch is uniform per wavefront), each with one barrier per pass, so
+    // neither holds the other's registers.
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    if (wv == 0) {
+        // shift slot grp = lane / 16, row r = lane % 16
+        const int grp = lane >> 4, r = lane & 15, base = grp * NB;
+        const bool jv[1] = {col0 + grp < a.n};
+        double xpr[1] = {0.0}, xpi[1] = {0.0};
+        for (int stp = 0; stp < nsub; ++stp) {
+            const int buf = stp & 1;
+            const Pass g = pass_of(stp);
+            const int q = a.qa + nsub - 1 - stp;
+            const int i0 = iS + g.lr0;
+            if (stp + 1 < nsub) stage_load(stp + 1);
+            // ---- rows of block q: apply x of block p, then back substitution
+            BlockSolve<NB, 1, EV_UPPER_N, SAFE> S;
+            const int c = grp;
+            const bool act = jv[0] && (i0 < Ll[c]);
+            zd b{0.0, 0.0};
+            if (r < g.bs) b = Bl[c * kSP + g.lr0 + r];
+            if (SAFE && g.bsp > 0) {
+                const int dk = dkl[buf ^ 1][c];
+                b.re = ldexp(b.re, -dk);
+                b.im = ldexp(b.im, -dk);
+            }
+            S.br[0] = b.re;
+            S.bi[0] = b.im;
+            if (g.bsp > 0) {
+                double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+                zd uo[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) uo[k] = Uo[buf][k * NB + r];
+                couple16s<0>(uo, xpr[0], xpi[0], ar, ai);
+                S.br[0] -= (ar[0] + ar[1]) + (ar[2] + ar[3]);
+                S.bi[0] -= (ai[0] + ai[1]) + (ai[2] + ai[3]);
+            }
+            const double cn_l = (SAFE && r < g.bs) ? a.safe.cn_in[i0 + r] : 0.0;
+            {
+                // rows past a partial block take 1 + 0i, as the table holds
+                // for rows past the outer block
+                const int pr_row = g.lr0 + r;
+                const bool in = r < g.bs && jv[0];
+                const double ppr[1] = {in ? Ppr[c][pr_row] : 1.0};
+                const double ppi[1] = {in ? Ppi[c][pr_row] : -0.0};   // pivot_entry(1, 0)
+                const int ppe[1] = {SAFE && in ? Ppe[SAFE ? c : 0][SAFE ? pr_row : 0] : 0};
+                const double pcd[1] = {SAFE && in ? Pcd[SAFE ? c : 0][SAFE ? pr_row : 0] : 1.0};
+                S.pivots_given(ppr, ppi, ppe, pcd);
+            }
+            S.run(Us[buf], g.bs, r, base, cn_l, w, omega, nullptr, zd{0.0, 0.0}, SAFE && a.safe.force_checked);
+            if (SAFE) {
+                const double asum = a.safe.above_sum[q];
+                double Gj = Gl[c];
+                const int dk = S.column_bound(0, act, asum, &Gj, w, omega);
+                if (r == 0 && jv[0]) {
+                    const int kc = kcl[c] + dk;
+                    if (act) {
+                        Gl[c] = S.Gs[0];
+                        kcl[c] = kc;
+                    }
+                    dkl[buf][c] = dk;
+                    a.safe.kb[(long)q * a.n + col0 + c] = kc;
+                }
+            }
+            if (r < g.bs) Bl[c * kSP + g.lr0 + r] = zd{S.br[0], S.bi[0]};
+            xpr[0] = S.br[0];
+            xpi[0] = S.bi[0];
+            if (stp + 1 < nsub) stage_store(buf ^ 1);
+            __syncthreads();
+        }
+    } else {
+        // ---- rows above the block being solved: chunks wv - 1 and wv + 2
+        zd un[NB];   // first chunk of a pass, loaded during the pass before
+        if (nsub > 1) uload(un, pass_of(1), wv - 1);
+        for (int stp = 0; stp < nsub; ++stp) {
+            const int buf = stp & 1;
+            const Pass g = pass_of(stp);
+            if (stp > 0) {
+                // settle the first chunk before the staging loads are issued,
+                // so that the wait for it does not also cover them
+#pragma unroll
+                for (int k = 0; k < NB; ++k) asm volatile("" : "+v"(un[k].re), "+v"(un[k].im));
+            }
+            if (stp + 1 < nsub) stage_load(stp + 1);
+            if (g.bsp > 0) {
+                // (a second chunk exists for wavefront 1 in the first passes
+                // of a full outer block only; its loads reuse the registers)
+                const int nch = (g.lr0 + 63) / 64;
+                const int c1 = wv - 1, c2 = wv + 2;
+                if (c1 < nch) uapply(un, g, c1, buf);
+                if (c2 < nch) {
+                    uload(un, g, c2);
+                    uapply(un, g, c2, buf);
+                }
+            }
+            if (stp + 1 < nsub) stage_store(buf ^ 1);
+            // first chunk of the next pass, in flight across the barrier
+            if (stp + 1 < nsub) {
+                const Pass gn = pass_of(stp + 1);
+                if (wv - 1 < (gn.lr0 + 63) / 64) uload(un, gn, wv - 1);
+            }
+            __syncthreads();
+        }
+    }
+
+    // ---- solution of the outer block -> HBM; safe state back
+    if (SAFE && tid < kColsN && col0 + tid < a.n) {
+        a.safe.G[col0 + tid] = Gl[tid];
+        a.safe.kcur[col0 + tid] = kcl[tid];
+    }
+    {
+        constexpr int PER = kColsN * kRowsMax / kWGN;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * kWGN;
+            const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
+            const int j = col0 + c;
+            if (j < a.n && rr < rows && iS + rr < Ll[c]) {
+                const zd v = Bl[c * kSP + rr];
+                a.B[(long)j * a.ldb + iS + rr] = v;
+                if (MIXED) a.b32[(long)j * a.ldb32 + iS + rr] = zf{(float)v.re, (float)v.im};
+            }
+        }
+    }
+}
+
+// Compute units of the current device, read once per device.
+int device_cus_blk() {
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int c = cus[dev].load(std::memory_order_relaxed);
+    if (c <= 0) {
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+            c = 256;
+        cus[dev].store(c, std::memory_order_relaxed);
+    }
+    return c;
+}
+
+// Narrow workgroups for the outer block when the 16-shift grid leaves compute
+// units idle.
+bool narrow_pays(const BlockArgs& a) {
+    const int wide = (a.n + kCols - 1) / kCols;
+    return wide < device_cus_blk();
+}
+
 template <int NB, int SPW, int EV>
 hipError_t launch_nb(const DiagArgs& a, hipStream_t s) {
     constexpr int per_wg = (kWG / 64) * (64 / NB) * SPW;
@@ -1207,6 +1676,19 @@ hipError_t launch_blk(const BlockArgs& a, hipStream_t s) {
     const bool safe = a.use_safe != 0;
     const bool mixed = a.b32 != nullptr;
     const bool varlen = a.col_len != nullptr;
+    if constexpr (NB == 16 && EV == EV_UPPER_N) {
+        // 4-shift workgroups where 16-shift ones would leave compute units idle
+        const bool narrow = a.V == nullptr && !(safe && mixed) && !(varlen && !safe) &&
+                            (a.width == 4 || (a.width == 0 && narrow_pays(a)));
+        if (narrow) {
+            const dim3 gn((a.n + kColsN - 1) / kColsN), bn(kWGN);
+            if (safe && varlen) hipLaunchKernelGGL((k_block_narrow<true, false, true>), gn, bn, 0, s, a);
+            else if (safe) hipLaunchKernelGGL((k_block_narrow<true, false, false>), gn, bn, 0, s, a);
+            else if (mixed) hipLaunchKernelGGL((k_block_narrow<false, true, false>), gn, bn, 0, s, a);
+            else hipLaunchKernelGGL((k_block_narrow<false, false, false>), gn, bn, 0, s, a);
+            return hipGetLastError();
+        }
+    }
     if (a.V != nullptr) {
         if constexpr (NB == 16 && EV == EV_UPPER_N) {
             if (mixed || (varlen && !safe)) return hipErrorInvalidValue;

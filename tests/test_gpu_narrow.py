@@ -1,0 +1,153 @@
+"""Fused outer blocks with 4 shifts per workgroup (mst_opts.fuse_blocks = 2,
+chosen automatically when 16-shift workgroups would leave compute units idle)
+against the oracle: plain solves on shapes with partial outer and diagonal
+blocks and shift counts that are not multiples of 4, the safe solve with
+rescaling, variable-length columns and the triangular eigenvectors (exponents
+equal to the oracle's Alg 5), mixed precision, the automatic choice, and
+agreement with the 16-shift kernel to rounding."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import announce, colerr, dev, host
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.0 ** -52
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1607_01477_amd as P
+    P._lib.load()
+    return P
+
+
+def _bits(X):
+    return np.ascontiguousarray(X).view(np.uint64)
+
+
+def _kappa(U, lam, cols):
+    Ut = np.triu(U)
+    m = U.shape[0]
+    out = []
+    for j in cols:
+        A = Ut - lam[j] * np.eye(m)
+        out.append(np.linalg.norm(A, np.inf) * np.linalg.norm(np.linalg.inv(A), np.inf))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("m,n,outer", [(1, 1, 256), (17, 5, 256), (256, 4, 256), (530, 70, 256),
+                                       (1000, 37, 128), (700, 9, 64)])
+def test_narrow_plain(P, oracle_mod, m, n, outer):
+    announce("narrow plain m=%d n=%d outer=%d" % (m, n, outer))
+    w = W.c1_plain(seed=400 + m + n, m=m, n=n)
+    X = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=outer, fuse_width=4))
+    X2 = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=outer, fuse_width=4))
+    assert np.array_equal(_bits(X), _bits(X2))
+    rr = oracle_mod.relative_residual(w.U, w.shifts, X, w.B)
+    assert rr.max() <= 1e-13, rr.max()
+    Xo = oracle_mod.solve(w.U, w.shifts, w.B)
+    cols = np.arange(0, n, max(1, n // 10))
+    kap = _kappa(w.U, w.shifts, cols)
+    assert np.all(colerr(X[:, cols], Xo[:, cols]) <= 64 * EPS * kap)
+    X16 = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=outer, fuse_width=16))
+    assert np.all(colerr(X[:, cols], X16[:, cols]) <= 128 * EPS * kap)
+
+
+def test_narrow_automatic_choice(P):
+    """Few shifts: the automatic width is the narrow one (same bits as forced
+    4); 4096 shifts fill the device with 16-shift workgroups (same bits as
+    forced 16)."""
+    w = W.c1_plain(seed=410, m=300, n=40)
+    args = (dev(w.U), dev(w.shifts))
+    Xa = host(P.mstrsm(*args, dev(w.B), nb=16))
+    X4 = host(P.mstrsm(*args, dev(w.B), nb=16, fuse_width=4))
+    assert np.array_equal(_bits(Xa), _bits(X4))
+    w = W.c1_plain(seed=411, m=300, n=4096)
+    args = (dev(w.U), dev(w.shifts))
+    Xa = host(P.mstrsm(*args, dev(w.B), nb=16))
+    X16 = host(P.mstrsm(*args, dev(w.B), nb=16, fuse_width=16))
+    assert np.array_equal(_bits(Xa), _bits(X16))
+
+
+@pytest.mark.parametrize("omega_log2", [960, 40])
+def test_narrow_safe_growth(P, oracle_mod, omega_log2):
+    g = W.rng(420)
+    m, n = 450, 30
+    U = W.random_upper(g, m, 1.0, W.cnormal(g, m))
+    lam = W.cnormal(g, n)
+    B = np.asfortranarray(W.cnormal(g, (m, n)))
+    announce("narrow safe omega 2^%d" % omega_log2)
+    X, s, k = P.mstrsm_safe(dev(U), dev(lam), dev(B), nb=16, omega_log2=omega_log2, fuse_width=4)
+    X, s, k = host(X), host(s), host(k)
+    Xo, so, ko = oracle_mod.solve_safe(U, lam, B, nb=16, omega_log2=omega_log2)
+    assert np.array_equal(k, ko) and np.array_equal(s, so)
+    if omega_log2 == 40:
+        assert np.any(k > 0)
+    assert np.all(np.isfinite(X))
+    rr = oracle_mod.relative_residual(U, lam, X, B, k=k)
+    assert rr.max() <= 1e-13, rr.max()
+    # forced checked steps: the same bits
+    Xf, sf, kf = P.mstrsm_safe(dev(U), dev(lam), dev(B), nb=16, omega_log2=omega_log2, fuse_width=4,
+                               force_phase2=True)
+    assert np.array_equal(_bits(host(Xf)), _bits(X)) and np.array_equal(host(kf), k)
+
+
+def test_narrow_col_len(P, oracle_mod):
+    """Variable-length columns, including lengths 0, 1, m and columns whose
+    workgroup has no column reaching an outer block (early exit)."""
+    import torch
+    g = W.rng(430)
+    m, n = 600, 41
+    U = W.random_upper(g, m, 1.0, W.cnormal(g, m))
+    lam = W.cnormal(g, n)
+    B = np.asfortranarray(W.cnormal(g, (m, n)))
+    L = np.sort(W.rng(431).integers(0, m + 1, n)).astype(np.int32)
+    L[:5] = [0, 1, 3, 16, 17]
+    L[-1] = m
+    announce("narrow col_len")
+    X, s, k = P.mstrsm_safe(dev(U), dev(lam), dev(B), col_len=dev(L, dtype=torch.int32), nb=16,
+                            omega_log2=50, fuse_width=4)
+    X, k = host(X), host(k)
+    Xo, so, ko = oracle_mod.solve_safe(U, lam, B, col_len=L, nb=16, omega_log2=50)
+    assert np.array_equal(k, ko)
+    for j in range(n):
+        assert np.array_equal(X[L[j]:, j], B[L[j]:, j])
+        if L[j] > 0:
+            e = np.abs(X[:L[j], j] - Xo[:L[j], j]).max() / max(np.abs(Xo[:L[j], j]).max(), 1e-300)
+            assert e <= 1e-8, (j, e)
+
+
+@pytest.mark.parametrize("m", [600, 2048])
+def test_narrow_triang_eig(P, oracle_mod, m):
+    w = W.c2_triang_eig(m=m)
+    announce("narrow triang_eig m=%d" % m)
+    ev, Z, k = P.triang_eig(dev(w.U), nb=16, fuse_width=4)
+    ev, Z, k = host(ev), host(Z), host(k)
+    lo, Zo, ko = oracle_mod.triang_eig(w.U, nb=16)
+    assert np.array_equal(ev, lo)
+    mism = np.nonzero(k != ko)[0]
+    assert len(mism) == 0, (mism[:10], k[mism[:10]], ko[mism[:10]])
+    if m == 2048:
+        assert np.any(k > 0)   # the full-size recipe rescales (at m = 600 nothing does)
+    assert np.all(np.tril(Z, -1) == 0)
+    T = w.U
+    Tn = np.max(np.sum(np.abs(T), axis=1))
+    R = T @ Z - Z * ev[None, :]
+    rel = np.max(np.abs(R), axis=0) / (Tn * np.max(np.abs(Z), axis=0))
+    assert rel.max() <= 1e-13, rel.max()
+
+
+def test_narrow_mixed_precision(P, oracle_mod):
+    w = W.c3_mixed(seed=440, m=700, n=60)
+    announce("narrow mixed")
+    X = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), precision=1, max_sweeps=2, refine_tol=-1.0,
+                      fuse_width=4))
+    rr = oracle_mod.relative_residual(w.U, w.shifts, X, w.B)
+    assert rr.max() <= 1e-13, rr.max()
+    Xo = oracle_mod.solve(w.U, w.shifts, w.B)
+    assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-13
