@@ -68,7 +68,7 @@ typedef struct {
                           fused kernel (diagonal blocks plus the substitution between them),
                           with 16 shifts per workgroup, or with 4 where 16-shift workgroups
                           would leave compute units idle (nb = 16, upper, op N, standard
-                          problem: fewer than 16 x (compute units) shifts); 1 or 2 force
+                          problem, at most 8 x (compute units) shifts); 1 or 2 force
                           16 or 4 shifts per workgroup (2 falls back to 16 where 4 is not
                           available). The two widths apply the in-block updates in another
                           summation order, so results agree to rounding.

@@ -1623,10 +1623,12 @@ int device_cus_blk() {
 }
 
 // Narrow workgroups for the outer block when the 16-shift grid leaves compute
-// units idle.
+// units idle and the narrow grid runs in one round (two narrow workgroups fit
+// on a compute unit).
 bool narrow_pays(const BlockArgs& a) {
-    const int wide = (a.n + kCols - 1) / kCols;
-    return wide < device_cus_blk();
+    const int cus = device_cus_blk();
+    const int wide = (a.n + kCols - 1) / kCols, narrow = (a.n + kColsN - 1) / kColsN;
+    return wide < cus && narrow <= 2 * cus;
 }
 
 template <int NB, int SPW, int EV>
