@@ -190,7 +190,8 @@ def mstrsm_safe_noalloc(U, shifts, B, col_len=None, *, scale=None, scale_log2=No
     return X, scale, klog
 
 
-def mstrsm_adjoint(U, shifts, G, *, nb=0, outer_nb=0, fuse=True, overlap=False, staged=False, gemm_split=0):
+def mstrsm_adjoint(U, shifts, G, *, nb=0, outer_nb=0, fuse=True, overlap=False, staged=False, gemm_split=0,
+                   fuse_width=0):
     """Y with (U - shifts[j] I)^H Y[:, j] = G[:, j] (G overwritten when column-major)."""
     U = _mat(U, "U")
     Y = _mat(G, "G")
@@ -198,7 +199,8 @@ def mstrsm_adjoint(U, shifts, G, *, nb=0, outer_nb=0, fuse=True, overlap=False, 
     if U.shape != (m, m):
         raise ValueError("U must be %d x %d" % (m, m))
     s = _vec(shifts, n, "shifts")
-    o = _opts(nb=nb, outer_nb=outer_nb, fuse=fuse, overlap=overlap, staged=staged, gemm_split=gemm_split)
+    o = _opts(nb=nb, outer_nb=outer_nb, fuse=fuse, overlap=overlap, staged=staged, gemm_split=gemm_split,
+              fuse_width=fuse_width)
     rc = _lib.load().mstrsm_adjoint(m, n, _p(U), _ld(U), _p(s), _p(Y), _ld(Y), ctypes.byref(o),
                                     _stream())
     _lib.check("mstrsm_adjoint", rc)
@@ -206,7 +208,7 @@ def mstrsm_adjoint(U, shifts, G, *, nb=0, outer_nb=0, fuse=True, overlap=False, 
 
 
 def mstrsm_op(A, shifts, B, *, uplo="U", op="N", side="L", nb=0, outer_nb=0, fuse=True,
-              precision=0, max_sweeps=2):
+              precision=0, max_sweeps=2, fuse_width=0):
     """Variants of the footnote to Sec. 2: X with op(A - shifts[j] I) X[:, j] = B[:, j]
     (side "L") or X[:, j]^T op(A - shifts[j] I) = B[:, j]^T (side "R"), A upper
     ("U") or lower ("L") triangular, op "N", "T" or "C" (side "R": "N" or "T").
@@ -217,7 +219,8 @@ def mstrsm_op(A, shifts, B, *, uplo="U", op="N", side="L", nb=0, outer_nb=0, fus
     if A.shape != (m, m):
         raise ValueError("A must be %d x %d" % (m, m))
     s = _vec(shifts, n, "shifts")
-    o = _opts(nb=nb, outer_nb=outer_nb, fuse=fuse, precision=precision, max_sweeps=max_sweeps)
+    o = _opts(nb=nb, outer_nb=outer_nb, fuse=fuse, precision=precision, max_sweeps=max_sweeps,
+              fuse_width=fuse_width)
     rc = _lib.load().mstrsm_op(ord(side), ord(uplo), ord(op), m, n, _p(A), _ld(A), _p(s), _p(X), _ld(X),
                                ctypes.byref(o), _stream())
     _lib.check("mstrsm_op", rc)

@@ -1209,9 +1209,11 @@ __global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_bl
 // The outer block of k_block for 4 shifts per workgroup of 4 wavefronts, for
 // launches whose 16-shift workgroups would leave compute units idle (few
 // shifts, or few columns reaching an outer block in the triangular-eigenvector
-// solve). Wavefront 0 solves the diagonal blocks exactly as a solving
+// solve), for every solve variant EV (safe, variable-length and mixed forms:
+// upper, op N). Wavefront 0 solves the diagonal blocks exactly as a solving
 // wavefront of k_block (one shift per lane group). Wavefronts 1-3 apply each
-// solved block to the rows above it with FP64 FMAs, one row per lane and all
+// solved block to the rows still to be solved (above it for back
+// substitution, below it for forward) with FP64 FMAs, one row per lane and all
 // four shifts: at four shifts a 16-column matrix-core tile would be three
 // quarters padding, and the substitution chain then shares its SIMD's FP64
 // pipeline with no matrix-core products (the four wavefronts of a workgroup
@@ -1221,8 +1223,12 @@ __global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_bl
 // the blocks, as in k_block.
 constexpr int kColsN = 4;     // shifts per narrow workgroup
 constexpr int kWGN = 256;     // threads per narrow workgroup
-template <bool SAFE, bool MIXED, bool VARLEN>
+template <int EV, bool SAFE, bool MIXED, bool VARLEN>
 __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
+    static_assert(EV == EV_UPPER_N || (!SAFE && !MIXED && !VARLEN), "variants: plain FP64 solves");
+    constexpr bool ADJ = ev_fwd(EV);          // forward substitution (E lower triangular)
+    constexpr bool TR = ev_tr(EV), CJ = ev_cj(EV), LOWA = ev_lower_a(EV);
+    using BS = BlockSolve<16, 1, EV, SAFE>;
     constexpr int NB = 16, NBB = NB * NB;
     constexpr int PERS = 2 * NBB / kWGN;
     __shared__ zd Bl[kColsN * kSP];
@@ -1280,8 +1286,8 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
             kcl[tid] = (j < a.n) ? a.safe.kcur[j] : 0;
         }
     }
-    // pivots: U(r, r) - lambda_j for every row of the outer block and shift
-    // (1 + 0i outside the block or past the shifts)
+    // pivots: A(r, r) - lambda_j (conjugated for CJ) for every row of the
+    // outer block and shift (1 + 0i outside the block or past the shifts)
     {
         constexpr int PER = kColsN * kRowsMax / kWGN;
 #pragma unroll
@@ -1289,12 +1295,14 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
             const int idx = tid + e * kWGN;
             const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
             double dr = 1.0, di = 0.0;
-            if (rr < rows && col0 + c < a.n)
-                BlockSolve<NB, 1, EV_UPPER_N, SAFE>::pivot_value(a.U[(long)(iS + rr) * a.ldu + iS + rr],
-                                                                 a.lam[col0 + c], delta, dr, di);
+            if (rr < rows && col0 + c < a.n) {
+                zd u = a.U[(long)(iS + rr) * a.ldu + iS + rr];
+                if (CJ) u.im = -u.im;   // as staged (E's diagonal)
+                BS::pivot_value(u, a.lam[col0 + c], delta, dr, di);
+            }
             double pr, pi, cd;
             int pe;
-            BlockSolve<NB, 1, EV_UPPER_N, SAFE>::pivot_entry(dr, di, pr, pi, pe, cd);
+            BS::pivot_entry(dr, di, pr, pi, pe, cd);
             Ppr[c][rr] = pr;
             Ppi[c][rr] = pi;
             if (SAFE) {
@@ -1338,22 +1346,25 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
         }
     }
 
-    // pass stp solves block ql (from the bottom) and applies block qp = ql + 1
-    // (solved in the pass before) to the rows above ql
+    // pass stp solves block ql (from the bottom; from the top for forward
+    // substitution) and applies block qp (solved in the pass before, adjacent
+    // to ql) to the rows [ubeg, uend) still to be solved beyond ql
     struct Pass {
-        int lr0, bs, p0, bsp;
+        int lr0, bs, p0, bsp, ubeg, uend;
     };
     auto pass_of = [&](int stp) __attribute__((always_inline)) {
         Pass g;
-        const int ql = nsub - 1 - stp;
+        const int ql = ADJ ? stp : nsub - 1 - stp;
         g.lr0 = ql * NB;
         g.bs = min(NB, rows - g.lr0);
-        g.p0 = (ql + 1) * NB;
+        g.p0 = (ADJ ? ql - 1 : ql + 1) * NB;
         g.bsp = stp > 0 ? min(NB, rows - g.p0) : 0;
+        g.ubeg = ADJ ? g.lr0 + g.bs : 0;
+        g.uend = ADJ ? rows : g.lr0;
         return g;
     };
 
-    // staging of the diagonal and coupling blocks of a pass (as in k_block)
+    // staging of the diagonal and coupling blocks of a pass, as in k_block
     zd ust[PERS];
     bool usv[PERS];
     auto stage_load = [&](int stp) __attribute__((always_inline)) {
@@ -1363,16 +1374,24 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
         for (int e = 0; e < PERS; ++e) {
             const int t = tid + e * kWGN;
             long off = (long)i0 * a.ldu + i0;   // the block's first pivot: always valid
-            bool v;
+            bool v = false;
             if (t < NBB) {
                 const int c = t / NB, rr = t - c * NB;
                 v = rr <= c && c < g.bs;
-                off = v ? (long)(i0 + c) * a.ldu + i0 + rr : off;
+                off = v ? (LOWA ? (long)(i0 + rr) * a.ldu + i0 + c : (long)(i0 + c) * a.ldu + i0 + rr) : off;
             } else {
                 const int t2 = t - NBB;
-                const int k = t2 / NB, r = t2 - k * NB;
-                v = r < g.bs && k < g.bsp;
-                off = v ? (long)(p0 + k) * a.ldu + i0 + r : off;
+                if (!TR) {
+                    // coefficient of x_p(k) in row r: A(i0 + r, p0 + k)
+                    const int k = t2 / NB, r = t2 - k * NB;
+                    v = r < g.bs && k < g.bsp;
+                    off = v ? (long)(p0 + k) * a.ldu + i0 + r : off;
+                } else {
+                    // transposed: A(p0 + k, i0 + r) (conjugated at the store for CJ)
+                    const int r = t2 / NB, k = t2 - r * NB;
+                    v = r < g.bs && k < g.bsp;
+                    off = v ? (long)(i0 + r) * a.ldu + p0 + k : off;
+                }
             }
             usv[e] = v;
             ust[e] = a.U[off];
@@ -1382,18 +1401,28 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
 #pragma unroll
         for (int e = 0; e < PERS; ++e) {
             const int t = tid + e * kWGN;
-            const zd v = usv[e] ? ust[e] : zd{0.0, 0.0};
+            zd v = usv[e] ? ust[e] : zd{0.0, 0.0};
+            if (CJ) v.im = -v.im;
             if (t < NBB) {
                 const int c = t / NB, rr = t - c * NB;
                 if (rr == c) {
                     Ud[buf][rr] = v;
                     Us[buf][c * NB + rr] = zd{0.0, 0.0};
-                } else {
+                } else if (!ADJ) {
                     Us[buf][c * NB + rr] = v;
+                } else {
+                    Us[buf][rr * NB + c] = v;
                 }
             } else {
                 const int t2 = t - NBB;
-                const int k = t2 / NB, r = t2 - k * NB;
+                int k, r;
+                if (!TR) {
+                    k = t2 / NB;
+                    r = t2 - k * NB;
+                } else {
+                    r = t2 / NB;
+                    k = t2 - r * NB;
+                }
                 Uo[buf][k * NB + r] = v;
             }
         }
@@ -1402,18 +1431,21 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     stage_store(0);
     __syncthreads();
 
-    // updating wavefronts: U(iS + row, iS + p0 + k), k < 16, of one 64-row
-    // chunk (row = chunk * 64 + lane), from clamped positions (in bounds; rows
-    // outside the update are never stored, entries past block p are zeroed)
+    // updating wavefronts: E(row, p0 + k), k < 16, of one 64-row chunk (row =
+    // ubeg + chunk * 64 + lane; E(r, c) = A(r, c), or A(c, r) conjugated for
+    // CJ when transposed), from clamped positions (in bounds; rows outside the
+    // update are never stored, entries past block p are never used)
     auto uload = [&](zd (&u)[NB], const Pass& g, int chunk) __attribute__((always_inline)) {
-        const int row = min(chunk * 64 + lane, max(g.lr0 - 1, 0));
-        // one running pointer down the columns (one 64-bit add per step),
-        // held at the block's last column past it
-        const zd* up = a.U + (long)(iS + g.p0) * a.ldu + iS + row;
+        const int row = max(min(g.ubeg + chunk * 64 + lane, g.uend - 1), 0);
+        // one running pointer along block p (one 64-bit add per step), held
+        // at its last column past it
+        const zd* up = TR ? a.U + (long)(iS + row) * a.ldu + iS + g.p0 : a.U + (long)(iS + g.p0) * a.ldu + iS + row;
+        const long st = TR ? 1 : a.ldu;
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
             u[k] = *up;
-            if (k + 1 < g.bsp) up += a.ldu;
+            if (CJ) u[k].im = -u[k].im;
+            if (k + 1 < g.bsp) up += st;
         }
     };
     // rows of the chunk -= U(rows, block p) x(block p), all four shifts per
@@ -1425,19 +1457,20 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     // LDS round trip on every step) nor hoists all of them to the top (every
     // x live at once). Rows p0 + k for
     // k >= bsp lie past the outer block, where Bl holds zeros (p0 + 15 <=
-    // 255), so no step needs a mask. Each component keeps two accumulators
+    // 255; only the last block can be partial, and it is never block p of
+    // forward substitution), so no step needs a mask. Each component keeps two accumulators
     // (the terms with Re u and with Im u), so a step's 16 FMAs are
     // independent. In the safe form the rows first take the exponent change
     // of block p.
     auto uapply = [&](const zd (&u)[NB], const Pass& g, int chunk, int buf) __attribute__((always_inline)) {
-        const int row = chunk * 64 + lane;   // < 256: at most four chunks
-        const bool ok = row < g.lr0;
+        const int row = g.ubeg + chunk * 64 + lane;   // < 256 where stored (row < uend)
+        const bool ok = row < g.uend;
         const zd* xb = Bl + g.p0;
         double sr[kColsN], si[kColsN], tr[kColsN], ti[kColsN];
         zd x0[kColsN], x1[kColsN], x2[kColsN], x3[kColsN];
 #pragma unroll
         for (int c = 0; c < kColsN; ++c) {
-            zd v = Bl[c * kSP + row];
+            zd v = Bl[c * kSP + min(row, kRowsMax - 1)];
             x0[c] = xb[c * kSP];
             x1[c] = xb[c * kSP + 1];
             x2[c] = xb[c * kSP + 2];
@@ -1494,11 +1527,11 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
         for (int stp = 0; stp < nsub; ++stp) {
             const int buf = stp & 1;
             const Pass g = pass_of(stp);
-            const int q = a.qa + nsub - 1 - stp;
+            const int q = a.qa + (ADJ ? stp : nsub - 1 - stp);
             const int i0 = iS + g.lr0;
             if (stp + 1 < nsub) stage_load(stp + 1);
-            // ---- rows of block q: apply x of block p, then back substitution
-            BlockSolve<NB, 1, EV_UPPER_N, SAFE> S;
+            // ---- rows of block q: apply x of block p, then the substitution
+            BS S;
             const int c = grp;
             const bool act = jv[0] && (i0 < Ll[c]);
             zd b{0.0, 0.0};
@@ -1553,7 +1586,7 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
             __syncthreads();
         }
     } else {
-        // ---- rows above the block being solved: chunks wv - 1 and wv + 2
+        // ---- rows beyond the block being solved: chunks wv - 1 and wv + 2
         zd un[NB];   // first chunk of a pass, loaded during the pass before
         if (nsub > 1) uload(un, pass_of(1), wv - 1);
         for (int stp = 0; stp < nsub; ++stp) {
@@ -1569,7 +1602,7 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
             if (g.bsp > 0) {
                 // (a second chunk exists for wavefront 1 in the first passes
                 // of a full outer block only; its loads reuse the registers)
-                const int nch = (g.lr0 + 63) / 64;
+                const int nch = (g.uend - g.ubeg + 63) / 64;
                 const int c1 = wv - 1, c2 = wv + 2;
                 if (c1 < nch) uapply(un, g, c1, buf);
                 if (c2 < nch) {
@@ -1581,7 +1614,7 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
             // first chunk of the next pass, in flight across the barrier
             if (stp + 1 < nsub) {
                 const Pass gn = pass_of(stp + 1);
-                if (wv - 1 < (gn.lr0 + 63) / 64) uload(un, gn, wv - 1);
+                if (wv - 1 < (gn.uend - gn.ubeg + 63) / 64) uload(un, gn, wv - 1);
             }
             __syncthreads();
         }
@@ -1678,16 +1711,20 @@ hipError_t launch_blk(const BlockArgs& a, hipStream_t s) {
     const bool safe = a.use_safe != 0;
     const bool mixed = a.b32 != nullptr;
     const bool varlen = a.col_len != nullptr;
-    if constexpr (NB == 16 && EV == EV_UPPER_N) {
+    if constexpr (NB == 16) {
         // 4-shift workgroups where 16-shift ones would leave compute units idle
-        const bool narrow = a.V == nullptr && !(safe && mixed) && !(varlen && !safe) &&
-                            (a.width == 4 || (a.width == 0 && narrow_pays(a)));
-        if (narrow) {
+        const bool supported = a.V == nullptr && !(safe && mixed) && !(varlen && !safe) &&
+                               (EV == EV_UPPER_N || (!safe && !mixed && !varlen));
+        if (supported && (a.width == 4 || (a.width == 0 && narrow_pays(a)))) {
             const dim3 gn((a.n + kColsN - 1) / kColsN), bn(kWGN);
-            if (safe && varlen) hipLaunchKernelGGL((k_block_narrow<true, false, true>), gn, bn, 0, s, a);
-            else if (safe) hipLaunchKernelGGL((k_block_narrow<true, false, false>), gn, bn, 0, s, a);
-            else if (mixed) hipLaunchKernelGGL((k_block_narrow<false, true, false>), gn, bn, 0, s, a);
-            else hipLaunchKernelGGL((k_block_narrow<false, false, false>), gn, bn, 0, s, a);
+            if constexpr (EV == EV_UPPER_N) {
+                if (safe && varlen) hipLaunchKernelGGL((k_block_narrow<EV, true, false, true>), gn, bn, 0, s, a);
+                else if (safe) hipLaunchKernelGGL((k_block_narrow<EV, true, false, false>), gn, bn, 0, s, a);
+                else if (mixed) hipLaunchKernelGGL((k_block_narrow<EV, false, true, false>), gn, bn, 0, s, a);
+                else hipLaunchKernelGGL((k_block_narrow<EV, false, false, false>), gn, bn, 0, s, a);
+            } else {
+                hipLaunchKernelGGL((k_block_narrow<EV, false, false, false>), gn, bn, 0, s, a);
+            }
             return hipGetLastError();
         }
     }

@@ -3,8 +3,10 @@ chosen automatically when 16-shift workgroups would leave compute units idle)
 against the oracle: plain solves on shapes with partial outer and diagonal
 blocks and shift counts that are not multiples of 4, the safe solve with
 rescaling, variable-length columns and the triangular eigenvectors (exponents
-equal to the oracle's Alg 5), mixed precision, the automatic choice, and
-agreement with the 16-shift kernel to rounding."""
+equal to the oracle's Alg 5), mixed precision, the lower-triangular,
+transposed and conjugated variants and the adjoint (forward substitution,
+the other triangle filled with NaN), the automatic choice, and agreement with
+the 16-shift kernel to rounding."""
 import numpy as np
 import pytest
 
@@ -151,3 +153,56 @@ def test_narrow_mixed_precision(P, oracle_mod):
     assert rr.max() <= 1e-13, rr.max()
     Xo = oracle_mod.solve(w.U, w.shifts, w.B)
     assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) <= 1e-13
+
+
+def _operator(A, lam, uplo, op):
+    T = np.triu(A) if uplo == "U" else np.tril(A)
+    E = T - lam * np.eye(A.shape[0])
+    return {"N": E, "T": E.T, "C": E.conj().T}[op]
+
+
+@pytest.mark.parametrize("uplo,op", [(u, o) for u in "UL" for o in "NTC"])
+def test_narrow_variants(P, oracle_mod, uplo, op):
+    """op(A - l_j I) x_j = b_j for A upper or lower and op N, T, C with 4-shift
+    fused blocks (forward substitution for lower N and upper T/C): residual,
+    oracle agreement, the unread triangle NaN, and agreement with the 16-shift
+    kernel."""
+    m, n = 530, 37
+    w = W.c1_plain(seed=450 + ord(uplo) + ord(op), m=m, n=n)
+    A = w.U if uplo == "U" else np.asfortranarray(w.U.T.copy())
+    An = A.copy(order="F")
+    if uplo == "U":
+        An[np.tril_indices(m, -1)] = np.nan
+    else:
+        An[np.triu_indices(m, 1)] = np.nan
+    announce("narrow variant %s%s" % (uplo, op))
+    X = host(P.mstrsm_op(dev(An), dev(w.shifts), dev(w.B), uplo=uplo, op=op, nb=16, fuse_width=4))
+    assert np.all(np.isfinite(X))
+    Xo = oracle_mod.solve_op(A, w.shifts, w.B, uplo, op)
+    X16 = host(P.mstrsm_op(dev(An), dev(w.shifts), dev(w.B), uplo=uplo, op=op, nb=16, fuse_width=16))
+    for j in range(n):
+        E = _operator(A, w.shifts[j], uplo, op)
+        r = np.abs(E @ X[:, j] - w.B[:, j]).max()
+        assert r <= 1e-13 * np.abs(E).sum(1).max() * np.abs(X[:, j]).max(), j
+        if j % 6 == 0:
+            kap = np.linalg.norm(E, np.inf) * np.linalg.norm(np.linalg.inv(E), np.inf)
+            assert colerr(X[:, j:j + 1], Xo[:, j:j + 1])[0] <= 64 * EPS * kap
+            assert colerr(X[:, j:j + 1], X16[:, j:j + 1])[0] <= 128 * EPS * kap
+
+
+def test_narrow_adjoint(P, oracle_mod):
+    m, n = 600, 50
+    w = W.c1_plain(seed=460, m=m, n=n)
+    announce("narrow adjoint")
+    Y = host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=4))
+    Y2 = host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=4))
+    assert np.array_equal(_bits(Y), _bits(Y2))
+    Yo = oracle_mod.solve_adjoint(w.U, w.shifts, w.B)
+    Ut = np.triu(w.U)
+    for j in range(0, n, 5):
+        A = (Ut - w.shifts[j] * np.eye(m)).conj().T
+        r = np.abs(A @ Y[:, j] - w.B[:, j]).max()
+        assert r <= 1e-13 * np.abs(A).sum(1).max() * np.abs(Y[:, j]).max()
+    cols = np.arange(0, n, 7)
+    kap = _kappa(w.U, w.shifts, cols)
+    assert np.all(colerr(Y[:, cols], Yo[:, cols]) <= 64 * EPS * kap)
