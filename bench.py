@@ -39,7 +39,7 @@ PEAK_FP64_MFMA_TF = 78.6
 # HBM bytes per launch of the substitution GEMM at this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs scaled by a 512 MiB copy (profiles/k_gemm_direct_solve_m4096_n4096.md).
 # Valid only for the GEMM source it was measured on (sha1 prefix of csrc/kgemm.hip).
-GEMM_TRAFFIC = {"kgemm_sha1": "dc75bb92c41cc83f", "bytes_per_launch": 295.4e6, "m": 4096, "n": 4096,
+GEMM_TRAFFIC = {"kgemm_sha1": "72f0deb18adf67ae", "bytes_per_launch": 295.4e6, "m": 4096, "n": 4096,
                 "nb": 16, "outer_nb": 256,
                 # the pencil substitution (profiles/k_gemm_direct_pencil_m4096_n4096.md)
                 "pencil_bytes_per_launch": 471.0e6}

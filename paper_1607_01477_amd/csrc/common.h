@@ -90,6 +90,11 @@ int block_rows_max();
 bool block_fusable(int nb);   // nb handled by the fused kernel (16 or 32)
 hipError_t launch_block(int ev, const BlockArgs& a, hipStream_t s);
 
+// Compute units of the current device (read once per device; 256 if the
+// query fails). Launch shapes that depend on it: the K split of the direct
+// GEMM and the width of the fused outer-block kernel.
+int device_cu_count();
+
 // ---------------------------------------------------------------- tile order
 // Workgroup -> output tile (tm, tn) of a TM x TN grid, shared by the GEMM
 // kernels. The hardware deals workgroup w to XCD w % 8; when the tile count is

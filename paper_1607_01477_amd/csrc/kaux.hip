@@ -8,6 +8,8 @@
 // over the workgroup) so results are bitwise reproducible run to run.
 #include "common.h"
 
+#include <atomic>
+
 namespace mst {
 namespace {
 
@@ -621,6 +623,19 @@ hipError_t launch_tridiag_max(int n, int iters, const double* alpha, const doubl
     hipLaunchKernelGGL(k_tridiag, dim3((n + 255) / 256), dim3(256), 0, s, n, iters, alpha, beta, steps,
                        sigma);
     return hipGetLastError();
+}
+
+int device_cu_count() {
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int c = cus[dev].load(std::memory_order_relaxed);
+    if (c <= 0) {
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+            c = 256;
+        cus[dev].store(c, std::memory_order_relaxed);
+    }
+    return c;
 }
 
 }  // namespace mst

@@ -29,7 +29,6 @@
 //             into one launch per outer block.
 #include "common.h"
 
-#include <atomic>
 
 namespace mst {
 namespace {
@@ -1641,25 +1640,12 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     }
 }
 
-// Compute units of the current device, read once per device.
-int device_cus_blk() {
-    static std::atomic<int> cus[64];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    int c = cus[dev].load(std::memory_order_relaxed);
-    if (c <= 0) {
-        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
-            c = 256;
-        cus[dev].store(c, std::memory_order_relaxed);
-    }
-    return c;
-}
 
 // Narrow workgroups for the outer block when the 16-shift grid leaves compute
 // units idle and the narrow grid runs in one round (two narrow workgroups fit
 // on a compute unit).
 bool narrow_pays(const BlockArgs& a) {
-    const int cus = device_cus_blk();
+    const int cus = device_cu_count();
     const int wide = (a.n + kCols - 1) / kCols, narrow = (a.n + kColsN - 1) / kColsN;
     return wide < cus && narrow <= 2 * cus;
 }

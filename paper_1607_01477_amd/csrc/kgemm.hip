@@ -20,7 +20,6 @@
 // receives a contiguous range of tiles.
 #include "common.h"
 
-#include <atomic>
 #include <type_traits>
 
 namespace mst {
@@ -816,19 +815,6 @@ hipError_t go(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Compute units of the current device, read once per device.
-int device_cus() {
-    static std::atomic<int> cus[64];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    int c = cus[dev].load(std::memory_order_relaxed);
-    if (c <= 0) {
-        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
-            c = 256;
-        cus[dev].store(c, std::memory_order_relaxed);
-    }
-    return c;
-}
 
 // K split of the direct GEMM for a launch shape (the measured cost of the
 // shapes of the blocked solve on MI355X, FP64 and FP32, N = 128 ... 4096):
@@ -841,7 +827,7 @@ int device_cus() {
 //    free up first), so it is used within one round only.
 // A split must promise a tenth less than the best smaller one.
 int pick_split(const GemmArgs& g, int occupancy) {
-    const long simds = 4L * device_cus();
+    const long simds = 4L * device_cu_count();
     const long nks = (g.K + 3) / 4;
     long best = 0;
     int best_ks = 1;
