@@ -409,18 +409,28 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
             }
         }
         if (qa > 0) {
-            // Two-level deferral: inside a group of outer blocks (kSuperRows rows) the
-            // rows above ob get X of ob (K = outer_nb); the rows above the whole
-            // group get X of all its outer blocks in one GEMM once the group is
-            // solved (K = its rows), so most of the substitution runs as a few
-            // deep products instead of many K = outer_nb ones.
+            // Two-level deferral: the rows above a group of outer blocks
+            // (kSuperRows rows) get X of all its outer blocks in one GEMM once
+            // the group is solved (K = its rows), so most of the substitution
+            // runs as a few deep products. Inside the group the order is
+            // binary: after the i-th outer block from the group's bottom is
+            // solved, X of the last L = lowbit(i + 1) solved blocks goes into
+            // the L blocks above them (of four: 1 into 1, 2 into 2, 1 into 1),
+            // which gives every row each block's X exactly once, keeps the
+            // next block's rows current, and makes the middle product twice
+            // as deep as one outer block.
             const int G = (o.outer < kSuperRows) ? kSuperRows / o.outer : 1;   // outer blocks per group
             const int g_lo = (ob / G) * G;
             const int g_hi = (g_lo + G - 1 < nob - 1) ? g_lo + G - 1 : nob - 1;
             const int g0 = q_first(g_lo) * nb;
-            hipError_t e = substitute(ob, g0, qa * nb, s);
-            if (e != hipSuccess) return e;
-            if (ob == g_lo && g0 > 0 && (e = substitute_range(g_lo, g_hi, 0, g0, s)) != hipSuccess) return e;
+            hipError_t e = hipSuccess;
+            if (ob == g_lo) {
+                if (g0 > 0 && (e = substitute_range(g_lo, g_hi, 0, g0, s)) != hipSuccess) return e;
+            } else {
+                const int i = g_hi - ob, L = (i + 1) & -(i + 1);
+                const int lo = (ob - L > g_lo) ? ob - L : g_lo;
+                if ((e = substitute_range(ob, ob + L - 1, q_first(lo) * nb, qa * nb, s)) != hipSuccess) return e;
+            }
         }
     }
     return hipSuccess;
@@ -469,10 +479,11 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
                 if (e != hipSuccess) return e;
             }
         }
-        // Two-level deferral, as in the back-substitution loop: rows below ob
-        // inside its group of outer blocks (kSuperRows rows) get Y of ob
-        // (K = outer_nb); the rows below the whole group get Y of all its
-        // outer blocks in one product once the group is solved.
+        // Two-level deferral, as in the back-substitution loop: the rows below
+        // a group of outer blocks (kSuperRows rows) get Y of all its outer
+        // blocks in one product once the group is solved; inside the group,
+        // after its i-th outer block from the top, Y of the last
+        // L = lowbit(i + 1) solved blocks goes into the L blocks below them.
         const int Gp = (o.outer < kSuperRows) ? kSuperRows / o.outer : 1;
         const int g_lo = (ob / Gp) * Gp;
         const int g_hi = (g_lo + Gp - 1 < nob - 1) ? g_lo + Gp - 1 : nob - 1;
@@ -487,9 +498,15 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
             g.C = G + r1; g.ldc = ldg;
             return timed(MST_PROF_GEMM_F64, gemm_flops(g), s, [&] { return launch_gemm_f64(g, s); });
         };
-        hipError_t e = below(qa * nb, end, end, g_end);
-        if (e != hipSuccess) return e;
-        if (ob == g_hi && (e = below(g_lo * P * nb, g_end, g_end, m)) != hipSuccess) return e;
+        hipError_t e = hipSuccess;
+        if (ob == g_hi) {
+            if ((e = below(g_lo * P * nb, g_end, g_end, m)) != hipSuccess) return e;
+        } else {
+            const int i = ob - g_lo, L = (i + 1) & -(i + 1);
+            const int hi = (ob + L < g_hi) ? ob + L : g_hi;   // last block that receives
+            const int r2 = ((hi + 1) * P * nb < m) ? (hi + 1) * P * nb : m;
+            if ((e = below((ob - L + 1) * P * nb, end, end, r2)) != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
