@@ -38,15 +38,17 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_MFMA_TF = 78.6
 # HBM bytes per launch of the substitution GEMM at this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs scaled by a 512 MiB copy (profiles/k_gemm_direct_solve_m4096_n4096.md).
-# Valid only for the GEMM source it was measured on (sha1 prefix of csrc/kgemm.hip).
-GEMM_TRAFFIC = {"kgemm_sha1": "72f0deb18adf67ae", "bytes_per_launch": 295.4e6, "m": 4096, "n": 4096,
+# Valid only for the sources it was measured on: the GEMM kernel and the block
+# loops that choose its launch shapes (sha1 prefix of csrc/kgemm.hip followed by
+# csrc/api.hip).
+GEMM_TRAFFIC = {"sources_sha1": "78588dcf788ab853", "bytes_per_launch": 278.4e6, "m": 4096, "n": 4096,
                 "nb": 16, "outer_nb": 256,
                 # the pencil substitution (profiles/k_gemm_direct_pencil_m4096_n4096.md)
-                "pencil_bytes_per_launch": 471.0e6}
+                "pencil_bytes_per_launch": 456.2e6}
 # The same for the real substitution GEMM (all its tile variants, averaged over
 # the 15 launches of a solve; profiles/real_solve_m4096_n4096.md), valid for the
-# source it was measured on (sha1 prefix of csrc/kreal.hip).
-REAL_GEMM_TRAFFIC = {"kreal_sha1": "fe0f0182779df525", "bytes_per_launch": 119.4e6, "m": 4096, "n": 4096,
+# sources it was measured on (sha1 prefix of csrc/kreal.hip followed by csrc/api.hip).
+REAL_GEMM_TRAFFIC = {"sources_sha1": "fa78cd6245f54b38", "bytes_per_launch": 112.8e6, "m": 4096, "n": 4096,
                      "outer_nb": 256}
 PEAK_FP32_MFMA_TF = 157.3
 METRIC = "complex128 multi-shift solve GFLOP/s at m=n=4096 and % of MFMA peak vs plain FP64"
@@ -69,28 +71,31 @@ def dev(a, torch):
     return out
 
 
-def gemm_traffic(m, n, nb, outer_nb, pencil=False):
+def sources_sha1(*names):
+    """sha1 prefix of the named csrc files, read in order; None if one is missing."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1607_01477_amd", "csrc", "kgemm.hip")
+    h = hashlib.sha1()
     try:
-        h = hashlib.sha1(open(src, "rb").read()).hexdigest()[:16]
+        for name in names:
+            with open(os.path.join(ROOT, "paper_1607_01477_amd", "csrc", name), "rb") as f:
+                h.update(f.read())
     except OSError:
         return None
+    return h.hexdigest()[:16]
+
+
+def gemm_traffic(m, n, nb, outer_nb, pencil=False):
     t = GEMM_TRAFFIC
-    if h != t["kgemm_sha1"] or (m, n, nb, outer_nb) != (t["m"], t["n"], t["nb"], t["outer_nb"]):
+    if (sources_sha1("kgemm.hip", "api.hip") != t["sources_sha1"]
+            or (m, n, nb, outer_nb) != (t["m"], t["n"], t["nb"], t["outer_nb"])):
         return None
     return t["pencil_bytes_per_launch"] if pencil else t["bytes_per_launch"]
 
 
 def real_gemm_traffic(m, n, outer_nb):
-    import hashlib
-    src = os.path.join(ROOT, "paper_1607_01477_amd", "csrc", "kreal.hip")
-    try:
-        h = hashlib.sha1(open(src, "rb").read()).hexdigest()[:16]
-    except OSError:
-        return None
     t = REAL_GEMM_TRAFFIC
-    if h != t["kreal_sha1"] or (m, n, outer_nb) != (t["m"], t["n"], t["outer_nb"]):
+    if (sources_sha1("kreal.hip", "api.hip") != t["sources_sha1"]
+            or (m, n, outer_nb) != (t["m"], t["n"], t["outer_nb"])):
         return None
     return t["bytes_per_launch"]
 

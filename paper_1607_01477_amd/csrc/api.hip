@@ -567,9 +567,15 @@ hipError_t real_loop(int m, int n, const double* U, long ldu, const double* lam,
             const int g_lo = (ob / G) * G;
             const int g_hi = (g_lo + G - 1 < nob - 1) ? g_lo + G - 1 : nob - 1;
             const int g0 = q_first(g_lo) * nb;
-            hipError_t e = gemm(g0, qa * nb, qa * nb, row_end(ob));
-            if (e != hipSuccess) return e;
-            if (ob == g_lo && g0 > 0 && (e = gemm(0, g0, g0, row_end(g_hi))) != hipSuccess) return e;
+            hipError_t e = hipSuccess;
+            if (ob == g_lo) {
+                if (g0 > 0 && (e = gemm(0, g0, g0, row_end(g_hi))) != hipSuccess) return e;
+            } else {
+                // the same binary order as the complex solve's groups
+                const int i = g_hi - ob, L = (i + 1) & -(i + 1);
+                const int lo = (ob - L > g_lo) ? ob - L : g_lo;
+                if ((e = gemm(q_first(lo) * nb, qa * nb, qa * nb, row_end(ob + L - 1))) != hipSuccess) return e;
+            }
         }
     }
     return hipSuccess;
