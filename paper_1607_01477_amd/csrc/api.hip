@@ -149,9 +149,9 @@ mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
     if (r.sweeps < 1 || r.sweeps > 3) return bad(pos);
     if (o->omega_log2) r.omega_log2 = o->omega_log2;
     if (r.omega_log2 < 8 || r.omega_log2 > 1000) return bad(pos);
-    if (o->fuse_blocks < -1 || o->fuse_blocks > 2) return bad(pos);
+    if (o->fuse_blocks < -1 || o->fuse_blocks > 3) return bad(pos);
     r.fuse = o->fuse_blocks >= 0;
-    r.fuse_width = o->fuse_blocks == 1 ? 16 : (o->fuse_blocks == 2 ? 4 : 0);
+    r.fuse_width = o->fuse_blocks == 1 ? 16 : o->fuse_blocks == 2 ? 4 : o->fuse_blocks == 3 ? 2 : 0;
     if (o->gemm_staged != 0 && o->gemm_staged != 1) return bad(pos);
     r.staged = o->gemm_staged;
     if (o->overlap != 0 && o->overlap != 1) return bad(pos);
@@ -454,6 +454,7 @@ hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* 
             BlockArgs b{};
             b.m = m; b.n = n; b.nb = nb; b.qa = qa; b.iS = qa * nb; b.rows = end - qa * nb;
             b.U = U; b.ldu = ldu; b.lam = lam; b.B = G; b.ldb = ldg;
+            b.width = o.fuse_width;
             b.safe.omega_log2 = o.omega_log2;
             const double fl = 4.0 * b.rows * (double)b.rows * n;
             hipError_t e = timed(MST_PROF_DIAG, fl, s, [&] { return launch_block(ev, b, s); });

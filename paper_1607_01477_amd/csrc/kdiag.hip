@@ -1220,9 +1220,31 @@ __global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_bl
 // wavefront u takes chunks u - 1 and u + 2, its first chunk's U entries
 // loaded during the pass before. Per element the updates keep the order of
 // the blocks, as in k_block.
-constexpr int kColsN = 4;     // shifts per narrow workgroup
 constexpr int kWGN = 256;     // threads per narrow workgroup
-template <int EV, bool SAFE, bool MIXED, bool VARLEN>
+
+// accumulators of a step of the narrow update, pinned after the step (see
+// uapply in k_block_narrow)
+template <int C>
+__device__ __forceinline__ void pin_step(double (&sr)[C], double (&si)[C], double (&tr)[C], double (&ti)[C]) {
+    if constexpr (C == 4) {
+        asm volatile(""
+                     : "+v"(sr[0]), "+v"(sr[1]), "+v"(sr[2]), "+v"(sr[3]), "+v"(si[0]), "+v"(si[1]), "+v"(si[2]),
+                       "+v"(si[3]), "+v"(tr[0]), "+v"(tr[1]), "+v"(tr[2]), "+v"(tr[3]), "+v"(ti[0]), "+v"(ti[1]),
+                       "+v"(ti[2]), "+v"(ti[3])
+                     :
+                     : "memory");
+    } else if constexpr (C == 2) {
+        asm volatile(""
+                     : "+v"(sr[0]), "+v"(sr[1]), "+v"(si[0]), "+v"(si[1]), "+v"(tr[0]), "+v"(tr[1]), "+v"(ti[0]),
+                       "+v"(ti[1])
+                     :
+                     : "memory");
+    } else {
+        static_assert(C == 1, "2^k shifts per narrow workgroup, k <= 2");
+        asm volatile("" : "+v"(sr[0]), "+v"(si[0]), "+v"(tr[0]), "+v"(ti[0]) : : "memory");
+    }
+}
+template <int EV, bool SAFE, bool MIXED, bool VARLEN, int C>
 __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     static_assert(EV == EV_UPPER_N || (!SAFE && !MIXED && !VARLEN), "variants: plain FP64 solves");
     constexpr bool ADJ = ev_fwd(EV);          // forward substitution (E lower triangular)
@@ -1230,21 +1252,21 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     using BS = BlockSolve<16, 1, EV, SAFE>;
     constexpr int NB = 16, NBB = NB * NB;
     constexpr int PERS = 2 * NBB / kWGN;
-    __shared__ zd Bl[kColsN * kSP];
+    __shared__ zd Bl[C * kSP];
     __shared__ zd Us[2][NBB];
     __shared__ zd Uo[2][NBB];
     __shared__ zd Ud[2][NB];
-    __shared__ double Gl[kColsN];
-    __shared__ int kcl[kColsN], dkl[2][kColsN], Ll[kColsN];
+    __shared__ double Gl[C];
+    __shared__ int kcl[C], dkl[2][C], Ll[C];
     // pivots of every row of the outer block and shift (formed in the prologue,
     // off the substitution chain): reciprocal, exponent (safe), cabs1 (safe)
-    __shared__ double Ppr[kColsN][kRowsMax], Ppi[kColsN][kRowsMax];
-    __shared__ int Ppe[SAFE ? kColsN : 1][SAFE ? kRowsMax : 1];
-    __shared__ double Pcd[SAFE ? kColsN : 1][SAFE ? kRowsMax : 1];
+    __shared__ double Ppr[C][kRowsMax], Ppi[C][kRowsMax];
+    __shared__ int Ppe[SAFE ? C : 1][SAFE ? kRowsMax : 1];
+    __shared__ double Pcd[SAFE ? C : 1][SAFE ? kRowsMax : 1];
 
     if (MIXED && a.skip && *a.skip) return;   // refinement stopped
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int col0 = blockIdx.x * kColsN;
+    const int col0 = blockIdx.x * C;
     const int iS = a.iS, rows = a.rows;
     const int w = a.safe.omega_log2;
     const double omega = ldexp(1.0, w);
@@ -1254,7 +1276,7 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     // column lengths of the workgroup's shifts
     int Lmax = 0;
 #pragma unroll
-    for (int c = 0; c < kColsN; ++c) {
+    for (int c = 0; c < C; ++c) {
         const int j = col0 + c;
         int L = 0;
         if (j < a.n) {
@@ -1270,13 +1292,13 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     if (VARLEN && Lmax <= iS) {
         // no column reaches the outer block: nothing to solve, the exponents
         // after each of its diagonal blocks are the current ones
-        if (SAFE && tid < kColsN * nsub) {
-            const int c = tid % kColsN, q = a.qa + tid / kColsN;
+        if (SAFE && tid < C * nsub) {
+            const int c = tid % C, q = a.qa + tid / C;
             if (col0 + c < a.n) a.safe.kb[(long)q * a.n + col0 + c] = a.safe.kcur[col0 + c];
         }
         return;
     }
-    if (tid < kColsN) {
+    if (tid < C) {
         const int j = col0 + tid;
         dkl[0][tid] = 0;
         dkl[1][tid] = 0;
@@ -1288,7 +1310,7 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     // pivots: A(r, r) - lambda_j (conjugated for CJ) for every row of the
     // outer block and shift (1 + 0i outside the block or past the shifts)
     {
-        constexpr int PER = kColsN * kRowsMax / kWGN;
+        constexpr int PER = C * kRowsMax / kWGN;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * kWGN;
@@ -1312,7 +1334,7 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     }
     // right-hand sides of the outer block -> LDS (rows outside the column: 0)
     {
-        constexpr int PER = kColsN * kRowsMax / kWGN;
+        constexpr int PER = C * kRowsMax / kWGN;
         zd st[PER];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
@@ -1465,10 +1487,10 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
         const int row = g.ubeg + chunk * 64 + lane;   // < 256 where stored (row < uend)
         const bool ok = row < g.uend;
         const zd* xb = Bl + g.p0;
-        double sr[kColsN], si[kColsN], tr[kColsN], ti[kColsN];
-        zd x0[kColsN], x1[kColsN], x2[kColsN], x3[kColsN];
+        double sr[C], si[C], tr[C], ti[C];
+        zd x0[C], x1[C], x2[C], x3[C];
 #pragma unroll
-        for (int c = 0; c < kColsN; ++c) {
+        for (int c = 0; c < C; ++c) {
             zd v = Bl[c * kSP + min(row, kRowsMax - 1)];
             x0[c] = xb[c * kSP];
             x1[c] = xb[c * kSP + 1];
@@ -1487,30 +1509,25 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
         for (int k = 0; k < NB; ++k) {
             if (k + 3 < NB) {
 #pragma unroll
-                for (int c = 0; c < kColsN; ++c) x3[c] = xb[c * kSP + k + 3];
+                for (int c = 0; c < C; ++c) x3[c] = xb[c * kSP + k + 3];
             }
 #pragma unroll
-            for (int c = 0; c < kColsN; ++c) {
+            for (int c = 0; c < C; ++c) {
                 sr[c] = fma(-u[k].re, x0[c].re, sr[c]);
                 si[c] = fma(-u[k].re, x0[c].im, si[c]);
                 tr[c] = fma(u[k].im, x0[c].im, tr[c]);
                 ti[c] = fma(-u[k].im, x0[c].re, ti[c]);
             }
-            asm volatile(""
-                         : "+v"(sr[0]), "+v"(sr[1]), "+v"(sr[2]), "+v"(sr[3]), "+v"(si[0]), "+v"(si[1]),
-                           "+v"(si[2]), "+v"(si[3]), "+v"(tr[0]), "+v"(tr[1]), "+v"(tr[2]), "+v"(tr[3]),
-                           "+v"(ti[0]), "+v"(ti[1]), "+v"(ti[2]), "+v"(ti[3])
-                         :
-                         : "memory");
+            pin_step<C>(sr, si, tr, ti);
 #pragma unroll
-            for (int c = 0; c < kColsN; ++c) {
+            for (int c = 0; c < C; ++c) {
                 x0[c] = x1[c];
                 x1[c] = x2[c];
                 x2[c] = x3[c];
             }
         }
 #pragma unroll
-        for (int c = 0; c < kColsN; ++c)
+        for (int c = 0; c < C; ++c)
             if (ok) Bl[c * kSP + row] = zd{sr[c] + tr[c], si[c] + ti[c]};
     };
 
@@ -1519,9 +1536,13 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     // neither holds the other's registers.
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     if (wv == 0) {
-        // shift slot grp = lane / 16, row r = lane % 16
+        // shift slot grp = lane / 16, row r = lane % 16; with fewer than four
+        // shifts the lane groups past them repeat the last shift's chain and
+        // store nothing
         const int grp = lane >> 4, r = lane & 15, base = grp * NB;
-        const bool jv[1] = {col0 + grp < a.n};
+        const bool own = grp < C;
+        const int c = own ? grp : C - 1;
+        const bool jv[1] = {own && col0 + grp < a.n};
         double xpr[1] = {0.0}, xpi[1] = {0.0};
         for (int stp = 0; stp < nsub; ++stp) {
             const int buf = stp & 1;
@@ -1531,7 +1552,6 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
             if (stp + 1 < nsub) stage_load(stp + 1);
             // ---- rows of block q: apply x of block p, then the substitution
             BS S;
-            const int c = grp;
             const bool act = jv[0] && (i0 < Ll[c]);
             zd b{0.0, 0.0};
             if (r < g.bs) b = Bl[c * kSP + g.lr0 + r];
@@ -1578,7 +1598,7 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
                     a.safe.kb[(long)q * a.n + col0 + c] = kc;
                 }
             }
-            if (r < g.bs) Bl[c * kSP + g.lr0 + r] = zd{S.br[0], S.bi[0]};
+            if (own && r < g.bs) Bl[c * kSP + g.lr0 + r] = zd{S.br[0], S.bi[0]};
             xpr[0] = S.br[0];
             xpi[0] = S.bi[0];
             if (stp + 1 < nsub) stage_store(buf ^ 1);
@@ -1620,12 +1640,12 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     }
 
     // ---- solution of the outer block -> HBM; safe state back
-    if (SAFE && tid < kColsN && col0 + tid < a.n) {
+    if (SAFE && tid < C && col0 + tid < a.n) {
         a.safe.G[col0 + tid] = Gl[tid];
         a.safe.kcur[col0 + tid] = kcl[tid];
     }
     {
-        constexpr int PER = kColsN * kRowsMax / kWGN;
+        constexpr int PER = C * kRowsMax / kWGN;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * kWGN;
@@ -1641,13 +1661,29 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
 }
 
 
-// Narrow workgroups for the outer block when the 16-shift grid leaves compute
-// units idle and the narrow grid runs in one round (two narrow workgroups fit
-// on a compute unit).
-bool narrow_pays(const BlockArgs& a) {
+// Shifts per workgroup of the fused outer block when the caller leaves it
+// open: 16 (k_block) unless that grid leaves compute units idle; then the
+// narrowest of 2 and 4 (k_block_narrow) whose grid runs in one round of two
+// workgroups per compute unit. Narrower workgroups shorten each pass (fewer
+// shifts per updating lane) and spread the chains over more compute units.
+int auto_width(const BlockArgs& a) {
     const int cus = device_cu_count();
-    const int wide = (a.n + kCols - 1) / kCols, narrow = (a.n + kColsN - 1) / kColsN;
-    return wide < cus && narrow <= 2 * cus;
+    const int wide = (a.n + kCols - 1) / kCols, w4 = (a.n + 3) / 4, w2 = (a.n + 1) / 2;
+    if (wide >= cus || w4 > 2 * cus) return 16;
+    return w2 <= 2 * cus ? 2 : 4;
+}
+
+template <int EV, int C>
+void launch_narrow(const BlockArgs& a, bool safe, bool mixed, bool varlen, hipStream_t s) {
+    const dim3 gn((a.n + C - 1) / C), bn(kWGN);
+    if constexpr (EV == EV_UPPER_N) {
+        if (safe && varlen) hipLaunchKernelGGL((k_block_narrow<EV, true, false, true, C>), gn, bn, 0, s, a);
+        else if (safe) hipLaunchKernelGGL((k_block_narrow<EV, true, false, false, C>), gn, bn, 0, s, a);
+        else if (mixed) hipLaunchKernelGGL((k_block_narrow<EV, false, true, false, C>), gn, bn, 0, s, a);
+        else hipLaunchKernelGGL((k_block_narrow<EV, false, false, false, C>), gn, bn, 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_block_narrow<EV, false, false, false, C>), gn, bn, 0, s, a);
+    }
 }
 
 template <int NB, int SPW, int EV>
@@ -1701,16 +1737,10 @@ hipError_t launch_blk(const BlockArgs& a, hipStream_t s) {
         // 4-shift workgroups where 16-shift ones would leave compute units idle
         const bool supported = a.V == nullptr && !(safe && mixed) && !(varlen && !safe) &&
                                (EV == EV_UPPER_N || (!safe && !mixed && !varlen));
-        if (supported && (a.width == 4 || (a.width == 0 && narrow_pays(a)))) {
-            const dim3 gn((a.n + kColsN - 1) / kColsN), bn(kWGN);
-            if constexpr (EV == EV_UPPER_N) {
-                if (safe && varlen) hipLaunchKernelGGL((k_block_narrow<EV, true, false, true>), gn, bn, 0, s, a);
-                else if (safe) hipLaunchKernelGGL((k_block_narrow<EV, true, false, false>), gn, bn, 0, s, a);
-                else if (mixed) hipLaunchKernelGGL((k_block_narrow<EV, false, true, false>), gn, bn, 0, s, a);
-                else hipLaunchKernelGGL((k_block_narrow<EV, false, false, false>), gn, bn, 0, s, a);
-            } else {
-                hipLaunchKernelGGL((k_block_narrow<EV, false, false, false>), gn, bn, 0, s, a);
-            }
+        const int width = !supported ? 16 : a.width ? a.width : auto_width(a);
+        if (width == 4 || width == 2) {
+            if (width == 4) launch_narrow<EV, 4>(a, safe, mixed, varlen, s);
+            else launch_narrow<EV, 2>(a, safe, mixed, varlen, s);
             return hipGetLastError();
         }
     }

@@ -1,12 +1,12 @@
-"""Fused outer blocks with 4 shifts per workgroup (mst_opts.fuse_blocks = 2,
-chosen automatically when 16-shift workgroups would leave compute units idle)
-against the oracle: plain solves on shapes with partial outer and diagonal
+"""Fused outer blocks with 4 or 2 shifts per workgroup (mst_opts.fuse_blocks
+= 2 or 3, chosen automatically when 16-shift workgroups would leave compute
+units idle) against the oracle: plain solves on shapes with partial outer and diagonal
 blocks and shift counts that are not multiples of 4, the safe solve with
 rescaling, variable-length columns and the triangular eigenvectors (exponents
 equal to the oracle's Alg 5), mixed precision, the lower-triangular,
 transposed and conjugated variants and the adjoint (forward substitution,
-the other triangle filled with NaN), the automatic choice, and agreement with
-the 16-shift kernel to rounding."""
+the other triangle filled with NaN), the automatic choice, agreement with
+the 16-shift kernel to rounding, and the same bits at both narrow widths."""
 import numpy as np
 import pytest
 
@@ -44,11 +44,12 @@ def _kappa(U, lam, cols):
 
 @pytest.mark.parametrize("m,n,outer", [(1, 1, 256), (17, 5, 256), (256, 4, 256), (530, 70, 256),
                                        (1000, 37, 128), (700, 9, 64)])
-def test_narrow_plain(P, oracle_mod, m, n, outer):
-    announce("narrow plain m=%d n=%d outer=%d" % (m, n, outer))
+@pytest.mark.parametrize("width", [4, 2])
+def test_narrow_plain(P, oracle_mod, m, n, outer, width):
+    announce("narrow w%d " % width + "plain m=%d n=%d outer=%d" % (m, n, outer))
     w = W.c1_plain(seed=400 + m + n, m=m, n=n)
-    X = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=outer, fuse_width=4))
-    X2 = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=outer, fuse_width=4))
+    X = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=outer, fuse_width=width))
+    X2 = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=outer, fuse_width=width))
     assert np.array_equal(_bits(X), _bits(X2))
     rr = oracle_mod.relative_residual(w.U, w.shifts, X, w.B)
     assert rr.max() <= 1e-13, rr.max()
@@ -61,14 +62,21 @@ def test_narrow_plain(P, oracle_mod, m, n, outer):
 
 
 def test_narrow_automatic_choice(P):
-    """Few shifts: the automatic width is the narrow one (same bits as forced
-    4); 4096 shifts fill the device with 16-shift workgroups (same bits as
-    forced 16)."""
+    """Few shifts: the automatic width is a narrow one (same bits as forced 2
+    and 4, unlike 16), in the back and the forward substitution; 4096 shifts
+    fill the device with 16-shift workgroups (same bits as forced 16)."""
     w = W.c1_plain(seed=410, m=300, n=40)
     args = (dev(w.U), dev(w.shifts))
     Xa = host(P.mstrsm(*args, dev(w.B), nb=16))
     X4 = host(P.mstrsm(*args, dev(w.B), nb=16, fuse_width=4))
+    X16 = host(P.mstrsm(*args, dev(w.B), nb=16, fuse_width=16))
     assert np.array_equal(_bits(Xa), _bits(X4))
+    assert not np.array_equal(_bits(Xa), _bits(X16))
+    Ya = host(P.mstrsm_adjoint(*args, dev(w.B), nb=16))
+    Y2 = host(P.mstrsm_adjoint(*args, dev(w.B), nb=16, fuse_width=2))
+    Y16 = host(P.mstrsm_adjoint(*args, dev(w.B), nb=16, fuse_width=16))
+    assert np.array_equal(_bits(Ya), _bits(Y2))
+    assert not np.array_equal(_bits(Ya), _bits(Y16))
     w = W.c1_plain(seed=411, m=300, n=4096)
     args = (dev(w.U), dev(w.shifts))
     Xa = host(P.mstrsm(*args, dev(w.B), nb=16))
@@ -77,14 +85,15 @@ def test_narrow_automatic_choice(P):
 
 
 @pytest.mark.parametrize("omega_log2", [960, 40])
-def test_narrow_safe_growth(P, oracle_mod, omega_log2):
+@pytest.mark.parametrize("width", [4, 2])
+def test_narrow_safe_growth(P, oracle_mod, omega_log2, width):
     g = W.rng(420)
     m, n = 450, 30
     U = W.random_upper(g, m, 1.0, W.cnormal(g, m))
     lam = W.cnormal(g, n)
     B = np.asfortranarray(W.cnormal(g, (m, n)))
-    announce("narrow safe omega 2^%d" % omega_log2)
-    X, s, k = P.mstrsm_safe(dev(U), dev(lam), dev(B), nb=16, omega_log2=omega_log2, fuse_width=4)
+    announce("narrow w%d " % width + "safe omega 2^%d" % omega_log2)
+    X, s, k = P.mstrsm_safe(dev(U), dev(lam), dev(B), nb=16, omega_log2=omega_log2, fuse_width=width)
     X, s, k = host(X), host(s), host(k)
     Xo, so, ko = oracle_mod.solve_safe(U, lam, B, nb=16, omega_log2=omega_log2)
     assert np.array_equal(k, ko) and np.array_equal(s, so)
@@ -94,12 +103,13 @@ def test_narrow_safe_growth(P, oracle_mod, omega_log2):
     rr = oracle_mod.relative_residual(U, lam, X, B, k=k)
     assert rr.max() <= 1e-13, rr.max()
     # forced checked steps: the same bits
-    Xf, sf, kf = P.mstrsm_safe(dev(U), dev(lam), dev(B), nb=16, omega_log2=omega_log2, fuse_width=4,
+    Xf, sf, kf = P.mstrsm_safe(dev(U), dev(lam), dev(B), nb=16, omega_log2=omega_log2, fuse_width=width,
                                force_phase2=True)
     assert np.array_equal(_bits(host(Xf)), _bits(X)) and np.array_equal(host(kf), k)
 
 
-def test_narrow_col_len(P, oracle_mod):
+@pytest.mark.parametrize("width", [4, 2])
+def test_narrow_col_len(P, oracle_mod, width):
     """Variable-length columns, including lengths 0, 1, m and columns whose
     workgroup has no column reaching an outer block (early exit)."""
     import torch
@@ -111,9 +121,9 @@ def test_narrow_col_len(P, oracle_mod):
     L = np.sort(W.rng(431).integers(0, m + 1, n)).astype(np.int32)
     L[:5] = [0, 1, 3, 16, 17]
     L[-1] = m
-    announce("narrow col_len")
+    announce("narrow w%d " % width + "col_len")
     X, s, k = P.mstrsm_safe(dev(U), dev(lam), dev(B), col_len=dev(L, dtype=torch.int32), nb=16,
-                            omega_log2=50, fuse_width=4)
+                            omega_log2=50, fuse_width=width)
     X, k = host(X), host(k)
     Xo, so, ko = oracle_mod.solve_safe(U, lam, B, col_len=L, nb=16, omega_log2=50)
     assert np.array_equal(k, ko)
@@ -125,10 +135,11 @@ def test_narrow_col_len(P, oracle_mod):
 
 
 @pytest.mark.parametrize("m", [600, 2048])
-def test_narrow_triang_eig(P, oracle_mod, m):
+@pytest.mark.parametrize("width", [4, 2])
+def test_narrow_triang_eig(P, oracle_mod, m, width):
     w = W.c2_triang_eig(m=m)
-    announce("narrow triang_eig m=%d" % m)
-    ev, Z, k = P.triang_eig(dev(w.U), nb=16, fuse_width=4)
+    announce("narrow w%d " % width + "triang_eig m=%d" % m)
+    ev, Z, k = P.triang_eig(dev(w.U), nb=16, fuse_width=width)
     ev, Z, k = host(ev), host(Z), host(k)
     lo, Zo, ko = oracle_mod.triang_eig(w.U, nb=16)
     assert np.array_equal(ev, lo)
@@ -144,11 +155,12 @@ def test_narrow_triang_eig(P, oracle_mod, m):
     assert rel.max() <= 1e-13, rel.max()
 
 
-def test_narrow_mixed_precision(P, oracle_mod):
+@pytest.mark.parametrize("width", [4, 2])
+def test_narrow_mixed_precision(P, oracle_mod, width):
     w = W.c3_mixed(seed=440, m=700, n=60)
-    announce("narrow mixed")
+    announce("narrow w%d " % width + "mixed")
     X = host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), precision=1, max_sweeps=2, refine_tol=-1.0,
-                      fuse_width=4))
+                      fuse_width=width))
     rr = oracle_mod.relative_residual(w.U, w.shifts, X, w.B)
     assert rr.max() <= 1e-13, rr.max()
     Xo = oracle_mod.solve(w.U, w.shifts, w.B)
@@ -162,7 +174,8 @@ def _operator(A, lam, uplo, op):
 
 
 @pytest.mark.parametrize("uplo,op", [(u, o) for u in "UL" for o in "NTC"])
-def test_narrow_variants(P, oracle_mod, uplo, op):
+@pytest.mark.parametrize("width", [4, 2])
+def test_narrow_variants(P, oracle_mod, uplo, op, width):
     """op(A - l_j I) x_j = b_j for A upper or lower and op N, T, C with 4-shift
     fused blocks (forward substitution for lower N and upper T/C): residual,
     oracle agreement, the unread triangle NaN, and agreement with the 16-shift
@@ -175,8 +188,8 @@ def test_narrow_variants(P, oracle_mod, uplo, op):
         An[np.tril_indices(m, -1)] = np.nan
     else:
         An[np.triu_indices(m, 1)] = np.nan
-    announce("narrow variant %s%s" % (uplo, op))
-    X = host(P.mstrsm_op(dev(An), dev(w.shifts), dev(w.B), uplo=uplo, op=op, nb=16, fuse_width=4))
+    announce("narrow w%d " % width + "variant %s%s" % (uplo, op))
+    X = host(P.mstrsm_op(dev(An), dev(w.shifts), dev(w.B), uplo=uplo, op=op, nb=16, fuse_width=width))
     assert np.all(np.isfinite(X))
     Xo = oracle_mod.solve_op(A, w.shifts, w.B, uplo, op)
     X16 = host(P.mstrsm_op(dev(An), dev(w.shifts), dev(w.B), uplo=uplo, op=op, nb=16, fuse_width=16))
@@ -190,12 +203,13 @@ def test_narrow_variants(P, oracle_mod, uplo, op):
             assert colerr(X[:, j:j + 1], X16[:, j:j + 1])[0] <= 128 * EPS * kap
 
 
-def test_narrow_adjoint(P, oracle_mod):
+@pytest.mark.parametrize("width", [4, 2])
+def test_narrow_adjoint(P, oracle_mod, width):
     m, n = 600, 50
     w = W.c1_plain(seed=460, m=m, n=n)
-    announce("narrow adjoint")
-    Y = host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=4))
-    Y2 = host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=4))
+    announce("narrow w%d " % width + "adjoint")
+    Y = host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=width))
+    Y2 = host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=width))
     assert np.array_equal(_bits(Y), _bits(Y2))
     Yo = oracle_mod.solve_adjoint(w.U, w.shifts, w.B)
     Ut = np.triu(w.U)
@@ -206,3 +220,24 @@ def test_narrow_adjoint(P, oracle_mod):
     cols = np.arange(0, n, 7)
     kap = _kappa(w.U, w.shifts, cols)
     assert np.all(colerr(Y[:, cols], Yo[:, cols]) <= 64 * EPS * kap)
+
+
+def test_narrow_widths_same_bits(P):
+    """2- and 4-shift workgroups take the same steps for each shift: the same
+    bits in the plain solve, the safe solve with rescaling (and the same
+    exponents) and the adjoint."""
+    w = W.c1_plain(seed=470, m=530, n=23)
+    announce("narrow widths same bits")
+    X = [host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=c)) for c in (4, 2)]
+    assert np.array_equal(_bits(X[0]), _bits(X[1]))
+    Y = [host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=c)) for c in (4, 2)]
+    assert np.array_equal(_bits(Y[0]), _bits(Y[1]))
+    g = W.rng(471)
+    m, n = 450, 19
+    U = W.random_upper(g, m, 1.0, W.cnormal(g, m))
+    lam = W.cnormal(g, n)
+    B = np.asfortranarray(W.cnormal(g, (m, n)))
+    R = [P.mstrsm_safe(dev(U), dev(lam), dev(B), nb=16, omega_log2=40, fuse_width=c) for c in (4, 2)]
+    assert np.any(host(R[0][2]) > 0)
+    assert np.array_equal(_bits(host(R[0][0])), _bits(host(R[1][0])))
+    assert np.array_equal(host(R[0][2]), host(R[1][2]))
