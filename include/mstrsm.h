@@ -66,14 +66,15 @@ typedef struct {
                           Results are the same bit for bit (tested). */
     int fuse_blocks;   /* 0 (default): an outer block of at most 256 rows is solved by one
                           fused kernel (diagonal blocks plus the substitution between them),
-                          with 16 shifts per workgroup, or with 4 or 2 where 16-shift
+                          with 16 shifts per workgroup, or with 4, 2 or 1 where 16-shift
                           workgroups would leave compute units idle (nb = 16, standard
                           problem, at most 8 x (compute units) shifts; the safe, variable-
-                          length and mixed forms in the upper op N solve); 1, 2 or 3 force
-                          16, 4 or 2 shifts per workgroup (2 and 3 fall back to 16 where
-                          the narrow kernel is not available). The 16-shift kernel applies
-                          the in-block updates in another summation order than the narrow
-                          ones, so results agree to rounding; 4 and 2 give the same bits.
+                          length and mixed forms in the upper op N solve); 1, 2, 3 or 4
+                          force 16, 4, 2 or 1 shifts per workgroup (2, 3 and 4 fall back to
+                          16 where the narrow kernel is not available). The 16-shift kernel
+                          applies the in-block updates in another summation order than the
+                          narrow ones, so results agree to rounding; 4, 2 and 1 give the
+                          same bits.
                           -1: one kernel per diagonal block plus separate GEMMs (same
                           arithmetic, kept for testing and for outer_nb > 256). */
     int gemm_staged;   /* 0 (default): substitution GEMM without LDS staging (each wavefront

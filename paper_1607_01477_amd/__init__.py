@@ -44,9 +44,9 @@ def _opts(nb=0, outer_nb=0, precision=0, max_sweeps=0, omega_log2=0, force_phase
     o.gemm_staged = 1 if staged else 0
     o.nb, o.outer_nb, o.precision = int(nb), int(outer_nb), int(precision)
     o.max_sweeps, o.omega_log2, o.force_phase2 = int(max_sweeps), int(omega_log2), int(force_phase2)
-    if fuse_width not in (0, 2, 4, 16):
-        raise ValueError("fuse_width must be 0 (automatic), 2, 4 or 16")
-    o.fuse_blocks = {0: 0, 16: 1, 4: 2, 2: 3}[fuse_width] if fuse else -1
+    if fuse_width not in (0, 1, 2, 4, 16):
+        raise ValueError("fuse_width must be 0 (automatic), 1, 2, 4 or 16")
+    o.fuse_blocks = {0: 0, 16: 1, 4: 2, 2: 3, 1: 4}[fuse_width] if fuse else -1
     return o
 
 

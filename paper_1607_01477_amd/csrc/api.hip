@@ -149,9 +149,9 @@ mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
     if (r.sweeps < 1 || r.sweeps > 3) return bad(pos);
     if (o->omega_log2) r.omega_log2 = o->omega_log2;
     if (r.omega_log2 < 8 || r.omega_log2 > 1000) return bad(pos);
-    if (o->fuse_blocks < -1 || o->fuse_blocks > 3) return bad(pos);
+    if (o->fuse_blocks < -1 || o->fuse_blocks > 4) return bad(pos);
     r.fuse = o->fuse_blocks >= 0;
-    r.fuse_width = o->fuse_blocks == 1 ? 16 : o->fuse_blocks == 2 ? 4 : o->fuse_blocks == 3 ? 2 : 0;
+    r.fuse_width = o->fuse_blocks == 1 ? 16 : o->fuse_blocks == 2 ? 4 : o->fuse_blocks == 3 ? 2 : o->fuse_blocks == 4 ? 1 : 0;
     if (o->gemm_staged != 0 && o->gemm_staged != 1) return bad(pos);
     r.staged = o->gemm_staged;
     if (o->overlap != 0 && o->overlap != 1) return bad(pos);

@@ -84,7 +84,7 @@ struct BlockArgs {
     SafeState safe;
     int use_safe;
     const int* skip;   // mixed precision: nothing is done when *skip != 0 (nullable)
-    int width;         // shifts per workgroup: 16, 4 or 2 (where available); 0 = chosen from n
+    int width;         // shifts per workgroup: 16, 4, 2 or 1 (where available); 0 = chosen from n
 };
 int block_rows_max();
 bool block_fusable(int nb);   // nb handled by the fused kernel (16 or 32)

@@ -1662,14 +1662,17 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
 
 
 // Shifts per workgroup of the fused outer block when the caller leaves it
-// open: 16 (k_block) unless that grid leaves compute units idle; then the
-// narrowest of 2 and 4 (k_block_narrow) whose grid runs in one round of two
-// workgroups per compute unit. Narrower workgroups shorten each pass (fewer
-// shifts per updating lane) and spread the chains over more compute units.
+// open: 16 (k_block) unless that grid leaves compute units idle; then
+// k_block_narrow with 1 shift per workgroup where that grid gives each compute
+// unit at most one workgroup, else the narrowest of 2 and 4 whose grid runs in
+// one round of two workgroups per compute unit. Narrower workgroups shorten
+// each pass (fewer shifts per updating lane) and spread the chains over more
+// compute units, until two of them share a compute unit.
 int auto_width(const BlockArgs& a) {
     const int cus = device_cu_count();
     const int wide = (a.n + kCols - 1) / kCols, w4 = (a.n + 3) / 4, w2 = (a.n + 1) / 2;
     if (wide >= cus || w4 > 2 * cus) return 16;
+    if (a.n <= cus) return 1;
     return w2 <= 2 * cus ? 2 : 4;
 }
 
@@ -1738,9 +1741,10 @@ hipError_t launch_blk(const BlockArgs& a, hipStream_t s) {
         const bool supported = a.V == nullptr && !(safe && mixed) && !(varlen && !safe) &&
                                (EV == EV_UPPER_N || (!safe && !mixed && !varlen));
         const int width = !supported ? 16 : a.width ? a.width : auto_width(a);
-        if (width == 4 || width == 2) {
+        if (width == 4 || width == 2 || width == 1) {
             if (width == 4) launch_narrow<EV, 4>(a, safe, mixed, varlen, s);
-            else launch_narrow<EV, 2>(a, safe, mixed, varlen, s);
+            else if (width == 2) launch_narrow<EV, 2>(a, safe, mixed, varlen, s);
+            else launch_narrow<EV, 1>(a, safe, mixed, varlen, s);
             return hipGetLastError();
         }
     }

@@ -62,9 +62,9 @@ def test_option_errors_without_gpu():
         o = _lib.MstOpts()
         o.gemm_split = good
         assert lib.mstrsm(0, 7, None, 1, None, None, 1, ctypes.byref(o), None) == _lib.MST_OK
-    # fuse_blocks: -1 (per block), 0 (automatic width), 1 / 2 / 3 (16 / 4 / 2 shifts per workgroup)
-    for fb, want in ((-2, _lib.MST_EARG), (4, _lib.MST_EARG), (-1, _lib.MST_OK), (0, _lib.MST_OK),
-                     (1, _lib.MST_OK), (2, _lib.MST_OK), (3, _lib.MST_OK)):
+    # fuse_blocks: -1 (per block), 0 (automatic width), 1 / 2 / 3 / 4 (16 / 4 / 2 / 1 shifts per workgroup)
+    for fb, want in ((-2, _lib.MST_EARG), (5, _lib.MST_EARG), (-1, _lib.MST_OK), (0, _lib.MST_OK),
+                     (1, _lib.MST_OK), (2, _lib.MST_OK), (3, _lib.MST_OK), (4, _lib.MST_OK)):
         o = _lib.MstOpts()
         o.fuse_blocks = fb
         assert lib.mstrsm(0, 7, None, 1, None, None, 1, ctypes.byref(o), None) == want

@@ -1,12 +1,12 @@
-"""Fused outer blocks with 4 or 2 shifts per workgroup (mst_opts.fuse_blocks
-= 2 or 3, chosen automatically when 16-shift workgroups would leave compute
+"""Fused outer blocks with 4, 2 or 1 shifts per workgroup (mst_opts.fuse_blocks
+= 2, 3 or 4, chosen automatically when 16-shift workgroups would leave compute
 units idle) against the oracle: plain solves on shapes with partial outer and diagonal
 blocks and shift counts that are not multiples of 4, the safe solve with
 rescaling, variable-length columns and the triangular eigenvectors (exponents
 equal to the oracle's Alg 5), mixed precision, the lower-triangular,
 transposed and conjugated variants and the adjoint (forward substitution,
 the other triangle filled with NaN), the automatic choice, agreement with
-the 16-shift kernel to rounding, and the same bits at both narrow widths."""
+the 16-shift kernel to rounding, and the same bits at every narrow width."""
 import numpy as np
 import pytest
 
@@ -44,7 +44,7 @@ def _kappa(U, lam, cols):
 
 @pytest.mark.parametrize("m,n,outer", [(1, 1, 256), (17, 5, 256), (256, 4, 256), (530, 70, 256),
                                        (1000, 37, 128), (700, 9, 64)])
-@pytest.mark.parametrize("width", [4, 2])
+@pytest.mark.parametrize("width", [4, 2, 1])
 def test_narrow_plain(P, oracle_mod, m, n, outer, width):
     announce("narrow w%d " % width + "plain m=%d n=%d outer=%d" % (m, n, outer))
     w = W.c1_plain(seed=400 + m + n, m=m, n=n)
@@ -62,8 +62,8 @@ def test_narrow_plain(P, oracle_mod, m, n, outer, width):
 
 
 def test_narrow_automatic_choice(P):
-    """Few shifts: the automatic width is a narrow one (same bits as forced 2
-    and 4, unlike 16), in the back and the forward substitution; 4096 shifts
+    """Few shifts: the automatic width is a narrow one (same bits as forced 1,
+    2 and 4, unlike 16), in the back and the forward substitution; 4096 shifts
     fill the device with 16-shift workgroups (same bits as forced 16)."""
     w = W.c1_plain(seed=410, m=300, n=40)
     args = (dev(w.U), dev(w.shifts))
@@ -85,7 +85,7 @@ def test_narrow_automatic_choice(P):
 
 
 @pytest.mark.parametrize("omega_log2", [960, 40])
-@pytest.mark.parametrize("width", [4, 2])
+@pytest.mark.parametrize("width", [4, 2, 1])
 def test_narrow_safe_growth(P, oracle_mod, omega_log2, width):
     g = W.rng(420)
     m, n = 450, 30
@@ -108,7 +108,7 @@ def test_narrow_safe_growth(P, oracle_mod, omega_log2, width):
     assert np.array_equal(_bits(host(Xf)), _bits(X)) and np.array_equal(host(kf), k)
 
 
-@pytest.mark.parametrize("width", [4, 2])
+@pytest.mark.parametrize("width", [4, 2, 1])
 def test_narrow_col_len(P, oracle_mod, width):
     """Variable-length columns, including lengths 0, 1, m and columns whose
     workgroup has no column reaching an outer block (early exit)."""
@@ -135,7 +135,7 @@ def test_narrow_col_len(P, oracle_mod, width):
 
 
 @pytest.mark.parametrize("m", [600, 2048])
-@pytest.mark.parametrize("width", [4, 2])
+@pytest.mark.parametrize("width", [4, 2, 1])
 def test_narrow_triang_eig(P, oracle_mod, m, width):
     w = W.c2_triang_eig(m=m)
     announce("narrow w%d " % width + "triang_eig m=%d" % m)
@@ -155,7 +155,7 @@ def test_narrow_triang_eig(P, oracle_mod, m, width):
     assert rel.max() <= 1e-13, rel.max()
 
 
-@pytest.mark.parametrize("width", [4, 2])
+@pytest.mark.parametrize("width", [4, 2, 1])
 def test_narrow_mixed_precision(P, oracle_mod, width):
     w = W.c3_mixed(seed=440, m=700, n=60)
     announce("narrow w%d " % width + "mixed")
@@ -174,7 +174,7 @@ def _operator(A, lam, uplo, op):
 
 
 @pytest.mark.parametrize("uplo,op", [(u, o) for u in "UL" for o in "NTC"])
-@pytest.mark.parametrize("width", [4, 2])
+@pytest.mark.parametrize("width", [4, 2, 1])
 def test_narrow_variants(P, oracle_mod, uplo, op, width):
     """op(A - l_j I) x_j = b_j for A upper or lower and op N, T, C with 4-shift
     fused blocks (forward substitution for lower N and upper T/C): residual,
@@ -203,7 +203,7 @@ def test_narrow_variants(P, oracle_mod, uplo, op, width):
             assert colerr(X[:, j:j + 1], X16[:, j:j + 1])[0] <= 128 * EPS * kap
 
 
-@pytest.mark.parametrize("width", [4, 2])
+@pytest.mark.parametrize("width", [4, 2, 1])
 def test_narrow_adjoint(P, oracle_mod, width):
     m, n = 600, 50
     w = W.c1_plain(seed=460, m=m, n=n)
@@ -223,21 +223,23 @@ def test_narrow_adjoint(P, oracle_mod, width):
 
 
 def test_narrow_widths_same_bits(P):
-    """2- and 4-shift workgroups take the same steps for each shift: the same
-    bits in the plain solve, the safe solve with rescaling (and the same
+    """4-, 2- and 1-shift workgroups take the same steps for each shift: the
+    same bits in the plain solve, the safe solve with rescaling (and the same
     exponents) and the adjoint."""
+    widths = (4, 2, 1)
     w = W.c1_plain(seed=470, m=530, n=23)
     announce("narrow widths same bits")
-    X = [host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=c)) for c in (4, 2)]
-    assert np.array_equal(_bits(X[0]), _bits(X[1]))
-    Y = [host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=c)) for c in (4, 2)]
-    assert np.array_equal(_bits(Y[0]), _bits(Y[1]))
+    X = [host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=c)) for c in widths]
+    Y = [host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=c)) for c in widths]
     g = W.rng(471)
     m, n = 450, 19
     U = W.random_upper(g, m, 1.0, W.cnormal(g, m))
     lam = W.cnormal(g, n)
     B = np.asfortranarray(W.cnormal(g, (m, n)))
-    R = [P.mstrsm_safe(dev(U), dev(lam), dev(B), nb=16, omega_log2=40, fuse_width=c) for c in (4, 2)]
+    R = [P.mstrsm_safe(dev(U), dev(lam), dev(B), nb=16, omega_log2=40, fuse_width=c) for c in widths]
     assert np.any(host(R[0][2]) > 0)
-    assert np.array_equal(_bits(host(R[0][0])), _bits(host(R[1][0])))
-    assert np.array_equal(host(R[0][2]), host(R[1][2]))
+    for i in (1, 2):
+        assert np.array_equal(_bits(X[0]), _bits(X[i]))
+        assert np.array_equal(_bits(Y[0]), _bits(Y[i]))
+        assert np.array_equal(_bits(host(R[0][0])), _bits(host(R[i][0])))
+        assert np.array_equal(host(R[0][2]), host(R[i][2]))
