@@ -46,7 +46,9 @@ typedef enum {
 /* Options. A NULL mst_opts* means all defaults; a zero field means its default. */
 typedef struct {
     int nb;            /* diagonal-block (and scaling-decision) size: 16, 32 or 64; default 16 */
-    int outer_nb;      /* rows per deferred substitution step, a multiple of nb; default 256.
+    int outer_nb;      /* rows per deferred substitution step, a multiple of nb; 0 (default):
+                          256, or 512 in plain FP64 back substitutions whose fused blocks
+                          run 1 or 2 shifts per workgroup (few shifts; see fuse_blocks).
                           Equal to nb gives the paper's right-looking order (Alg 3 / Alg 5). */
     int precision;     /* 0: all FP64.
                           1: substitution GEMMs in FP32 on MFMA (FP32 accumulation),
@@ -76,7 +78,8 @@ typedef struct {
                           narrow ones, so results agree to rounding; 4, 2 and 1 give the
                           same bits.
                           -1: one kernel per diagonal block plus separate GEMMs (same
-                          arithmetic, kept for testing and for outer_nb > 256). */
+                          arithmetic, kept for testing and for outer blocks larger than the
+                          fused kernel takes). */
     int gemm_staged;   /* 0 (default): substitution GEMM without LDS staging (each wavefront
                           streams its operands from L1/L2); 1: LDS-staged GEMM. Same results
                           up to summation order; kept for testing. */

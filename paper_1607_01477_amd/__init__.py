@@ -1,7 +1,7 @@
 """Blocked multi-shift triangular solves on AMD MI355X (gfx950).
 
 Python binding of ``libmstrsm.so`` (C-ABI declared in ``include/mstrsm.h``).
-Keyword options left at 0 take the library's defaults (nb = 16, outer_nb = 256).
+Keyword options left at 0 take the library's defaults (nb = 16; outer_nb = 256, or 512 in plain back substitutions with few shifts).
 Every function here only marshals arguments: tensors must be complex128 (int32
 for ``col_len``) on a ROCm device; matrices are passed column-major (a
 Fortran-ordered view, ``t.stride(0) == 1``), copied into that layout if they

@@ -123,6 +123,7 @@ double gemm_flops(const GemmArgs& g) {
 
 struct Opts {
     int nb = 16, outer = 256, precision = 0, sweeps = 2, omega_log2 = 960;
+    bool outer_auto = true;   // outer_nb left to the library
     bool fuse = true;
     int fuse_width = 0;
     int staged = 0;
@@ -141,6 +142,7 @@ mst_status read_opts(const mst_opts* o, Opts& r, int pos) {
     if (o->nb) r.nb = o->nb;
     if (r.nb != 16 && r.nb != 32 && r.nb != 64) return bad(pos);
     r.outer = o->outer_nb ? o->outer_nb : (r.nb > 256 ? r.nb : 256);
+    r.outer_auto = o->outer_nb == 0;
     if (o->outer_nb == 0 && r.outer % r.nb) r.outer = r.nb;
     if (r.outer < r.nb || r.outer % r.nb || r.outer > 8192) return bad(pos);
     r.precision = o->precision;
@@ -247,10 +249,24 @@ hipError_t aux_get(int nev, Aux** out) {
 // rows per group of the two-level deferral in the one-stream forward loop
 constexpr int kSuperRows = 1024;
 
+// Outer block size of a back substitution: where the library chooses it and
+// the fused kernel runs narrow workgroups of at most 2 shifts (plain FP64
+// solves with few shifts), outer blocks of twice the rows: half the fused
+// launches and half the substitution GEMMs, whose small launches are bound by
+// their start-up rather than their flops at this n.
+Opts outer_for(const Opts& o, int n, bool plain) {
+    Opts r = o;
+    if (o.outer_auto && o.fuse && !o.overlap && o.outer < block_rows_for(n, o.nb, o.fuse_width, plain))
+        r.outer = block_rows_for(n, o.nb, o.fuse_width, plain);
+    return r;
+}
+
 hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long ldu32,
-                        const zd* lam, zd* B, long ldb, zf* W32, long ldw, const Opts& o,
+                        const zd* lam, zd* B, long ldb, zf* W32, long ldw, const Opts& oin,
                         const SafeState* safe, const int* col_len, hipStream_t s,
                         const zd* V = nullptr, long ldv = 0, int ev = EV_UPPER_N) {
+    const bool plain = safe == nullptr && col_len == nullptr && W32 == nullptr && V == nullptr;
+    const Opts o = outer_for(oin, n, plain);
     // ev: EV_UPPER_N, or EV_LOWER_T / EV_LOWER_C (plain FP64): back substitution
     // with E(r, c) = A(c, r) (conjugated for EV_LOWER_C) read from A's lower triangle
     const bool etr = ev_tr(ev);
@@ -259,7 +275,7 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
     const int nblk = (m + nb - 1) / nb;
     const int nob = (nblk + P - 1) / P;
     const bool mixed = W32 != nullptr;
-    const bool fused = o.fuse && o.outer <= block_rows_max() && block_fusable(o.nb);
+    const bool fused = o.fuse && o.outer <= block_rows_for(n, o.nb, o.fuse_width, plain) && block_fusable(o.nb);
     auto q_first = [&](int ob) { return ob * P; };
     auto q_last = [&](int ob) { return (ob * P + P < nblk ? ob * P + P : nblk) - 1; };
     auto row_end = [&](int ob) { return ((q_last(ob) + 1) * nb < m) ? (q_last(ob) + 1) * nb : m; };
@@ -441,12 +457,13 @@ hipError_t forward_loop(int m, int n, const zd* U, long ldu, const zf* U32, long
 // A's lower triangle): forward substitution, blocks top to bottom
 hipError_t adjoint_loop(int m, int n, const zd* U, long ldu, const zd* lam, zd* G, long ldg,
                         const Opts& o, hipStream_t s, int ev = EV_UPPER_C) {
+    // (outer blocks as given: 512-row blocks measured slower here than 256)
     const bool etr = ev_tr(ev);
     const int amode = etr ? (ev_cj(ev) ? 1 : 2) : 0;
     const int nb = o.nb, P = o.outer / o.nb;
     const int nblk = (m + nb - 1) / nb;
     const int nob = (nblk + P - 1) / P;
-    const bool fused = o.fuse && o.outer <= block_rows_max() && block_fusable(o.nb);
+    const bool fused = o.fuse && o.outer <= block_rows_for(n, o.nb, o.fuse_width, true) && block_fusable(o.nb);
     for (int ob = 0; ob < nob; ++ob) {
         const int qa = ob * P, qb = (qa + P < nblk ? qa + P : nblk) - 1;
         const int end = ((qb + 1) * nb < m) ? (qb + 1) * nb : m;

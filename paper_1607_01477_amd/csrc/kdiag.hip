@@ -1244,15 +1244,18 @@ __device__ __forceinline__ void pin_step(double (&sr)[C], double (&si)[C], doubl
         asm volatile("" : "+v"(sr[0]), "+v"(si[0]), "+v"(tr[0]), "+v"(ti[0]) : : "memory");
     }
 }
-template <int EV, bool SAFE, bool MIXED, bool VARLEN, int C>
+template <int EV, bool SAFE, bool MIXED, bool VARLEN, int C, int R>
 __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     static_assert(EV == EV_UPPER_N || (!SAFE && !MIXED && !VARLEN), "variants: plain FP64 solves");
+    static_assert(R == kRowsMax || (R == 2 * kRowsMax && C <= 2 && !SAFE && !MIXED && !VARLEN),
+                  "512-row outer blocks: plain FP64, at most 2 shifts");
+    constexpr int SP = R + 1;   // padded LDS column stride
     constexpr bool ADJ = ev_fwd(EV);          // forward substitution (E lower triangular)
     constexpr bool TR = ev_tr(EV), CJ = ev_cj(EV), LOWA = ev_lower_a(EV);
     using BS = BlockSolve<16, 1, EV, SAFE>;
     constexpr int NB = 16, NBB = NB * NB;
     constexpr int PERS = 2 * NBB / kWGN;
-    __shared__ zd Bl[C * kSP];
+    __shared__ zd Bl[C * SP];
     __shared__ zd Us[2][NBB];
     __shared__ zd Uo[2][NBB];
     __shared__ zd Ud[2][NB];
@@ -1260,9 +1263,9 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     __shared__ int kcl[C], dkl[2][C], Ll[C];
     // pivots of every row of the outer block and shift (formed in the prologue,
     // off the substitution chain): reciprocal, exponent (safe), cabs1 (safe)
-    __shared__ double Ppr[C][kRowsMax], Ppi[C][kRowsMax];
-    __shared__ int Ppe[SAFE ? C : 1][SAFE ? kRowsMax : 1];
-    __shared__ double Pcd[SAFE ? C : 1][SAFE ? kRowsMax : 1];
+    __shared__ double Ppr[C][R], Ppi[C][R];
+    __shared__ int Ppe[SAFE ? C : 1][SAFE ? R : 1];
+    __shared__ double Pcd[SAFE ? C : 1][SAFE ? R : 1];
 
     if (MIXED && a.skip && *a.skip) return;   // refinement stopped
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1310,11 +1313,11 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     // pivots: A(r, r) - lambda_j (conjugated for CJ) for every row of the
     // outer block and shift (1 + 0i outside the block or past the shifts)
     {
-        constexpr int PER = C * kRowsMax / kWGN;
+        constexpr int PER = C * R / kWGN;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * kWGN;
-            const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
+            const int c = idx / R, rr = idx - c * R;
             double dr = 1.0, di = 0.0;
             if (rr < rows && col0 + c < a.n) {
                 zd u = a.U[(long)(iS + rr) * a.ldu + iS + rr];
@@ -1334,12 +1337,12 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     }
     // right-hand sides of the outer block -> LDS (rows outside the column: 0)
     {
-        constexpr int PER = C * kRowsMax / kWGN;
+        constexpr int PER = C * R / kWGN;
         zd st[PER];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * kWGN;
-            const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
+            const int c = idx / R, rr = idx - c * R;
             const int j = col0 + c;
             int L = 0;
             if (j < a.n) {
@@ -1362,8 +1365,8 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * kWGN;
-            const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
-            Bl[c * kSP + rr] = st[e];
+            const int c = idx / R, rr = idx - c * R;
+            Bl[c * SP + rr] = st[e];
         }
     }
 
@@ -1478,23 +1481,23 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
     // LDS round trip on every step) nor hoists all of them to the top (every
     // x live at once). Rows p0 + k for
     // k >= bsp lie past the outer block, where Bl holds zeros (p0 + 15 <=
-    // 255; only the last block can be partial, and it is never block p of
+    // R - 1; only the last block can be partial, and it is never block p of
     // forward substitution), so no step needs a mask. Each component keeps two accumulators
     // (the terms with Re u and with Im u), so a step's 16 FMAs are
     // independent. In the safe form the rows first take the exponent change
     // of block p.
     auto uapply = [&](const zd (&u)[NB], const Pass& g, int chunk, int buf) __attribute__((always_inline)) {
-        const int row = g.ubeg + chunk * 64 + lane;   // < 256 where stored (row < uend)
+        const int row = g.ubeg + chunk * 64 + lane;   // < R where stored (row < uend)
         const bool ok = row < g.uend;
         const zd* xb = Bl + g.p0;
         double sr[C], si[C], tr[C], ti[C];
         zd x0[C], x1[C], x2[C], x3[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            zd v = Bl[c * kSP + min(row, kRowsMax - 1)];
-            x0[c] = xb[c * kSP];
-            x1[c] = xb[c * kSP + 1];
-            x2[c] = xb[c * kSP + 2];
+            zd v = Bl[c * SP + min(row, R - 1)];
+            x0[c] = xb[c * SP];
+            x1[c] = xb[c * SP + 1];
+            x2[c] = xb[c * SP + 2];
             if (SAFE) {
                 const int dk = dkl[buf ^ 1][c];
                 v.re = ldexp(v.re, -dk);
@@ -1509,7 +1512,7 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
         for (int k = 0; k < NB; ++k) {
             if (k + 3 < NB) {
 #pragma unroll
-                for (int c = 0; c < C; ++c) x3[c] = xb[c * kSP + k + 3];
+                for (int c = 0; c < C; ++c) x3[c] = xb[c * SP + k + 3];
             }
 #pragma unroll
             for (int c = 0; c < C; ++c) {
@@ -1528,7 +1531,7 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
         }
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            if (ok) Bl[c * kSP + row] = zd{sr[c] + tr[c], si[c] + ti[c]};
+            if (ok) Bl[c * SP + row] = zd{sr[c] + tr[c], si[c] + ti[c]};
     };
 
     // The solving and the updating wavefronts run separate pass loops (the
@@ -1554,7 +1557,7 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
             BS S;
             const bool act = jv[0] && (i0 < Ll[c]);
             zd b{0.0, 0.0};
-            if (r < g.bs) b = Bl[c * kSP + g.lr0 + r];
+            if (r < g.bs) b = Bl[c * SP + g.lr0 + r];
             if (SAFE && g.bsp > 0) {
                 const int dk = dkl[buf ^ 1][c];
                 b.re = ldexp(b.re, -dk);
@@ -1598,14 +1601,14 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
                     a.safe.kb[(long)q * a.n + col0 + c] = kc;
                 }
             }
-            if (own && r < g.bs) Bl[c * kSP + g.lr0 + r] = zd{S.br[0], S.bi[0]};
+            if (own && r < g.bs) Bl[c * SP + g.lr0 + r] = zd{S.br[0], S.bi[0]};
             xpr[0] = S.br[0];
             xpi[0] = S.bi[0];
             if (stp + 1 < nsub) stage_store(buf ^ 1);
             __syncthreads();
         }
     } else {
-        // ---- rows beyond the block being solved: chunks wv - 1 and wv + 2
+        // ---- rows beyond the block being solved: chunks wv - 1, wv + 2, wv + 5, ...
         zd un[NB];   // first chunk of a pass, loaded during the pass before
         if (nsub > 1) uload(un, pass_of(1), wv - 1);
         for (int stp = 0; stp < nsub; ++stp) {
@@ -1619,14 +1622,13 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
             }
             if (stp + 1 < nsub) stage_load(stp + 1);
             if (g.bsp > 0) {
-                // (a second chunk exists for wavefront 1 in the first passes
-                // of a full outer block only; its loads reuse the registers)
+                // (further chunks exist in the first passes of a full outer
+                // block only; their loads reuse the registers)
                 const int nch = (g.uend - g.ubeg + 63) / 64;
-                const int c1 = wv - 1, c2 = wv + 2;
-                if (c1 < nch) uapply(un, g, c1, buf);
-                if (c2 < nch) {
-                    uload(un, g, c2);
-                    uapply(un, g, c2, buf);
+                if (wv - 1 < nch) uapply(un, g, wv - 1, buf);
+                for (int ch = wv + 2; ch < nch; ch += 3) {
+                    uload(un, g, ch);
+                    uapply(un, g, ch, buf);
                 }
             }
             if (stp + 1 < nsub) stage_store(buf ^ 1);
@@ -1645,14 +1647,14 @@ __global__ __launch_bounds__(kWGN) void k_block_narrow(BlockArgs a) {
         a.safe.kcur[col0 + tid] = kcl[tid];
     }
     {
-        constexpr int PER = C * kRowsMax / kWGN;
+        constexpr int PER = C * R / kWGN;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * kWGN;
-            const int c = idx / kRowsMax, rr = idx - c * kRowsMax;
+            const int c = idx / R, rr = idx - c * R;
             const int j = col0 + c;
             if (j < a.n && rr < rows && iS + rr < Ll[c]) {
-                const zd v = Bl[c * kSP + rr];
+                const zd v = Bl[c * SP + rr];
                 a.B[(long)j * a.ldb + iS + rr] = v;
                 if (MIXED) a.b32[(long)j * a.ldb32 + iS + rr] = zf{(float)v.re, (float)v.im};
             }
@@ -1677,16 +1679,27 @@ int auto_width(const BlockArgs& a) {
 }
 
 template <int EV, int C>
-void launch_narrow(const BlockArgs& a, bool safe, bool mixed, bool varlen, hipStream_t s) {
+hipError_t launch_narrow(const BlockArgs& a, bool safe, bool mixed, bool varlen, hipStream_t s) {
     const dim3 gn((a.n + C - 1) / C), bn(kWGN);
-    if constexpr (EV == EV_UPPER_N) {
-        if (safe && varlen) hipLaunchKernelGGL((k_block_narrow<EV, true, false, true, C>), gn, bn, 0, s, a);
-        else if (safe) hipLaunchKernelGGL((k_block_narrow<EV, true, false, false, C>), gn, bn, 0, s, a);
-        else if (mixed) hipLaunchKernelGGL((k_block_narrow<EV, false, true, false, C>), gn, bn, 0, s, a);
-        else hipLaunchKernelGGL((k_block_narrow<EV, false, false, false, C>), gn, bn, 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_block_narrow<EV, false, false, false, C>), gn, bn, 0, s, a);
+    if (a.rows > kRowsMax) {
+        // 512-row outer blocks: plain FP64 with at most 2 shifts per workgroup
+        if constexpr (C <= 2) {
+            if (safe || mixed || varlen) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_block_narrow<EV, false, false, false, C, 2 * kRowsMax>), gn, bn, 0, s, a);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
     }
+    if constexpr (EV == EV_UPPER_N) {
+        if (safe && varlen) hipLaunchKernelGGL((k_block_narrow<EV, true, false, true, C, kRowsMax>), gn, bn, 0, s, a);
+        else if (safe) hipLaunchKernelGGL((k_block_narrow<EV, true, false, false, C, kRowsMax>), gn, bn, 0, s, a);
+        else if (mixed) hipLaunchKernelGGL((k_block_narrow<EV, false, true, false, C, kRowsMax>), gn, bn, 0, s, a);
+        else hipLaunchKernelGGL((k_block_narrow<EV, false, false, false, C, kRowsMax>), gn, bn, 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_block_narrow<EV, false, false, false, C, kRowsMax>), gn, bn, 0, s, a);
+    }
+    return hipGetLastError();
 }
 
 template <int NB, int SPW, int EV>
@@ -1742,11 +1755,11 @@ hipError_t launch_blk(const BlockArgs& a, hipStream_t s) {
                                (EV == EV_UPPER_N || (!safe && !mixed && !varlen));
         const int width = !supported ? 16 : a.width ? a.width : auto_width(a);
         if (width == 4 || width == 2 || width == 1) {
-            if (width == 4) launch_narrow<EV, 4>(a, safe, mixed, varlen, s);
-            else if (width == 2) launch_narrow<EV, 2>(a, safe, mixed, varlen, s);
-            else launch_narrow<EV, 1>(a, safe, mixed, varlen, s);
-            return hipGetLastError();
+            if (width == 4) return launch_narrow<EV, 4>(a, safe, mixed, varlen, s);
+            if (width == 2) return launch_narrow<EV, 2>(a, safe, mixed, varlen, s);
+            return launch_narrow<EV, 1>(a, safe, mixed, varlen, s);
         }
+        if (a.rows > kRowsMax) return hipErrorInvalidValue;
     }
     if (a.V != nullptr) {
         if constexpr (NB == 16 && EV == EV_UPPER_N) {
@@ -1824,10 +1837,19 @@ hipError_t launch_diag(int nb, int ev, const DiagArgs& a, hipStream_t s) {
 
 int block_rows_max() { return kRowsMax; }
 
+int block_rows_for(int n, int nb, int width, bool plain) {
+    if (nb != 16 || !plain) return kRowsMax;
+    BlockArgs a{};
+    a.n = n;
+    const int w = width ? width : auto_width(a);
+    return (w == 1 || w == 2) ? 2 * kRowsMax : kRowsMax;
+}
+
 bool block_fusable(int nb) { return nb == 16 || nb == 32; }
 
 hipError_t launch_block(int ev, const BlockArgs& a, hipStream_t s) {
-    if (a.rows <= 0 || a.rows > kRowsMax || a.n <= 0 || a.iS % a.nb) return hipErrorInvalidValue;
+    if (a.rows <= 0 || a.rows > 2 * kRowsMax || a.n <= 0 || a.iS % a.nb) return hipErrorInvalidValue;
+    if (a.rows > kRowsMax && (a.nb != 16 || a.V != nullptr)) return hipErrorInvalidValue;
     switch (a.nb) {
         case 32: return launch_blk_ev<32>(ev, a, s);
         case 16: return launch_blk_ev<16>(ev, a, s);

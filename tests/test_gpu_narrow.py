@@ -43,7 +43,8 @@ def _kappa(U, lam, cols):
 
 
 @pytest.mark.parametrize("m,n,outer", [(1, 1, 256), (17, 5, 256), (256, 4, 256), (530, 70, 256),
-                                       (1000, 37, 128), (700, 9, 64)])
+                                       (1000, 37, 128), (700, 9, 64), (300, 11, 512), (530, 70, 512),
+                                       (1100, 23, 512)])
 @pytest.mark.parametrize("width", [4, 2, 1])
 def test_narrow_plain(P, oracle_mod, m, n, outer, width):
     announce("narrow w%d " % width + "plain m=%d n=%d outer=%d" % (m, n, outer))
@@ -62,21 +63,34 @@ def test_narrow_plain(P, oracle_mod, m, n, outer, width):
 
 
 def test_narrow_automatic_choice(P):
-    """Few shifts: the automatic width is a narrow one (same bits as forced 1,
-    2 and 4, unlike 16), in the back and the forward substitution; 4096 shifts
-    fill the device with 16-shift workgroups (same bits as forced 16)."""
+    """Few shifts: the automatic width is a narrow one (same bits as forced 2,
+    unlike 16), in the back and the forward substitution, with 512-row outer
+    blocks in plain back substitutions; 4096 shifts fill the device with
+    16-shift workgroups (same bits as forced 16)."""
     w = W.c1_plain(seed=410, m=300, n=40)
     args = (dev(w.U), dev(w.shifts))
     Xa = host(P.mstrsm(*args, dev(w.B), nb=16))
-    X4 = host(P.mstrsm(*args, dev(w.B), nb=16, fuse_width=4))
+    X2 = host(P.mstrsm(*args, dev(w.B), nb=16, fuse_width=2))
     X16 = host(P.mstrsm(*args, dev(w.B), nb=16, fuse_width=16))
-    assert np.array_equal(_bits(Xa), _bits(X4))
+    assert np.array_equal(_bits(Xa), _bits(X2))
     assert not np.array_equal(_bits(Xa), _bits(X16))
     Ya = host(P.mstrsm_adjoint(*args, dev(w.B), nb=16))
     Y2 = host(P.mstrsm_adjoint(*args, dev(w.B), nb=16, fuse_width=2))
     Y16 = host(P.mstrsm_adjoint(*args, dev(w.B), nb=16, fuse_width=16))
     assert np.array_equal(_bits(Ya), _bits(Y2))
     assert not np.array_equal(_bits(Ya), _bits(Y16))
+    # few shifts, plain FP64, outer block left to the library: 512 rows (the
+    # same bits as forced 512; 256-row blocks group the products otherwise)
+    w = W.c1_plain(seed=412, m=1100, n=23)
+    args = (dev(w.U), dev(w.shifts))
+    Xa = host(P.mstrsm(*args, dev(w.B), nb=16))
+    X512 = host(P.mstrsm(*args, dev(w.B), nb=16, outer_nb=512, fuse_width=2))
+    X256 = host(P.mstrsm(*args, dev(w.B), nb=16, outer_nb=256, fuse_width=2))
+    assert np.array_equal(_bits(Xa), _bits(X512))
+    assert not np.array_equal(_bits(Xa), _bits(X256))
+    Ya = host(P.mstrsm_adjoint(*args, dev(w.B), nb=16))
+    Y256 = host(P.mstrsm_adjoint(*args, dev(w.B), nb=16, outer_nb=256, fuse_width=1))
+    assert np.array_equal(_bits(Ya), _bits(Y256))   # forward substitution keeps 256
     w = W.c1_plain(seed=411, m=300, n=4096)
     args = (dev(w.U), dev(w.shifts))
     Xa = host(P.mstrsm(*args, dev(w.B), nb=16))
@@ -225,12 +239,19 @@ def test_narrow_adjoint(P, oracle_mod, width):
 def test_narrow_widths_same_bits(P):
     """4-, 2- and 1-shift workgroups take the same steps for each shift: the
     same bits in the plain solve, the safe solve with rescaling (and the same
-    exponents) and the adjoint."""
+    exponents) and the adjoint at one outer block size (256 rows; 512 for the
+    widths that take it)."""
     widths = (4, 2, 1)
-    w = W.c1_plain(seed=470, m=530, n=23)
+    w = W.c1_plain(seed=470, m=1100, n=23)
     announce("narrow widths same bits")
-    X = [host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=c)) for c in widths]
-    Y = [host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, fuse_width=c)) for c in widths]
+    X = [host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=256, fuse_width=c)) for c in widths]
+    Y = [host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=256, fuse_width=c))
+         for c in widths]
+    X5 = [host(P.mstrsm(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=512, fuse_width=c)) for c in (2, 1)]
+    Y5 = [host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=512, fuse_width=c))
+          for c in (2, 1)]
+    assert np.array_equal(_bits(X5[0]), _bits(X5[1]))
+    assert np.array_equal(_bits(Y5[0]), _bits(Y5[1]))
     g = W.rng(471)
     m, n = 450, 19
     U = W.random_upper(g, m, 1.0, W.cnormal(g, m))
