@@ -41,15 +41,15 @@ PEAK_FP64_MFMA_TF = 78.6
 # Valid only for the sources it was measured on: the GEMM kernel and the block
 # loops that choose its launch shapes (sha1 prefix of csrc/kgemm.hip followed by
 # csrc/api.hip).
-GEMM_TRAFFIC = {"sources_sha1": "78588dcf788ab853", "bytes_per_launch": 278.4e6, "m": 4096, "n": 4096,
-                "nb": 16, "outer_nb": 256,
+GEMM_TRAFFIC = {"sources_sha1": "e777515967a6c0b0", "bytes_per_launch": 278.4e6, "m": 4096, "n": 4096,
+                "nb": 16, "outer_nb": 0,
                 # the pencil substitution (profiles/k_gemm_direct_pencil_m4096_n4096.md)
-                "pencil_bytes_per_launch": 456.2e6}
+                "pencil_bytes_per_launch": 456.1e6}
 # The same for the real substitution GEMM (all its tile variants, averaged over
 # the 15 launches of a solve; profiles/real_solve_m4096_n4096.md), valid for the
 # sources it was measured on (sha1 prefix of csrc/kreal.hip followed by csrc/api.hip).
-REAL_GEMM_TRAFFIC = {"sources_sha1": "fa78cd6245f54b38", "bytes_per_launch": 112.8e6, "m": 4096, "n": 4096,
-                     "outer_nb": 256}
+REAL_GEMM_TRAFFIC = {"sources_sha1": "cf78bf470363a34f", "bytes_per_launch": 112.6e6, "m": 4096, "n": 4096,
+                     "outer_nb": 0}
 PEAK_FP32_MFMA_TF = 157.3
 METRIC = "complex128 multi-shift solve GFLOP/s at m=n=4096 and % of MFMA peak vs plain FP64"
 METRIC_PENCIL = "complex128 generalized multi-shift solve GFLOP/s (8 m^2 n) at m=n=4096"
@@ -259,7 +259,7 @@ def main() -> int:
     ap.add_argument("--m", type=int, default=4096)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--nb", type=int, default=16)
-    ap.add_argument("--outer-nb", type=int, default=256)
+    ap.add_argument("--outer-nb", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

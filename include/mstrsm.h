@@ -48,7 +48,8 @@ typedef struct {
     int nb;            /* diagonal-block (and scaling-decision) size: 16, 32 or 64; default 16 */
     int outer_nb;      /* rows per deferred substitution step, a multiple of nb; 0 (default):
                           256, or 512 in plain FP64 back substitutions whose fused blocks
-                          run 1 or 2 shifts per workgroup (few shifts; see fuse_blocks).
+                          run 1 or 2 shifts per workgroup with at most one workgroup per
+                          compute unit (few shifts; see fuse_blocks).
                           Equal to nb gives the paper's right-looking order (Alg 3 / Alg 5). */
     int precision;     /* 0: all FP64.
                           1: substitution GEMMs in FP32 on MFMA (FP32 accumulation),

@@ -90,8 +90,8 @@ struct BlockArgs {
 int block_rows_max();
 // Rows an outer block may have in the fused kernel for n shifts at the given
 // width (0 = automatic): twice block_rows_max() where the narrow kernel runs
-// at most 2 shifts per workgroup in a plain FP64 solve (nb = 16), else
-// block_rows_max().
+// at most 2 shifts per workgroup, one workgroup per compute unit, in a plain
+// FP64 solve (nb = 16), else block_rows_max().
 int block_rows_for(int n, int nb, int width, bool plain);
 bool block_fusable(int nb);   // nb handled by the fused kernel (16 or 32)
 hipError_t launch_block(int ev, const BlockArgs& a, hipStream_t s);

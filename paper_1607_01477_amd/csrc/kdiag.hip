@@ -1842,7 +1842,9 @@ int block_rows_for(int n, int nb, int width, bool plain) {
     BlockArgs a{};
     a.n = n;
     const int w = width ? width : auto_width(a);
-    return (w == 1 || w == 2) ? 2 * kRowsMax : kRowsMax;
+    // 512-row blocks where every narrow workgroup has a compute unit to itself
+    // (measured: at two per compute unit they gain nothing, or lose at m = 1024)
+    return ((w == 1 || w == 2) && (n + w - 1) / w <= device_cu_count()) ? 2 * kRowsMax : kRowsMax;
 }
 
 bool block_fusable(int nb) { return nb == 16 || nb == 32; }
