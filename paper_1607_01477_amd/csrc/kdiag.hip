@@ -1205,21 +1205,23 @@ __global__ __launch_bounds__(block_threads(NB, ev_fwd(EV), SAFE, GEN)) void k_bl
 }
 
 // ---------------------------------------------------------------- narrow fused outer block
-// The outer block of k_block for 4 shifts per workgroup of 4 wavefronts, for
-// launches whose 16-shift workgroups would leave compute units idle (few
-// shifts, or few columns reaching an outer block in the triangular-eigenvector
-// solve), for every solve variant EV (safe, variable-length and mixed forms:
-// upper, op N). Wavefront 0 solves the diagonal blocks exactly as a solving
-// wavefront of k_block (one shift per lane group). Wavefronts 1-3 apply each
-// solved block to the rows still to be solved (above it for back
-// substitution, below it for forward) with FP64 FMAs, one row per lane and all
-// four shifts: at four shifts a 16-column matrix-core tile would be three
-// quarters padding, and the substitution chain then shares its SIMD's FP64
-// pipeline with no matrix-core products (the four wavefronts of a workgroup
-// run on four different SIMDs). Rows of the update go in 64-row chunks:
-// wavefront u takes chunks u - 1 and u + 2, its first chunk's U entries
-// loaded during the pass before. Per element the updates keep the order of
-// the blocks, as in k_block.
+// The outer block of k_block for C = 4, 2 or 1 shifts per workgroup of 4
+// wavefronts, for launches whose 16-shift workgroups would leave compute units
+// idle (few shifts, or few columns reaching an outer block in the
+// triangular-eigenvector solve), for every solve variant EV (safe,
+// variable-length and mixed forms: upper, op N), over outer blocks of up to
+// R = 256 rows (512 for plain solves at C <= 2). Wavefront 0 solves the
+// diagonal blocks exactly as a solving wavefront of k_block (one shift per
+// lane group). Wavefronts 1-3 apply each solved block to the rows still to be
+// solved (above it for back substitution, below it for forward) with FP64
+// FMAs, one row per lane and all C shifts: at four shifts or fewer a
+// 16-column matrix-core tile would be mostly padding, and the substitution
+// chain then shares its SIMD's FP64 pipeline with no matrix-core products
+// (the four wavefronts of a workgroup run on four different SIMDs). Rows of
+// the update go in 64-row chunks: wavefront u takes chunks u - 1, u + 2,
+// u + 5, ..., its first chunk's U entries loaded during the pass before. Per
+// element the updates keep the order of the blocks, as in k_block, and a
+// shift's arithmetic does not depend on C.
 constexpr int kWGN = 256;     // threads per narrow workgroup
 
 // accumulators of a step of the narrow update, pinned after the step (see
