@@ -478,7 +478,15 @@ __global__ __launch_bounds__(NT) void k_gemm_direct(GemmArgs g) {
     // wait before each k-step covers only that step's loads, not the ones in
     // flight for later steps. Elements outside the product are zeroed where
     // they are consumed (the clamped load may return anything, even NaN).
-    const int nks = (g.K + 3) / 4;
+    int nks = (g.K + 3) / 4;
+    if (VARLEN) {
+        // no k-step past the longest of the wavefront's columns: beyond it
+        // every B element is masked to zero (triangular right-hand sides
+        // such as the eigenvector solve's skip about half the products)
+        int bm = max(blim0, blim1);
+        for (int off = 32; off >= 1; off >>= 1) bm = max(bm, __shfl_xor(bm, off, 64));
+        nks = min(nks, (max(bm, 0) + 3) / 4);
+    }
     const int kfirst0 = RES ? (rw >> 2) : 0;   // U(row, k) = 0 for k < row
     const int nloc0 = nks - kfirst0;
     const int ra0 = min(rw + lr, g.M - 1), ra1 = min(rw + 16 + lr, g.M - 1);
