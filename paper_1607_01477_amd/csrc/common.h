@@ -69,8 +69,8 @@ struct DiagArgs {
 };
 hipError_t launch_diag(int nb, int ev, const DiagArgs& a, hipStream_t s);
 
-// Whole outer block [iS, iS+rows) (rows <= block_rows_max(), or twice that for
-// the narrow kernel of a plain solve: block_rows_for; iS a multiple of nb,
+// Whole outer block [iS, iS+rows) (rows <= block_rows_for(...): 256, or 512 for
+// the narrow kernel of a plain solve; iS a multiple of nb,
 // first diagonal block index qa) for all n shifts: the diagonal blocks in
 // order and the substitution between them, in one launch. V != nullptr: the
 // pencil U - lambda_j V (nb = 16, forward, FP64 only).
@@ -87,11 +87,10 @@ struct BlockArgs {
     const int* skip;   // mixed precision: nothing is done when *skip != 0 (nullable)
     int width;         // shifts per workgroup: 16, 4, 2 or 1 (where available); 0 = chosen from n
 };
-int block_rows_max();
 // Rows an outer block may have in the fused kernel for n shifts at the given
-// width (0 = automatic): twice block_rows_max() where the narrow kernel runs
-// at most 2 shifts per workgroup, one workgroup per compute unit, in a plain
-// FP64 solve (nb = 16), else block_rows_max().
+// width (0 = automatic): 512 where the narrow kernel runs at most 2 shifts per
+// workgroup, one workgroup per compute unit, in a plain FP64 solve (nb = 16),
+// else 256.
 int block_rows_for(int n, int nb, int width, bool plain);
 bool block_fusable(int nb);   // nb handled by the fused kernel (16 or 32)
 hipError_t launch_block(int ev, const BlockArgs& a, hipStream_t s);

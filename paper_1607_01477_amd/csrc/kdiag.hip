@@ -1837,8 +1837,6 @@ hipError_t launch_diag(int nb, int ev, const DiagArgs& a, hipStream_t s) {
     }
 }
 
-int block_rows_max() { return kRowsMax; }
-
 int block_rows_for(int n, int nb, int width, bool plain) {
     if (nb != 16 || !plain) return kRowsMax;
     BlockArgs a{};
