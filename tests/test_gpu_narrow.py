@@ -264,3 +264,28 @@ def test_narrow_widths_same_bits(P):
         assert np.array_equal(_bits(Y[0]), _bits(Y[i]))
         assert np.array_equal(_bits(host(R[0][0])), _bits(host(R[i][0])))
         assert np.array_equal(host(R[0][2]), host(R[i][2]))
+
+
+@pytest.mark.parametrize("width", [2, 1])
+def test_narrow_512_rows_forward_and_safe(P, oracle_mod, width):
+    """512-row outer blocks forced in the forward substitution (adjoint; the
+    library keeps 256 there unless asked) against the oracle, and a forced
+    outer_nb = 512 in the safe solve, which the fused kernels do not take
+    (per-block path), with exponents equal to the oracle's."""
+    m, n = 1100, 23
+    w = W.c1_plain(seed=480 + width, m=m, n=n)
+    announce("narrow w%d 512-row adjoint and safe" % width)
+    Y = host(P.mstrsm_adjoint(dev(w.U), dev(w.shifts), dev(w.B), nb=16, outer_nb=512, fuse_width=width))
+    Yo = oracle_mod.solve_adjoint(w.U, w.shifts, w.B)
+    cols = np.arange(0, n, 4)
+    kap = _kappa(w.U, w.shifts, cols)
+    assert np.all(colerr(Y[:, cols], Yo[:, cols]) <= 64 * EPS * kap)
+    g = W.rng(490)
+    U = W.random_upper(g, 600, 1.0, W.cnormal(g, 600))
+    lam = W.cnormal(g, 17)
+    B = np.asfortranarray(W.cnormal(g, (600, 17)))
+    X, s, k = P.mstrsm_safe(dev(U), dev(lam), dev(B), nb=16, outer_nb=512, omega_log2=40, fuse_width=width)
+    Xo, so, ko = oracle_mod.solve_safe(U, lam, B, nb=16, omega_log2=40)
+    assert np.array_equal(host(k), ko) and np.array_equal(host(s), so)
+    rr = oracle_mod.relative_residual(U, lam, host(X), B, k=host(k))
+    assert rr.max() <= 1e-13, rr.max()
