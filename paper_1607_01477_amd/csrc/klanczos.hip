@@ -78,6 +78,30 @@ __global__ __launch_bounds__(kT) void k_trl_orth(int m, int i, int k0, int kdim,
     double* Hj = H + (long)j * kdim * kdim;
     const int t = threadIdx.x;
 
+    // v -= sum_l coef_l q_l over l = 0..i, in that order; the basis entries
+    // are loaded four at a time so that each thread keeps several loads in
+    // flight (one at a time leaves the stream short of HBM bandwidth)
+    auto sub_basis = [&](zd& v, int r) __attribute__((always_inline)) {
+        int l = 0;
+        for (; l + 4 <= i + 1; l += 4) {
+            zd q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = qj[(l + u) * qs + r];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double hr = coef[2 * (l + u)], hi = coef[2 * (l + u) + 1];
+                v.re -= hr * q[u].re - hi * q[u].im;
+                v.im -= hr * q[u].im + hi * q[u].re;
+            }
+        }
+        for (; l <= i; ++l) {
+            const zd q = qj[l * qs + r];
+            const double hr = coef[2 * l], hi = coef[2 * l + 1];
+            v.re -= hr * q.re - hi * q.im;
+            v.im -= hr * q.im + hi * q.re;
+        }
+    };
+
     // pass 1
     const bool border = (i == k0) && (k0 > 0);
     const int l0 = border ? 0 : i - 1, l1 = border ? k0 : i;   // vectors removed: [l0, l1)
@@ -113,12 +137,7 @@ __global__ __launch_bounds__(kT) void k_trl_orth(int m, int i, int k0, int kdim,
                         v.re -= alpha * q.re;
                         v.im -= alpha * q.im;
                     } else {
-                        for (int l = 0; l <= i; ++l) {
-                            const zd q = qj[l * qs + r];
-                            const double hr = coef[2 * l], hi = coef[2 * l + 1];
-                            v.re -= hr * q.re - hi * q.im;
-                            v.im -= hr * q.im + hi * q.re;
-                        }
+                        sub_basis(v, r);
                     }
                     w[r] = v;
                 }
@@ -145,12 +164,7 @@ __global__ __launch_bounds__(kT) void k_trl_orth(int m, int i, int k0, int kdim,
     double b2[1] = {0.0};
     for (int r = t; r < m; r += kT) {
         zd v = w[r];
-        for (int l = 0; l <= i; ++l) {
-            const zd q = qj[l * qs + r];
-            const double hr = coef[2 * l], hi = coef[2 * l + 1];
-            v.re -= hr * q.re - hi * q.im;
-            v.im -= hr * q.im + hi * q.re;
-        }
+        sub_basis(v, r);
         w[r] = v;
         b2[0] += v.re * v.re + v.im * v.im;
     }
