@@ -217,6 +217,7 @@ __global__ __launch_bounds__(64) void k_trl_ritz(int kdim, int keep, double tol,
     const int np = (kdim + 1) & ~1;   // players of the tournament (a dummy when kdim is odd)
     const int npair = np / 2;
     __syncthreads();
+    double prev = -1.0;   // off-diagonal mass before the last sweep
     for (int sweep = 0; sweep < 60; ++sweep) {
         // off-diagonal and diagonal mass (fixed-order wavefront sums)
         double off = 0.0, dia = 0.0;
@@ -228,7 +229,11 @@ __global__ __launch_bounds__(64) void k_trl_ritz(int kdim, int keep, double tol,
             off += __shfl_xor(off, o, 64);
             dia += __shfl_xor(dia, o, 64);
         }
-        if (!(off > 1e-32 * dia)) break;
+        // converged; or the off-diagonal mass has reached the rounding floor
+        // (about (kdim eps)^2 of the diagonal's) and stopped falling, where
+        // further sweeps only move rounding errors around
+        if (!(off > 1e-32 * dia) || (off <= 1e-24 * dia && prev >= 0.0 && off >= 0.5 * prev)) break;
+        prev = off;
         for (int step = 0; step < np - 1; ++step) {
             // pairs of this step: player 0 against rotating player step + 1, and
             // the others folded around the circle of players 1 .. np - 1
