@@ -40,10 +40,8 @@ PEAK_FP64_MFMA_TF = 78.6
 # FETCH_SIZE / WRITE_SIZE runs scaled by a 512 MiB copy (profiles/k_gemm_direct_solve_m4096_n4096.md).
 # Valid only for the sources it was measured on: the GEMM kernel and the block
 # loops that choose its launch shapes (sha1 prefix of csrc/kgemm.hip followed by
-# csrc/api.hip; moved to a later kgemm.hip whose change, the k-range of
-# variable-length columns, leaves the gfx950 code of the kernels these
-# workloads launch identical).
-GEMM_TRAFFIC = {"sources_sha1": "1010a805c6675784", "bytes_per_launch": 278.4e6, "m": 4096, "n": 4096,
+# csrc/api.hip).
+GEMM_TRAFFIC = {"sources_sha1": "1010a805c6675784", "bytes_per_launch": 278.3e6, "m": 4096, "n": 4096,
                 "nb": 16, "outer_nb": 0,
                 # the pencil substitution (profiles/k_gemm_direct_pencil_m4096_n4096.md)
                 "pencil_bytes_per_launch": 456.1e6}
